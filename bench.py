@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the Richards-equation hot path on one MI355X.
+
+One step = one backward-Euler time step with its whole Picard loop (soil
+coefficients, assembly, PCG solve, Picard exit test, step acceptance) on the
+3-D hillslope workload (128 x 128 x 64 cells, lognormal Ks, rain on top),
+inputs resident in HBM.  Prints ONE JSON line with the throughput in
+cell-steps/s, the roofline of the dominant kernel (HIP events on the library
+stream, inside the timed region) and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 144] [--warmup 3] [--workload hillslope]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_TFLOPS = 78.6
+
+# Algorithmic bytes per active cell and launch (FP64 arrays, one pass each;
+# neighbour values are reuse, not extra traffic).  Kernel -> (jacobi, zline).
+ALGO_BYTES = {
+    "spmv": (56, 48),      # read r, diag (z), p_old, K, Dd; write p, q
+    "update": (56, 80),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z)
+    "coeff": (56, 56),     # read h^m, h^n, theta^n, Ks; write K, Dd, bst
+    "resid": (56, 80),     # read K, h^m, Dd, bst; write r, e, diag (+ tz, rdp, z)
+    "apply_h": (24, 24),   # read e, h^m; write h^m
+    "accept": (24, 24),    # read h^m; write h^n, theta^n
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=144)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="hillslope", choices=["hillslope", "watershed", "column100"])
+    ap.add_argument("--precond", default="zline", choices=["zline", "jacobi"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_1809_10895_amd import workloads as W
+    if name == "hillslope":
+        w = W.hillslope()
+        desc = "hillslope 128x128x64, 1x1x0.1 m cells, lognormal Ks (ln-sigma 1), rain 1e-7 m/s, dt 600 s"
+    elif name == "watershed":
+        w = W.watershed()
+        desc = "watershed 512x512x64 (fractal surface mask), 2x2x0.2 m cells, 3 Eq.-5 layers, dt 600 s"
+        w.dt = 600.0
+    else:
+        w = W.column100()
+        desc = "1-D column 1x1x100, dz 1 cm, top Dirichlet -0.75 m, dt 10 s"
+    return w, desc
+
+
+def cpu_baseline(w, seconds):
+    """The oracle as it stands, single thread, on as many steps of the same
+    workload as fit in `seconds` (at least one)."""
+    import oracle
+    P = oracle.Problem(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, ktop=w.ktop, grad_elev=w.grad_elev)
+    from paper_1809_10895_amd import workloads as W
+    W.configure(w, P)
+    P.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, ebats=0, dt0=w.dt)
+    P.set_state(w.h0)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        s, _ = P.step(w.dt)
+        if s != 0:
+            break
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": w.active_cells * n / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d backward-Euler steps of the same workload from its initial state, "
+                      "DIC-PCG in natural order, one thread (%.1f s)" % (n, el)}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rf_kernels.hip", "rf_internal.h"):
+        with open(os.path.join(ROOT, "paper_1809_10895_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1809_10895_amd import Solver, workloads as W
+
+    w, desc = make_workload(args.workload)
+    pc = 1 if args.precond == "zline" else 0
+    S = Solver(0)
+    S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
+    W.configure(w, S)
+    S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt, ebats=0)
+    S.bind()
+    h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
+    assert S.set_state(h0) == 0, S.last_error()
+
+    picard = cg = 0
+    for _ in range(args.warmup):
+        s, st = S.step(w.dt)
+        assert s == 0, S.last_error()
+    S.set_timing(not args.no_timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s, st = S.step(w.dt)
+        if s != 0:
+            raise SystemExit("step failed: " + S.last_error())
+        picard += st["picard_iters"]
+        cg += st["cg_iters_total"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = S.get_timing()
+    cells = w.active_cells
+    value = cells * args.steps / el
+
+    # dominant kernel by summed event time
+    kern = max((k for k in ALGO_BYTES if k in tm and tm[k]["launches"]),
+               key=lambda k: tm[k]["ms"], default=None)
+    roof = None
+    if kern is not None and tm[kern]["launches"]:
+        avg_s = tm[kern]["ms"] / tm[kern]["launches"] * 1e-3
+        algo = ALGO_BYTES[kern][pc] * cells
+        achieved = algo / avg_s / 1e9
+        traffic = measured_traffic(args.workload, kern)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kern, "avg_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": algo}
+    kernels = {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2)
+                   if v["launches"] else None, "share": None, "idle_launches": v["idle_launches"]}
+               for k, v in tm.items() if isinstance(v, dict)}
+    tot = sum(v["ms"] for k, v in tm.items() if isinstance(v, dict))
+    for k, v in tm.items():
+        if isinstance(v, dict) and tot > 0:
+            kernels[k]["share"] = round(v["ms"] / tot, 3)
+
+    cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    out = {
+        "metric": "cell-steps/s at Picard tol 1e-6", "value": value, "unit": "cell-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "active_cells": cells, "grid": [w.nx, w.ny, w.nz],
+                   "dt_s": w.dt, "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
+                   "precond": args.precond, "picard_per_step": picard / args.steps,
+                   "cg_per_picard": cg / max(picard, 1),
+                   "wall_s_per_simulated_day": el / (args.steps * w.dt) * 86400.0},
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * rf.h -- C ABI of the MI355X (gfx950) Richards-equation hot path.
+ *
+ * The library advances the 3-D transient Richards equation in pressure-head
+ * form, C(h) dh/dt = div(K(h) grad(h + z))  (Orgogozo et al.,
+ * arXiv:1809.10895, Sec. 1, Eq. 1), on a uniform structured grid of
+ * constant-volume hexahedral cells (programme summary, "Restrictions").
+ * Each backward-Euler step (Sec. 2.2) is linearised by classical Picard
+ * iteration with the chord-slope capacity; pressure diffusion is implicit,
+ * gravity explicit from the previous Picard iterate with arithmetic-mean
+ * face conductivity (Sec. 2.2, last paragraph); each linear system is solved
+ * by preconditioned conjugate gradients (Sec. 2.2); the Picard exit test is
+ * global (Sec. 2.3); time steps adapt by EBATS (Sec. 2.2).  Soil properties
+ * follow van Genuchten-Mualem, Eqs. 2-4.
+ *
+ * Conventions shared by every call:
+ *   - Units are SI: metres, seconds, m/s.  z (and grad_elev) point upward.
+ *   - Cell (i,j,k) of an nx*ny*nz grid is element k + nz*(i + nx*j) of every
+ *     per-cell array (z fastest); k = 0 is the bottom layer.  Column (i,j)
+ *     holds active cells k < k_top[i + nx*j]; the others are carried
+ *     unchanged and never read.
+ *   - Host pointers (grid, soil, forcing tables) are copied during the call;
+ *     the caller keeps ownership.
+ *   - Device pointers (workspace, states, outputs) belong to the caller.  The
+ *     library never allocates device memory; all work is enqueued on the
+ *     stream given to rf_create and the calls return when the stream has
+ *     finished that work (rf_step/rf_run synchronise only to read scalars).
+ *   - Every call returns an rf_status; rf_last_error() explains the last
+ *     failure.  No call throws.  A context is not thread-safe.
+ *   - Required order: rf_create -> rf_setup_grid -> rf_set_soil ->
+ *     rf_bind_workspace -> rf_set_state -> rf_step / rf_run.  Boundary
+ *     conditions, forcing and options may be set at any time after the grid.
+ *     Calls out of order return RF_ERR_STATE.
+ */
+#ifndef RF_H
+#define RF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RF_OK = 0,
+    RF_ERR_ARG = -1,           /* invalid argument (NULL, size, range) */
+    RF_ERR_STATE = -2,         /* call made out of the required order */
+    RF_ERR_HIP = -3,           /* a HIP runtime call failed */
+    RF_ERR_NOMEM = -4,         /* workspace smaller than rf_workspace_bytes */
+    RF_ERR_NOT_CONVERGED = -5, /* Picard loop did not meet tol_picard */
+    RF_ERR_LINEAR = -6,        /* PCG broke down or hit max_cg */
+    RF_ERR_NONFINITE = -7      /* NaN/Inf in the state or an iterate */
+} rf_status;
+
+enum { RF_VGM = 0, RF_GARDNER = 1 };                           /* soil model */
+enum { RF_XMIN = 0, RF_XMAX, RF_YMIN, RF_YMAX, RF_ZMIN, RF_ZMAX }; /* faces */
+enum { RF_NOFLOW = 0, RF_DIRICHLET = 1, RF_FLUX = 2, RF_FREE_DRAINAGE = 3 };
+enum { RF_PRECOND_JACOBI = 0, RF_PRECOND_ZLINE = 1 };
+
+#define RF_MAX_LAYERS 16
+#define RF_MAX_PICARD_LOG 128
+
+typedef struct rf_ctx rf_ctx;
+
+typedef struct {
+    double tol_picard;  /* Picard exit: max |h^{m+1} - h^m| over the domain [m] (Sec. 2.3) */
+    double tol_cg;      /* PCG exit: max |r_c / A_cc| [m] */
+    int max_picard;     /* Picard iterations allowed per rf_step */
+    int max_cg;         /* PCG iterations allowed per Picard iteration */
+    double chord_eps;   /* |h^m - h^n| below this uses the analytic C(h^m) of Eq. 3 [m] */
+    int precond;        /* RF_PRECOND_JACOBI or RF_PRECOND_ZLINE */
+    int check_every;    /* PCG iterations enqueued between convergence polls (>= 1) */
+    double dt0;         /* first time step of rf_run [s] (fixed step when ebats = 0) */
+    double dt_max;      /* EBATS upper bound [s] */
+    double dt_min;      /* EBATS gives up below this [s] */
+    int ebats;          /* 1: adaptive steps in rf_run (Sec. 2.2); 0: fixed dt0 */
+    int inc_after;      /* consecutive easy steps before dt *= factor (default 10) */
+    int few_iters;      /* an easy step needs at most this many Picard its (default 3) */
+    int max_iters;      /* under EBATS a step needing more Picard its is rerun (default 8) */
+    double factor;      /* EBATS growth / shrink factor (default 1.3) */
+} rf_options;
+
+typedef struct {
+    int converged;
+    int picard_iters;
+    int cg_iters_total;
+    int cg_iters[RF_MAX_PICARD_LOG];     /* PCG iterations of each Picard iteration */
+    double delta[RF_MAX_PICARD_LOG];     /* max |h^{m+1} - h^m| of each Picard iteration */
+    double dt;
+    double t;                            /* time after the step (before, if rejected) */
+} rf_step_stats;
+
+typedef struct {
+    int accepted, rejected;
+    long picard_total, cg_total;
+    double dt_last;   /* step size EBATS will try next */
+    double t;
+} rf_run_stats;
+
+typedef struct {
+    double storage;      /* sum over active cells of V * theta~(h) now [m^3] */
+    double storage0;     /* same at the last rf_set_state [m^3] */
+    double inflow[6];    /* cumulative boundary inflow per face since rf_set_state [m^3] */
+    double error;        /* storage - storage0 - sum(inflow) [m^3] */
+} rf_mass;
+
+/* Fills *o with the defaults: tol_picard 1e-6, tol_cg 1e-8 (1/100 of the
+ * Picard tolerance, the ratio of Sec. 3.2, 4.2, App. A, App. B), max_picard
+ * 50, max_cg 10000, chord_eps 1e-9, z-line preconditioner, check_every 8,
+ * dt0 1, dt_max 3600, dt_min 1e-6, EBATS on with 10 / 3 / 8 / 1.3 (Sec. 2.2). */
+void rf_default_options(rf_options *o);
+
+/* Creates a context on HIP device `hip_device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *ctx receives the handle. */
+rf_status rf_create(rf_ctx **ctx, int hip_device, void *hip_stream);
+void rf_destroy(rf_ctx *ctx);
+/* Message for the last non-OK status (static storage inside the context). */
+const char *rf_last_error(const rf_ctx *ctx);
+
+/* Grid (programme summary "Nature of problem", "Restrictions"): nx*ny*nz
+ * cells of dx*dy*dz metres.  k_top (host, nx*ny int32, values clipped to
+ * [0, nz]) masks cells above a surface; NULL = all active.  grad_elev (host,
+ * 3 doubles) is grad z in grid axes, NULL = (0,0,1).  Invalidates any bound
+ * workspace. */
+rf_status rf_setup_grid(rf_ctx *ctx, int nx, int ny, int nz, double dx, double dy, double dz,
+                        const int32_t *k_top, const double *grad_elev);
+
+/* Soil (Sec. 1, Eqs. 2-4; Sec. 3.2, Eq. 5 for layered sets).  params (host)
+ * holds nlayer rows {theta_r, theta_s, alpha [1/m], n, Ks [m/s], S [1/m]}.
+ * layer_of_cell (host, N bytes) selects a row per cell, NULL = row 0.
+ * ln_ks_offset (host, N doubles) scales Ks per cell by exp(offset), NULL =
+ * none.  model RF_GARDNER uses K = Ks exp(alpha h), theta = theta_r +
+ * (theta_s - theta_r) exp(alpha h) (Appendix A, Eq. A6). */
+rf_status rf_set_soil(rf_ctx *ctx, int model, int nlayer, const double *params,
+                      const uint8_t *layer_of_cell, const double *ln_ks_offset);
+
+/* Boundary condition of one face of the domain box (Sec. 3.1, 3.2, App. A,
+ * App. B): RF_NOFLOW; RF_DIRICHLET with head `value` [m] (face conductivity
+ * K(value), half-cell distance); RF_FLUX with `value` [m/s] positive into the
+ * domain; RF_FREE_DRAINAGE (zero pressure gradient, gravity outflow).  On a
+ * masked grid RF_ZMAX applies to the top face of each column's highest
+ * active cell; faces towards inactive cells are no-flow. */
+rf_status rf_set_bc(rf_ctx *ctx, int face, int type, double value);
+
+/* Time-varying flux on an RF_FLUX face (Sec. 3.2): nseg piecewise-constant
+ * segments starting at t_start[s] (host, increasing) with flux[s] [m/s].
+ * Before t_start[0] the rf_set_bc value applies.  rf_run never lets a step
+ * straddle a segment start.  nseg = 0 clears the table. */
+rf_status rf_set_forcing(rf_ctx *ctx, int face, int nseg, const double *t_start,
+                         const double *flux);
+
+rf_status rf_set_options(rf_ctx *ctx, const rf_options *opt);
+
+/* Device workspace the caller must provide for the current grid. */
+rf_status rf_workspace_bytes(const rf_ctx *ctx, size_t *bytes);
+/* Binds `bytes` bytes of device memory at dev_ptr (256-byte aligned) as the
+ * workspace; uploads grid and soil tables into it. */
+rf_status rf_bind_workspace(rf_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Sets h^n from h_dev (device, N doubles) at time t; resets the water-balance
+ * accumulators and the EBATS state.  RF_ERR_NONFINITE if an active cell of
+ * h_dev is not finite (the state is then unchanged). */
+rf_status rf_set_state(rf_ctx *ctx, const double *h_dev, double t);
+/* Copies h^n into h_dev (device, N doubles, may be NULL) and the time into
+ * *t (may be NULL). */
+rf_status rf_get_state(const rf_ctx *ctx, double *h_dev, double *t);
+
+/* One backward-Euler step of size dt with the Picard loop (Sec. 2.2, 2.3).
+ * h_guess_dev (device, N doubles) is the first Picard iterate; NULL = h^n.
+ * On RF_ERR_NOT_CONVERGED / RF_ERR_LINEAR / RF_ERR_NONFINITE the state is
+ * left bitwise as before the call.  *out (may be NULL) receives the stats. */
+rf_status rf_step(rf_ctx *ctx, double dt, const double *h_guess_dev, rf_step_stats *out);
+
+/* Advances to t_end with fixed dt0 steps (ebats = 0) or EBATS (Sec. 2.2):
+ * a step that fails or needs more than max_iters Picard iterations is rerun
+ * with dt/factor; after inc_after consecutive accepted steps with at most
+ * few_iters iterations dt grows by factor, up to dt_max.  Returns
+ * RF_ERR_NOT_CONVERGED if dt falls below dt_min (state at the last accepted
+ * step).  *out (may be NULL) receives the totals. */
+rf_status rf_run(rf_ctx *ctx, double t_end, rf_run_stats *out);
+
+/* Water balance since rf_set_state: storage sum V theta~(h) (Eq. 2 plus
+ * S*max(h,0)) and the boundary inflow of every accepted step, evaluated with
+ * the converged iterate. */
+rf_status rf_mass_balance(const rf_ctx *ctx, rf_mass *out);
+
+/* --- building blocks of one Picard iteration, for inspection and tests --- */
+
+/* theta~(h), C(h) and K(h) (Eqs. 2-4) of every cell at h_dev (device, N);
+ * any output pointer may be NULL.  Inactive cells are not written. */
+rf_status rf_eval_soil(rf_ctx *ctx, const double *h_dev, double *theta_dev, double *C_dev,
+                       double *K_dev);
+
+/* Assembles the Picard system of iterate hm_dev (device, N) for the step
+ * h^n -> h^n + dt (Sec. 2.2) and keeps it as the current operator; writes the
+ * matrix diagonal A_cc and right-hand side b_c (device, N each, may be NULL)
+ * of active cells. */
+rf_status rf_assemble(rf_ctx *ctx, const double *hm_dev, double dt, double *diag_dev,
+                      double *rhs_dev);
+/* y = A x with the operator of the last rf_assemble (device, N each). */
+rf_status rf_apply_operator(rf_ctx *ctx, const double *x_dev, double *y_dev);
+/* z = M^-1 r with the preconditioner of the last rf_assemble (device, N). */
+rf_status rf_apply_precond(rf_ctx *ctx, const double *r_dev, double *z_dev);
+
+/* --- measurement ------------------------------------------------------- */
+
+#define RF_NKERNELS 8
+typedef struct {
+    const char *name[RF_NKERNELS];  /* "coeff", "resid", "spmv", "update", "apply_h", "accept", "misc" */
+    long launches[RF_NKERNELS];     /* launches that did work, timed with HIP events */
+    double ms[RF_NKERNELS];         /* summed event time of those launches */
+    long idle_launches[RF_NKERNELS];/* PCG launches enqueued past convergence (return at once) */
+    double idle_ms[RF_NKERNELS];
+    long cells;                     /* active cells of the grid */
+} rf_timing;
+
+/* on != 0: bracket every launch with HIP events on the context stream
+ * (costs a little launch overhead).  Resets the counters. */
+rf_status rf_set_timing(rf_ctx *ctx, int on);
+rf_status rf_get_timing(rf_ctx *ctx, rf_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RF_H */

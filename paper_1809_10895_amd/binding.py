@@ -1,0 +1,292 @@
+"""ctypes binding of the C ABI declared in include/rf.h.
+
+Argument marshalling only: every step of the Picard / PCG loop runs in the
+HIP kernels of librf_mi355x.so.  PyTorch provides device memory (the
+workspace and the state tensors) and the HIP stream.  Importing this module
+does not need a GPU; creating a Solver does, and fails loudly if the library
+has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "librf_mi355x.so")
+
+RF_OK, RF_ERR_ARG, RF_ERR_STATE, RF_ERR_HIP, RF_ERR_NOMEM = 0, -1, -2, -3, -4
+RF_ERR_NOT_CONVERGED, RF_ERR_LINEAR, RF_ERR_NONFINITE = -5, -6, -7
+RF_VGM, RF_GARDNER = 0, 1
+RF_XMIN, RF_XMAX, RF_YMIN, RF_YMAX, RF_ZMIN, RF_ZMAX = range(6)
+RF_NOFLOW, RF_DIRICHLET, RF_FLUX, RF_FREE_DRAINAGE = range(4)
+RF_PRECOND_JACOBI, RF_PRECOND_ZLINE = 0, 1
+RF_MAX_PICARD_LOG = 128
+RF_NKERNELS = 8
+
+STATUS_NAMES = {0: "RF_OK", -1: "RF_ERR_ARG", -2: "RF_ERR_STATE", -3: "RF_ERR_HIP",
+                -4: "RF_ERR_NOMEM", -5: "RF_ERR_NOT_CONVERGED", -6: "RF_ERR_LINEAR",
+                -7: "RF_ERR_NONFINITE"}
+
+# Every function the header declares (checked against include/rf.h by the tests).
+EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf_setup_grid",
+           "rf_set_soil", "rf_set_bc", "rf_set_forcing", "rf_set_options", "rf_workspace_bytes",
+           "rf_bind_workspace", "rf_set_state", "rf_get_state", "rf_step", "rf_run",
+           "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
+           "rf_apply_precond", "rf_set_timing", "rf_get_timing"]
+
+
+class RfOptions(C.Structure):
+    _fields_ = [("tol_picard", C.c_double), ("tol_cg", C.c_double), ("max_picard", C.c_int),
+                ("max_cg", C.c_int), ("chord_eps", C.c_double), ("precond", C.c_int),
+                ("check_every", C.c_int), ("dt0", C.c_double), ("dt_max", C.c_double),
+                ("dt_min", C.c_double), ("ebats", C.c_int), ("inc_after", C.c_int),
+                ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double)]
+
+
+class RfStepStats(C.Structure):
+    _fields_ = [("converged", C.c_int), ("picard_iters", C.c_int), ("cg_iters_total", C.c_int),
+                ("cg_iters", C.c_int * RF_MAX_PICARD_LOG),
+                ("delta", C.c_double * RF_MAX_PICARD_LOG), ("dt", C.c_double), ("t", C.c_double)]
+
+
+class RfRunStats(C.Structure):
+    _fields_ = [("accepted", C.c_int), ("rejected", C.c_int), ("picard_total", C.c_long),
+                ("cg_total", C.c_long), ("dt_last", C.c_double), ("t", C.c_double)]
+
+
+class RfMass(C.Structure):
+    _fields_ = [("storage", C.c_double), ("storage0", C.c_double), ("inflow", C.c_double * 6),
+                ("error", C.c_double)]
+
+
+class RfTiming(C.Structure):
+    _fields_ = [("name", C.c_char_p * RF_NKERNELS), ("launches", C.c_long * RF_NKERNELS),
+                ("ms", C.c_double * RF_NKERNELS), ("idle_launches", C.c_long * RF_NKERNELS),
+                ("idle_ms", C.c_double * RF_NKERNELS), ("cells", C.c_long)]
+
+
+class RfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB):
+    """Loads librf_mi355x.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is missing: build it with __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.c_double, C.c_int
+    L.rf_default_options.argtypes = [C.POINTER(RfOptions)]
+    L.rf_default_options.restype = None
+    L.rf_create.argtypes = [C.POINTER(vp), ip, vp]
+    L.rf_destroy.argtypes = [vp]
+    L.rf_destroy.restype = None
+    L.rf_last_error.argtypes = [vp]
+    L.rf_last_error.restype = C.c_char_p
+    L.rf_setup_grid.argtypes = [vp, ip, ip, ip, dp, dp, dp, vp, vp]
+    L.rf_set_soil.argtypes = [vp, ip, ip, vp, vp, vp]
+    L.rf_set_bc.argtypes = [vp, ip, ip, dp]
+    L.rf_set_forcing.argtypes = [vp, ip, ip, vp, vp]
+    L.rf_set_options.argtypes = [vp, C.POINTER(RfOptions)]
+    L.rf_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.rf_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    L.rf_set_state.argtypes = [vp, vp, dp]
+    L.rf_get_state.argtypes = [vp, vp, C.POINTER(C.c_double)]
+    L.rf_step.argtypes = [vp, dp, vp, C.POINTER(RfStepStats)]
+    L.rf_run.argtypes = [vp, dp, C.POINTER(RfRunStats)]
+    L.rf_mass_balance.argtypes = [vp, C.POINTER(RfMass)]
+    L.rf_eval_soil.argtypes = [vp, vp, vp, vp, vp]
+    L.rf_assemble.argtypes = [vp, vp, dp, vp, vp]
+    L.rf_apply_operator.argtypes = [vp, vp, vp]
+    L.rf_apply_precond.argtypes = [vp, vp, vp]
+    L.rf_set_timing.argtypes = [vp, ip]
+    L.rf_get_timing.argtypes = [vp, C.POINTER(RfTiming)]
+    for name in EXPORTS:
+        if name not in ("rf_default_options", "rf_destroy", "rf_last_error"):
+            getattr(L, name).restype = C.c_int      # rf_status
+    _lib = L
+    return L
+
+
+def default_options() -> dict:
+    o = RfOptions()
+    load_library().rf_default_options(C.byref(o))
+    return {name: getattr(o, name) for name, _ in RfOptions._fields_}
+
+
+def step_stats_dict(st: RfStepStats) -> dict:
+    n = min(st.picard_iters, RF_MAX_PICARD_LOG)
+    return {"converged": bool(st.converged), "picard_iters": st.picard_iters,
+            "cg_iters_total": st.cg_iters_total, "cg_iters": list(st.cg_iters[:n]),
+            "delta": list(st.delta[:n]), "dt": st.dt, "t": st.t}
+
+
+def _ptr(t):
+    """Device pointer of a CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    import numpy as np
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+class Solver:
+    """One problem on one GPU: grid, soil, boundary conditions, state."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        s = self.L.rf_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if s != RF_OK:
+            raise RfError(s, "rf_create failed")
+        self.h = h
+        self.ws = None
+        self.shape = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rf_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, s):
+        if s != RF_OK:
+            raise RfError(s, self.L.rf_last_error(self.h).decode())
+        return s
+
+    def last_error(self) -> str:
+        return self.L.rf_last_error(self.h).decode()
+
+    # --- set-up -------------------------------------------------------------
+    def setup_grid(self, nx, ny, nz, dx, dy, dz, ktop=None, grad_elev=None):
+        import numpy as np
+        kt, ktp = _host(ktop, np.int32)
+        g, gp = _host(grad_elev, np.float64)
+        self._check(self.L.rf_setup_grid(self.h, nx, ny, nz, dx, dy, dz, ktp, gp))
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.ws = None
+
+    def set_soil(self, params, layer_of_cell=None, ln_ks_offset=None, model=RF_VGM):
+        import numpy as np
+        p = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+        lay, layp = _host(layer_of_cell, np.uint8)
+        lk, lkp = _host(ln_ks_offset, np.float64)
+        self._check(self.L.rf_set_soil(self.h, model, p.shape[0], p.ctypes.data_as(C.c_void_p),
+                                       layp, lkp))
+
+    def set_bc(self, face, kind, value=0.0):
+        self._check(self.L.rf_set_bc(self.h, face, kind, float(value)))
+
+    def set_forcing(self, face, t_start, flux):
+        import numpy as np
+        t0, t0p = _host(t_start, np.float64)
+        q, qp = _host(flux, np.float64)
+        self._check(self.L.rf_set_forcing(self.h, face, len(t0), t0p, qp))
+
+    def set_options(self, **kw):
+        o = RfOptions()
+        self.L.rf_default_options(C.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self._check(self.L.rf_set_options(self.h, C.byref(o)))
+
+    def workspace_bytes(self) -> int:
+        n = C.c_size_t()
+        self._check(self.L.rf_workspace_bytes(self.h, C.byref(n)))
+        return n.value
+
+    def bind(self):
+        nbytes = self.workspace_bytes()
+        self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        self._check(self.L.rf_bind_workspace(self.h, _ptr(self.ws), nbytes))
+
+    # --- state --------------------------------------------------------------
+    def set_state(self, h, t=0.0):
+        return self.L.rf_set_state(self.h, _ptr(h), float(t))
+
+    def get_state(self):
+        out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+        t = C.c_double()
+        self._check(self.L.rf_get_state(self.h, _ptr(out), C.byref(t)))
+        return out, t.value
+
+    def step(self, dt, guess=None):
+        st = RfStepStats()
+        s = self.L.rf_step(self.h, float(dt), _ptr(guess), C.byref(st))
+        return s, step_stats_dict(st)
+
+    def run(self, t_end):
+        rs = RfRunStats()
+        s = self.L.rf_run(self.h, float(t_end), C.byref(rs))
+        return s, {"accepted": rs.accepted, "rejected": rs.rejected,
+                   "picard_total": rs.picard_total, "cg_total": rs.cg_total,
+                   "dt_last": rs.dt_last, "t": rs.t}
+
+    def mass_balance(self):
+        m = RfMass()
+        self._check(self.L.rf_mass_balance(self.h, C.byref(m)))
+        return {"storage": m.storage, "storage0": m.storage0, "inflow": list(m.inflow),
+                "error": m.error}
+
+    # --- building blocks ----------------------------------------------------
+    def eval_soil(self, h):
+        t = self.torch
+        th, cap, k = (t.full((self.N,), float("nan"), dtype=t.float64, device=self.device)
+                      for _ in range(3))
+        self._check(self.L.rf_eval_soil(self.h, _ptr(h), _ptr(th), _ptr(cap), _ptr(k)))
+        return th, cap, k
+
+    def assemble(self, hm, dt):
+        t = self.torch
+        diag, rhs = (t.full((self.N,), float("nan"), dtype=t.float64, device=self.device)
+                     for _ in range(2))
+        self._check(self.L.rf_assemble(self.h, _ptr(hm), float(dt), _ptr(diag), _ptr(rhs)))
+        return diag, rhs
+
+    def apply_operator(self, x):
+        y = self.torch.full((self.N,), float("nan"), dtype=self.torch.float64, device=self.device)
+        self._check(self.L.rf_apply_operator(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def apply_precond(self, r):
+        z = self.torch.full((self.N,), float("nan"), dtype=self.torch.float64, device=self.device)
+        self._check(self.L.rf_apply_precond(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    # --- measurement --------------------------------------------------------
+    def set_timing(self, on=True):
+        self._check(self.L.rf_set_timing(self.h, 1 if on else 0))
+
+    def get_timing(self) -> dict:
+        tm = RfTiming()
+        self._check(self.L.rf_get_timing(self.h, C.byref(tm)))
+        out = {"cells": tm.cells}
+        for k in range(RF_NKERNELS):
+            name = tm.name[k].decode() if tm.name[k] else ""
+            if name:
+                out[name] = {"launches": tm.launches[k], "ms": tm.ms[k],
+                             "idle_launches": tm.idle_launches[k], "idle_ms": tm.idle_ms[k]}
+        return out

@@ -1,0 +1,767 @@
+// Host orchestrator and C ABI of the MI355X Richards-equation library.
+//
+// The host owns only control flow: the Picard loop of one backward-Euler
+// step (Sec. 2.2), the global exit test (Sec. 2.3), the EBATS time loop
+// (Sec. 2.2), forcing lookup and the water-balance accumulators.  All
+// per-cell arithmetic runs in the HIP kernels of rf_kernels.hip, enqueued on
+// the caller's stream; the host reads back a few scalars once per PCG poll.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "rf_internal.h"
+
+using namespace rf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct EvPair {
+    hipEvent_t a, b;
+    int kernel;
+    int spec;   // index of a PCG launch inside the current Picard iteration, -1 otherwise
+};
+
+}  // namespace
+
+struct rf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char err[512] = {0};
+
+    bool have_grid = false, have_soil = false, have_ws = false, have_state = false;
+    int nx = 0, ny = 0, nz = 0;
+    double dx = 0, dy = 0, dz = 0;
+    double gvec[3] = {0, 0, 1};
+    std::vector<int32_t> ktop;
+    long active = 0;
+
+    int model = RF_VGM;
+    int nlayer = 0;
+    double params[RF_MAX_LAYERS][6];
+    std::vector<uint8_t> layer;
+    std::vector<double> lnks;
+
+    int bc_type[6] = {0, 0, 0, 0, 0, 0};
+    double bc_value[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<double> seg_t[6], seg_q[6];
+
+    rf_options opt;
+
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    Arrays A{};
+    Geo G{};
+    Soil S{};
+
+    double t = 0.0, dt_cur = 1.0;
+    int easy = 0;
+    double storage0 = 0.0, storage = 0.0, inflow[6] = {0, 0, 0, 0, 0, 0};
+    int last_cg = 0;
+
+    Scalars *hsc = nullptr;   // pinned host mirror of the device scalars
+    double *hpart = nullptr;  // pinned host copy of block partials
+    bool assembled = false;
+
+    bool timing = false;
+    std::vector<EvPair> pending;
+    std::vector<EvPair> freelist;
+    rf_timing tm{};
+};
+
+static const char *kKernelNames[RF_NKERNELS] = {"coeff", "resid", "spmv", "update",
+                                                "apply_h", "accept", "misc", ""};
+
+static rf_status fail(rf_ctx *c, rf_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, RF_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// timing helpers
+// ---------------------------------------------------------------------------
+
+static void timed_begin(rf_ctx *c, int kernel, int spec, EvPair &p)
+{
+    if (!c->timing) return;
+    if (c->freelist.empty()) {
+        EvPair q;
+        (void)hipEventCreate(&q.a);
+        (void)hipEventCreate(&q.b);
+        c->freelist.push_back(q);
+    }
+    p = c->freelist.back();
+    c->freelist.pop_back();
+    p.kernel = kernel;
+    p.spec = spec;
+    (void)hipEventRecord(p.a, c->stream);
+}
+
+static void timed_end(rf_ctx *c, EvPair &p)
+{
+    if (!c->timing) return;
+    (void)hipEventRecord(p.b, c->stream);
+    c->pending.push_back(p);
+}
+
+// Called after a stream synchronisation; `iters` = PCG iterations done in the
+// current Picard iteration (launches with spec >= iters did no work).
+static void timed_collect(rf_ctx *c, int iters)
+{
+    if (!c->timing) return;
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        const bool idle = p.spec >= 0 && p.spec >= iters;
+        if (idle) {
+            c->tm.idle_launches[p.kernel]++;
+            c->tm.idle_ms[p.kernel] += ms;
+        } else {
+            c->tm.launches[p.kernel]++;
+            c->tm.ms[p.kernel] += ms;
+        }
+        c->freelist.push_back(p);
+    }
+    c->pending.clear();
+}
+
+#define TIMED(ctx, kid, spec, call)                                     \
+    do {                                                                \
+        EvPair ev_;                                                     \
+        timed_begin(ctx, kid, spec, ev_);                               \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess)                                           \
+            return fail(ctx, RF_ERR_HIP, "launch %s: %s", kKernelNames[kid], \
+                        hipGetErrorString(e_));                         \
+        timed_end(ctx, ev_);                                            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------
+
+static size_t layout(const rf_ctx *c, char *base, Arrays *A)
+{
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    const size_t ncol = (size_t)c->nx * c->ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    Arrays a{};
+    double **dbl[] = {&a.hn, &a.thn, &a.hm, &a.hnew, &a.K, &a.Dd, &a.bst, &a.diag, &a.r,
+                      &a.p0, &a.p1, &a.q, &a.e, &a.z, &a.Ks, &a.tz, &a.rdp};
+    for (double **p : dbl) *p = (double *)take(N * sizeof(double));
+    a.layer = c->layer.empty() ? nullptr : (uint8_t *)take(N);
+    a.ktop = (int32_t *)take(ncol * sizeof(int32_t));
+    a.pr = (double *)take((size_t)kMaxBlocks * 2 * sizeof(double));
+    a.pq = (double *)take((size_t)kMaxBlocks * sizeof(double));
+    a.pd = (double *)take((size_t)kMaxBlocks * 2 * sizeof(double));
+    a.ps = (double *)take((size_t)kMaxBlocks * kRedSlots * sizeof(double));
+    a.ks_layer = (double *)take(RF_MAX_LAYERS * sizeof(double));
+    a.sc = (Scalars *)take(sizeof(Scalars));
+    if (A) *A = a;
+    return off;
+}
+
+static Bc bc_at(const rf_ctx *c, double t)
+{
+    Bc b;
+    for (int f = 0; f < 6; f++) {
+        b.type[f] = c->bc_type[f];
+        b.value[f] = c->bc_value[f];
+        const auto &ts = c->seg_t[f];
+        if (c->bc_type[f] == RF_FLUX && !ts.empty() && t >= ts[0]) {
+            size_t s = 0;
+            while (s + 1 < ts.size() && ts[s + 1] <= t) s++;
+            b.value[f] = c->seg_q[f][s];
+        }
+    }
+    return b;
+}
+
+static double next_forcing_change(const rf_ctx *c, double t)
+{
+    double tn = INFINITY;
+    for (int f = 0; f < 6; f++) {
+        if (c->bc_type[f] != RF_FLUX) continue;
+        for (double s : c->seg_t[f])
+            if (s > t * (1.0 + 1e-15) + 1e-12 && s < tn) tn = s;
+    }
+    return tn;
+}
+
+static rf_status sync_scalars(rf_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hsc, c->A.sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+// Copies the nv-valued block partials of the last kernel and combines them on
+// the host in block order (sum, or max where bit i of maxmask is set).
+static rf_status host_reduce(rf_ctx *c, const double *dev, int nv, unsigned maxmask, double *tot)
+{
+    const int nb = c->G.nblk;
+    HIPCHK(c, hipMemcpyAsync(c->hpart, dev, (size_t)nb * nv * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < nv; i++) tot[i] = 0.0;
+    for (int b = 0; b < nb; b++)
+        for (int i = 0; i < nv; i++) {
+            const double x = c->hpart[(size_t)b * nv + i];
+            tot[i] = ((maxmask >> i) & 1u) ? std::max(tot[i], x) : tot[i] + x;
+        }
+    return RF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void rf_default_options(rf_options *o)
+{
+    if (!o) return;
+    o->tol_picard = 1e-6;
+    o->tol_cg = 1e-8;
+    o->max_picard = 50;
+    o->max_cg = 10000;
+    o->chord_eps = 1e-9;
+    o->precond = RF_PRECOND_ZLINE;
+    o->check_every = 8;
+    o->dt0 = 1.0;
+    o->dt_max = 3600.0;
+    o->dt_min = 1e-6;
+    o->ebats = 1;
+    o->inc_after = 10;
+    o->few_iters = 3;
+    o->max_iters = 8;
+    o->factor = 1.3;
+}
+
+rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
+{
+    if (!out) return RF_ERR_ARG;
+    *out = nullptr;
+    rf_ctx *c = new (std::nothrow) rf_ctx();
+    if (!c) return RF_ERR_NOMEM;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    rf_default_options(&c->opt);
+    c->dt_cur = c->opt.dt0;
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipHostMalloc((void **)&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->hpart, (size_t)kMaxBlocks * kRedSlots * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        if (c->hsc) (void)hipHostFree(c->hsc);
+        delete c;
+        return RF_ERR_HIP;
+    }
+    memset(c->hsc, 0, sizeof(Scalars));
+    c->tm.cells = 0;
+    for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
+    *out = c;
+    return RF_OK;
+}
+
+void rf_destroy(rf_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &p : c->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto &p : c->freelist) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->hpart) (void)hipHostFree(c->hpart);
+    delete c;
+}
+
+const char *rf_last_error(const rf_ctx *c) { return c ? c->err : "null context"; }
+
+rf_status rf_setup_grid(rf_ctx *c, int nx, int ny, int nz, double dx, double dy, double dz,
+                        const int32_t *k_top, const double *grad_elev)
+{
+    if (!c) return RF_ERR_ARG;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || !(dy > 0) || !(dz > 0) ||
+        (double)nx * ny > 2e9 || (double)nx * ny * nz > 4e10)
+        return fail(c, RF_ERR_ARG, "invalid grid %d x %d x %d / %g %g %g", nx, ny, nz, dx, dy, dz);
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    c->dx = dx; c->dy = dy; c->dz = dz;
+    c->gvec[0] = grad_elev ? grad_elev[0] : 0.0;
+    c->gvec[1] = grad_elev ? grad_elev[1] : 0.0;
+    c->gvec[2] = grad_elev ? grad_elev[2] : 1.0;
+    const size_t ncol = (size_t)nx * ny;
+    c->ktop.assign(ncol, nz);
+    c->active = 0;
+    for (size_t i = 0; i < ncol; i++) {
+        int kt = k_top ? k_top[i] : nz;
+        kt = std::max(0, std::min(nz, kt));
+        c->ktop[i] = kt;
+        c->active += kt;
+    }
+    Geo &G = c->G;
+    G.nx = nx; G.ny = ny; G.nz = nz;
+    G.ncol = (int)ncol;
+    // enough blocks to fill the chip, few enough that every block of the next
+    // kernel can combine all block partials cheaply
+    int nb = (int)std::min<size_t>((ncol + kWavesPerBlock - 1) / kWavesPerBlock, kMaxBlocks);
+    if (nb >= 8) nb = (nb + 7) / 8 * 8;
+    G.nblk = nb;
+    G.cpb = (int)((ncol + nb - 1) / nb);
+    G.V = dx * dy * dz;
+    G.A[0] = dy * dz; G.A[1] = dx * dz; G.A[2] = dx * dy;
+    G.Tk[0] = G.A[0] / dx; G.Tk[1] = G.A[1] / dy; G.Tk[2] = G.A[2] / dz;
+    for (int i = 0; i < 3; i++) G.g[i] = c->gvec[i];
+    c->have_grid = true;
+    c->have_soil = false;
+    c->have_ws = false;
+    c->have_state = false;
+    c->assembled = false;
+    c->layer.clear();
+    c->lnks.clear();
+    c->tm.cells = c->active;
+    return RF_OK;
+}
+
+static rf_status upload_soil(rf_ctx *c)
+{
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    Arrays &A = c->A;
+    if (!c->layer.empty() && !A.layer)
+        return fail(c, RF_ERR_STATE, "layer table added after binding: bind the workspace again");
+    if (A.layer) HIPCHK(c, hipMemcpyAsync(A.layer, c->layer.data(), N, hipMemcpyHostToDevice, c->stream));
+    if (!c->lnks.empty())
+        HIPCHK(c, hipMemcpyAsync(A.Ks, c->lnks.data(), N * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+    else
+        HIPCHK(c, hipMemsetAsync(A.Ks, 0, N * sizeof(double), c->stream));
+    double ksl[RF_MAX_LAYERS];
+    for (int l = 0; l < c->nlayer; l++) ksl[l] = c->params[l][4];
+    HIPCHK(c, hipMemcpyAsync(A.ks_layer, ksl, sizeof(ksl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_init_ks(c->G, c->S, A, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+rf_status rf_set_soil(rf_ctx *c, int model, int nlayer, const double *params,
+                      const uint8_t *layer_of_cell, const double *ln_ks_offset)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_grid) return fail(c, RF_ERR_STATE, "rf_set_soil before rf_setup_grid");
+    if (!params || nlayer < 1 || nlayer > RF_MAX_LAYERS || (model != RF_VGM && model != RF_GARDNER))
+        return fail(c, RF_ERR_ARG, "invalid soil arguments");
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    for (int l = 0; l < nlayer; l++) {
+        const double *p = params + 6 * l;
+        if (!(p[0] >= 0) || !(p[1] > p[0]) || !(p[2] > 0) || !(p[4] > 0) || !(p[5] >= 0) ||
+            (model == RF_VGM && !(p[3] > 1.0)))
+            return fail(c, RF_ERR_ARG, "invalid soil parameters in layer %d", l);
+    }
+    if (layer_of_cell)
+        for (size_t i = 0; i < N; i++)
+            if (layer_of_cell[i] >= nlayer) return fail(c, RF_ERR_ARG, "layer index out of range");
+    const bool had_layer = !c->layer.empty();
+    c->model = model;
+    c->nlayer = nlayer;
+    for (int l = 0; l < nlayer; l++) memcpy(c->params[l], params + 6 * l, 6 * sizeof(double));
+    if (layer_of_cell) c->layer.assign(layer_of_cell, layer_of_cell + N); else c->layer.clear();
+    if (ln_ks_offset) c->lnks.assign(ln_ks_offset, ln_ks_offset + N); else c->lnks.clear();
+    Soil &S = c->S;
+    S.model = model;
+    S.nlayer = nlayer;
+    for (int l = 0; l < nlayer; l++) {
+        const double *p = params + 6 * l;
+        S.L[l].tr = p[0]; S.L[l].ts = p[1]; S.L[l].a = p[2]; S.L[l].n = p[3];
+        S.L[l].m = (model == RF_VGM) ? 1.0 - 1.0 / p[3] : 0.0;
+        S.L[l].S = p[5];
+    }
+    c->have_soil = true;
+    if (c->have_ws) {
+        if (had_layer != !c->layer.empty()) {
+            c->have_ws = false;   // layout changes: the caller must bind again
+            c->have_state = false;
+            return RF_OK;
+        }
+        rf_status s = upload_soil(c);
+        if (s) return s;
+        c->have_state = false;
+    }
+    return RF_OK;
+}
+
+rf_status rf_set_bc(rf_ctx *c, int face, int type, double value)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_grid) return fail(c, RF_ERR_STATE, "rf_set_bc before rf_setup_grid");
+    if (face < 0 || face > 5 || type < 0 || type > 3 || !std::isfinite(value))
+        return fail(c, RF_ERR_ARG, "invalid boundary condition");
+    c->bc_type[face] = type;
+    c->bc_value[face] = value;
+    return RF_OK;
+}
+
+rf_status rf_set_forcing(rf_ctx *c, int face, int nseg, const double *t_start, const double *flux)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_grid) return fail(c, RF_ERR_STATE, "rf_set_forcing before rf_setup_grid");
+    if (face < 0 || face > 5 || nseg < 0 || (nseg > 0 && (!t_start || !flux)))
+        return fail(c, RF_ERR_ARG, "invalid forcing");
+    for (int s = 1; s < nseg; s++)
+        if (!(t_start[s] > t_start[s - 1])) return fail(c, RF_ERR_ARG, "forcing times must increase");
+    c->seg_t[face].assign(t_start, t_start + nseg);
+    c->seg_q[face].assign(flux, flux + nseg);
+    return RF_OK;
+}
+
+rf_status rf_set_options(rf_ctx *c, const rf_options *o)
+{
+    if (!c || !o) return RF_ERR_ARG;
+    if (!(o->tol_picard > 0) || !(o->tol_cg > 0) || o->max_picard < 1 || o->max_cg < 1 ||
+        !(o->chord_eps >= 0) || (o->precond != RF_PRECOND_JACOBI && o->precond != RF_PRECOND_ZLINE) ||
+        o->check_every < 1 || !(o->dt0 > 0) || !(o->dt_max > 0) || !(o->dt_min > 0) ||
+        o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0))
+        return fail(c, RF_ERR_ARG, "invalid options");
+    c->opt = *o;
+    c->dt_cur = o->dt0;
+    c->easy = 0;
+    return RF_OK;
+}
+
+rf_status rf_workspace_bytes(const rf_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return RF_ERR_ARG;
+    if (!c->have_grid || !c->have_soil) return RF_ERR_STATE;
+    *bytes = layout(c, nullptr, nullptr);
+    return RF_OK;
+}
+
+rf_status rf_bind_workspace(rf_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_grid || !c->have_soil)
+        return fail(c, RF_ERR_STATE, "rf_bind_workspace before grid and soil");
+    if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0)
+        return fail(c, RF_ERR_ARG, "workspace must be a 256-byte aligned device pointer");
+    const size_t need = layout(c, nullptr, nullptr);
+    if (bytes < need)
+        return fail(c, RF_ERR_NOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
+    HIPCHK(c, hipSetDevice(c->device));
+    layout(c, (char *)dev_ptr, &c->A);
+    c->ws = dev_ptr;
+    c->ws_bytes = bytes;
+    HIPCHK(c, hipMemcpyAsync(c->A.ktop, c->ktop.data(), c->ktop.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->A.sc, 0, sizeof(Scalars), c->stream));
+    rf_status s = upload_soil(c);
+    if (s) return s;
+    c->have_ws = true;
+    c->have_state = false;
+    c->assembled = false;
+    return RF_OK;
+}
+
+rf_status rf_set_state(rf_ctx *c, const double *h_dev, double t)
+{
+    if (!c || !h_dev) return RF_ERR_ARG;
+    if (!c->have_ws) return fail(c, RF_ERR_STATE, "rf_set_state before rf_bind_workspace");
+    if (!std::isfinite(t)) return fail(c, RF_ERR_ARG, "non-finite time");
+    HIPCHK(c, launch_check_finite(c->G, c->A, h_dev, c->stream));
+    double bad = 0.0;
+    rf_status s = host_reduce(c, c->A.ps, 1, 0u, &bad);
+    if (s) return s;
+    if (bad != 0.0)
+        return fail(c, RF_ERR_NONFINITE, "%.0f non-finite active cells in the state", bad);
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    // inactive cells are carried unchanged: take the whole array first
+    HIPCHK(c, hipMemcpyAsync(c->A.hn, h_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_set_state(c->G, c->S, c->A, h_dev, c->stream));
+    double st = 0.0;
+    s = host_reduce(c, c->A.ps, 1, 0u, &st);
+    if (s) return s;
+    c->storage0 = c->storage = st;
+    for (int f = 0; f < 6; f++) c->inflow[f] = 0.0;
+    c->t = t;
+    c->dt_cur = c->opt.dt0;
+    c->easy = 0;
+    c->last_cg = c->opt.check_every;
+    c->have_state = true;
+    return RF_OK;
+}
+
+rf_status rf_get_state(const rf_ctx *cc, double *h_dev, double *t)
+{
+    rf_ctx *c = const_cast<rf_ctx *>(cc);
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_get_state before rf_set_state");
+    if (h_dev) {
+        const size_t N = (size_t)c->nx * c->ny * c->nz;
+        HIPCHK(c, hipMemcpyAsync(h_dev, c->A.hn, N * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (t) *t = c->t;
+    return RF_OK;
+}
+
+// One Picard iteration's PCG solve: enqueue PCG iterations in chunks (the
+// first sized by the previous solve) until the device reports that the
+// Picard update hnew = h^m + e has been written, or a failure.  Leaves
+// c->hsc current.
+static rf_status pcg_solve(rf_ctx *c)
+{
+    const Geo &G = c->G;
+    Arrays &A = c->A;
+    const int pc = c->opt.precond;
+    double *pin = A.p0, *pout = A.p1;
+    int chunk = std::max(1, c->last_cg);
+    int launched = 0;
+    for (;;) {
+        for (int i = 0; i < chunk; i++) {
+            TIMED(c, K_SPMV, launched, launch_spmv(G, A, pc, pin, pout, c->opt.tol_cg, c->opt.max_cg,
+                                                   c->stream));
+            TIMED(c, K_UPDATE, launched, launch_update(G, A, pc, pout, c->stream));
+            std::swap(pin, pout);
+            launched++;
+        }
+        TIMED(c, K_APPLYH, -1, launch_apply_h(G, A, c->opt.tol_cg, c->opt.max_cg, c->stream));
+        rf_status s = sync_scalars(c);
+        if (s) return s;
+        if (c->hsc->applied || c->hsc->fail) {
+            timed_collect(c, c->hsc->final_iters);
+            break;
+        }
+        timed_collect(c, launched);
+        chunk = std::max(1, std::min(c->opt.check_every, c->last_cg / 2 + 1));
+    }
+    c->last_cg = std::max(1, c->hsc->final_iters);
+    return RF_OK;
+}
+
+static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_picard,
+                             rf_step_stats *st)
+{
+    memset(st, 0, sizeof(*st));
+    st->dt = dt;
+    st->t = c->t;
+    const Geo &G = c->G;
+    Arrays &A = c->A;
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    const Bc bc = bc_at(c, c->t);
+    HIPCHK(c, hipMemcpyAsync(A.hm, guess ? guess : A.hn, N * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    rf_status status = RF_ERR_NOT_CONVERGED;
+    for (int m = 0; m < max_picard; m++) {
+        TIMED(c, K_COEFF, -1, launch_coeff(G, c->S, bc, A, dt, c->opt.chord_eps, c->stream));
+        TIMED(c, K_RESID, -1, launch_resid(G, A, c->opt.precond, nullptr, c->stream));
+        rf_status s = pcg_solve(c);
+        if (s) return s;
+        const Scalars h = *c->hsc;
+        st->picard_iters = m + 1;
+        st->cg_iters_total += h.final_iters;
+        if (m < RF_MAX_PICARD_LOG) st->cg_iters[m] = h.final_iters;
+        if (h.fail) {
+            status = (h.fail == 3) ? RF_ERR_NONFINITE : RF_ERR_LINEAR;
+            fail(c, status, "PCG %s in Picard iteration %d after %d iterations",
+                 h.fail == 1 ? "breakdown" : h.fail == 2 ? "hit max_cg" : "produced NaN/Inf", m,
+                 h.final_iters);
+            break;
+        }
+        double dd[2];
+        s = host_reduce(c, A.pd, 2, 1u, dd);
+        if (s) return s;
+        if (m < RF_MAX_PICARD_LOG) st->delta[m] = dd[0];
+        std::swap(A.hm, A.hnew);      // h^{m+1} becomes the current iterate
+        if (dd[1] != 0.0 || !std::isfinite(dd[0])) {
+            status = fail(c, RF_ERR_NONFINITE, "non-finite Picard iterate");
+            break;
+        }
+        if (dd[0] < c->opt.tol_picard) {
+            status = RF_OK;
+            break;
+        }
+    }
+    if (status == RF_ERR_NOT_CONVERGED)
+        fail(c, status, "Picard did not converge in %d iterations (dt %g)", max_picard, dt);
+    if (status != RF_OK) {
+        timed_collect(c, 0);
+        return status;
+    }
+    TIMED(c, K_ACCEPT, -1, launch_accept(G, c->S, bc, A, c->stream));
+    double sums[7];
+    rf_status s = host_reduce(c, A.ps, 7, 0u, sums);
+    if (s) return s;
+    timed_collect(c, 0);
+    c->storage = sums[0];
+    for (int f = 0; f < 6; f++) c->inflow[f] += dt * sums[1 + f];
+    c->t += dt;
+    st->converged = 1;
+    st->t = c->t;
+    return RF_OK;
+}
+
+rf_status rf_step(rf_ctx *c, double dt, const double *h_guess_dev, rf_step_stats *out)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_step before rf_set_state");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, RF_ERR_ARG, "invalid dt %g", dt);
+    rf_step_stats st;
+    rf_status s = picard_step(c, dt, h_guess_dev, c->opt.max_picard, &st);
+    if (out) *out = st;
+    return s;
+}
+
+rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_run before rf_set_state");
+    rf_run_stats rs;
+    memset(&rs, 0, sizeof(rs));
+    rf_step_stats st;
+    rf_status ret = RF_OK;
+    while (c->t < t_end * (1.0 - 1e-15) - 1e-12) {
+        double dt = c->opt.ebats ? c->dt_cur : c->opt.dt0;
+        bool clipped = false;
+        const double tf = next_forcing_change(c, c->t);
+        if (c->t + dt > tf) { dt = tf - c->t; clipped = true; }
+        if (c->t + dt > t_end) { dt = t_end - c->t; clipped = true; }
+        const int maxp = c->opt.ebats ? c->opt.max_iters : c->opt.max_picard;
+        rf_status s = picard_step(c, dt, nullptr, maxp, &st);
+        rs.picard_total += st.picard_iters;
+        rs.cg_total += st.cg_iters_total;
+        if (s == RF_ERR_HIP || s == RF_ERR_ARG || s == RF_ERR_STATE) { ret = s; break; }
+        if (s != RF_OK) {
+            rs.rejected++;
+            if (!c->opt.ebats) { ret = s; break; }
+            c->dt_cur = dt / c->opt.factor;
+            c->easy = 0;
+            if (c->dt_cur < c->opt.dt_min) {
+                ret = fail(c, RF_ERR_NOT_CONVERGED, "EBATS: dt %g fell below dt_min %g", c->dt_cur,
+                           c->opt.dt_min);
+                break;
+            }
+            continue;
+        }
+        rs.accepted++;
+        if (c->opt.ebats) {
+            if (!clipped) c->dt_cur = dt;
+            if (st.picard_iters <= c->opt.few_iters) {
+                if (++c->easy >= c->opt.inc_after) {
+                    c->dt_cur = std::min(c->dt_cur * c->opt.factor, c->opt.dt_max);
+                    c->easy = 0;
+                }
+            } else {
+                c->easy = 0;
+            }
+        }
+    }
+    rs.t = c->t;
+    rs.dt_last = c->opt.ebats ? c->dt_cur : c->opt.dt0;
+    if (out) *out = rs;
+    return ret;
+}
+
+rf_status rf_mass_balance(const rf_ctx *c, rf_mass *out)
+{
+    if (!c || !out) return RF_ERR_ARG;
+    if (!c->have_state) return RF_ERR_STATE;
+    out->storage = c->storage;
+    out->storage0 = c->storage0;
+    double in = 0.0;
+    for (int f = 0; f < 6; f++) {
+        out->inflow[f] = c->inflow[f];
+        in += c->inflow[f];
+    }
+    out->error = c->storage - c->storage0 - in;
+    return RF_OK;
+}
+
+rf_status rf_eval_soil(rf_ctx *c, const double *h_dev, double *theta_dev, double *C_dev,
+                       double *K_dev)
+{
+    if (!c || !h_dev) return RF_ERR_ARG;
+    if (!c->have_ws) return fail(c, RF_ERR_STATE, "rf_eval_soil before rf_bind_workspace");
+    HIPCHK(c, launch_eval_soil(c->G, c->S, c->A, h_dev, theta_dev, C_dev, K_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_dev,
+                      double *rhs_dev)
+{
+    if (!c || !hm_dev) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_assemble before rf_set_state");
+    if (!(dt > 0)) return fail(c, RF_ERR_ARG, "invalid dt");
+    const size_t N = (size_t)c->nx * c->ny * c->nz;
+    const Bc bc = bc_at(c, c->t);
+    HIPCHK(c, hipMemcpyAsync(c->A.hm, hm_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_coeff(c->G, c->S, bc, c->A, dt, c->opt.chord_eps, c->stream));
+    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, rhs_dev, c->stream));
+    if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->assembled = true;
+    return RF_OK;
+}
+
+rf_status rf_apply_operator(rf_ctx *c, const double *x_dev, double *y_dev)
+{
+    if (!c || !x_dev || !y_dev) return RF_ERR_ARG;
+    if (!c->assembled) return fail(c, RF_ERR_STATE, "rf_apply_operator before rf_assemble");
+    HIPCHK(c, launch_operator(c->G, c->A, x_dev, y_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+rf_status rf_apply_precond(rf_ctx *c, const double *r_dev, double *z_dev)
+{
+    if (!c || !r_dev || !z_dev) return RF_ERR_ARG;
+    if (!c->assembled) return fail(c, RF_ERR_STATE, "rf_apply_precond before rf_assemble");
+    HIPCHK(c, launch_precond(c->G, c->A, c->opt.precond, r_dev, z_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+rf_status rf_set_timing(rf_ctx *c, int on)
+{
+    if (!c) return RF_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    timed_collect(c, 0);
+    c->timing = on != 0;
+    const long cells = c->active;
+    memset(&c->tm, 0, sizeof(c->tm));
+    for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
+    c->tm.cells = cells;
+    return RF_OK;
+}
+
+rf_status rf_get_timing(rf_ctx *c, rf_timing *out)
+{
+    if (!c || !out) return RF_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    timed_collect(c, 0);
+    *out = c->tm;
+    return RF_OK;
+}
+
+}  // extern "C"
