@@ -39,12 +39,17 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=144)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="hillslope", choices=["hillslope", "watershed", "column100"])
     ap.add_argument("--precond", default="zline", choices=["zline", "jacobi"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="copy this many MiB with torch before the steps (reference kernel of "
+                         "known traffic for hardware-counter runs)")
+    ap.add_argument("--cols-per-wave", type=int, default=0,
+                    help="launch shape of the PCG kernels (0 = chosen from the grid size)")
     return ap.parse_args()
 
 
@@ -118,21 +123,36 @@ def main():
     import torch
     from paper_1809_10895_amd import Solver, workloads as W
 
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w, desc = make_workload(args.workload)
     pc = 1 if args.precond == "zline" else 0
     S = Solver(0)
     S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
     W.configure(w, S)
-    S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt, ebats=0)
+    S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt, ebats=0,
+                  cols_per_wave=args.cols_per_wave)
     S.bind()
     h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
     assert S.set_state(h0) == 0, S.last_error()
 
     picard = cg = 0
+    # warm-up steps, the first ones timing every kernel to find the dominant one
+    S.set_timing(True)
     for _ in range(args.warmup):
         s, st = S.step(w.dt)
         assert s == 0, S.last_error()
-    S.set_timing(not args.no_timing)
+    tm_all = S.get_timing()
+    tot_all = sum(v["ms"] for v in tm_all.values() if isinstance(v, dict))
+    kern = max((k for k in ALGO_BYTES if k in tm_all and tm_all[k]["launches"]),
+               key=lambda k: tm_all[k]["ms"], default=None)
+    # timed region: HIP events bracket only the dominant kernel's launches
+    S.set_timing([kern] if (kern and not args.no_timing) else False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -147,11 +167,8 @@ def main():
     cells = w.active_cells
     value = cells * args.steps / el
 
-    # dominant kernel by summed event time
-    kern = max((k for k in ALGO_BYTES if k in tm and tm[k]["launches"]),
-               key=lambda k: tm[k]["ms"], default=None)
     roof = None
-    if kern is not None and tm[kern]["launches"]:
+    if kern is not None and not args.no_timing and tm[kern]["launches"]:
         avg_s = tm[kern]["ms"] / tm[kern]["launches"] * 1e-3
         algo = ALGO_BYTES[kern][pc] * cells
         achieved = algo / avg_s / 1e9
@@ -160,13 +177,12 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern, "avg_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes_per_launch": algo}
+    # per-kernel breakdown from the warm-up steps (all kernels timed there)
     kernels = {k: {"launches": v["launches"], "avg_us": round(v["ms"] / v["launches"] * 1e3, 2)
-                   if v["launches"] else None, "share": None, "idle_launches": v["idle_launches"]}
-               for k, v in tm.items() if isinstance(v, dict)}
-    tot = sum(v["ms"] for k, v in tm.items() if isinstance(v, dict))
-    for k, v in tm.items():
-        if isinstance(v, dict) and tot > 0:
-            kernels[k]["share"] = round(v["ms"] / tot, 3)
+                   if v["launches"] else None,
+                   "share": round(v["ms"] / tot_all, 3) if tot_all > 0 else None,
+                   "idle_launches": v["idle_launches"]}
+               for k, v in tm_all.items() if isinstance(v, dict)}
 
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
@@ -176,11 +192,12 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "active_cells": cells, "grid": [w.nx, w.ny, w.nz],
                    "dt_s": w.dt, "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
-                   "precond": args.precond, "picard_per_step": picard / args.steps,
+                   "precond": args.precond, "cols_per_wave": args.cols_per_wave,
+                   "picard_per_step": picard / args.steps,
                    "cg_per_picard": cg / max(picard, 1),
                    "wall_s_per_simulated_day": el / (args.steps * w.dt) * 86400.0},
         "roofline": roof,
-        "kernels": kernels,
+        "kernels_warmup": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -79,6 +79,8 @@ typedef struct {
     int few_iters;      /* an easy step needs at most this many Picard its (default 3) */
     int max_iters;      /* under EBATS a step needing more Picard its is rerun (default 8) */
     double factor;      /* EBATS growth / shrink factor (default 1.3) */
+    int cols_per_wave;  /* launch shape of the PCG kernels: z-columns per wavefront
+                           (0 = chosen from the grid size) */
 } rf_options;
 
 typedef struct {
@@ -215,9 +217,11 @@ typedef struct {
     long cells;                     /* active cells of the grid */
 } rf_timing;
 
-/* on != 0: bracket every launch with HIP events on the context stream
- * (costs a little launch overhead).  Resets the counters. */
-rf_status rf_set_timing(rf_ctx *ctx, int on);
+/* Brackets the launches of kernel k with HIP events on the context stream
+ * when bit k of `mask` is set (k indexes rf_timing.name; mask 0xff times
+ * every kernel, 0 turns timing off).  Each bracketed launch costs some
+ * launch overhead.  Resets the counters. */
+rf_status rf_set_timing(rf_ctx *ctx, int mask);
 rf_status rf_get_timing(rf_ctx *ctx, rf_timing *out);
 
 #ifdef __cplusplus

@@ -40,7 +40,8 @@ class RfOptions(C.Structure):
                 ("max_cg", C.c_int), ("chord_eps", C.c_double), ("precond", C.c_int),
                 ("check_every", C.c_int), ("dt0", C.c_double), ("dt_max", C.c_double),
                 ("dt_min", C.c_double), ("ebats", C.c_int), ("inc_after", C.c_int),
-                ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double)]
+                ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double),
+                ("cols_per_wave", C.c_int)]
 
 
 class RfStepStats(C.Structure):
@@ -277,8 +278,19 @@ class Solver:
         return z
 
     # --- measurement --------------------------------------------------------
-    def set_timing(self, on=True):
-        self._check(self.L.rf_set_timing(self.h, 1 if on else 0))
+    KERNELS = ("coeff", "resid", "spmv", "update", "apply_h", "accept", "decide", "begin")
+
+    def set_timing(self, kernels=True):
+        """kernels: True (all), False/None (off) or an iterable of kernel names."""
+        if kernels is True:
+            mask = 0xff
+        elif not kernels:
+            mask = 0
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << self.KERNELS.index(k)
+        self._check(self.L.rf_set_timing(self.h, mask))
 
     def get_timing(self) -> dict:
         tm = RfTiming()

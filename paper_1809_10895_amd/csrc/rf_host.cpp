@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -27,7 +28,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct EvPair {
     hipEvent_t a, b;
     int kernel;
-    int spec;   // index of a PCG launch inside the current Picard iteration, -1 otherwise
+    int m;      // Picard iteration of the launch (-1: none)
+    int j;      // PCG iteration of an spmv/update launch, launch count of apply_h/accept
 };
 
 }  // namespace
@@ -65,20 +67,23 @@ struct rf_ctx {
     double t = 0.0, dt_cur = 1.0;
     int easy = 0;
     double storage0 = 0.0, storage = 0.0, inflow[6] = {0, 0, 0, 0, 0, 0};
-    int last_cg = 0;
+    int pred_picard = 3;                   // Picard iterations enqueued up front
+    int pred_cg[RF_MAX_PICARD_LOG];        // PCG iterations enqueued per Picard iteration
+    int pairs_enq[RF_MAX_PICARD_LOG];      // PCG iterations enqueued in this step
+    int apply_enq[RF_MAX_PICARD_LOG];      // Picard-update launches in this step
 
     Scalars *hsc = nullptr;   // pinned host mirror of the device scalars
     double *hpart = nullptr;  // pinned host copy of block partials
     bool assembled = false;
 
-    bool timing = false;
+    int timing = 0;           // bit k: bracket kernel k with events
     std::vector<EvPair> pending;
     std::vector<EvPair> freelist;
     rf_timing tm{};
 };
 
 static const char *kKernelNames[RF_NKERNELS] = {"coeff", "resid", "spmv", "update",
-                                                "apply_h", "accept", "misc", ""};
+                                                "apply_h", "accept", "decide", "begin"};
 
 static rf_status fail(rf_ctx *c, rf_status s, const char *fmt, ...)
 {
@@ -100,9 +105,10 @@ static rf_status fail(rf_ctx *c, rf_status s, const char *fmt, ...)
 // timing helpers
 // ---------------------------------------------------------------------------
 
-static void timed_begin(rf_ctx *c, int kernel, int spec, EvPair &p)
+static void timed_begin(rf_ctx *c, int kernel, int m, int j, EvPair &p)
 {
-    if (!c->timing) return;
+    p.kernel = -1;
+    if (!((c->timing >> kernel) & 1)) return;
     if (c->freelist.empty()) {
         EvPair q;
         (void)hipEventCreate(&q.a);
@@ -112,42 +118,71 @@ static void timed_begin(rf_ctx *c, int kernel, int spec, EvPair &p)
     p = c->freelist.back();
     c->freelist.pop_back();
     p.kernel = kernel;
-    p.spec = spec;
+    p.m = m;
+    p.j = j;
     (void)hipEventRecord(p.a, c->stream);
 }
 
 static void timed_end(rf_ctx *c, EvPair &p)
 {
-    if (!c->timing) return;
+    if (p.kernel < 0) return;
     (void)hipEventRecord(p.b, c->stream);
     c->pending.push_back(p);
 }
 
-// Called after a stream synchronisation; `iters` = PCG iterations done in the
-// current Picard iteration (launches with spec >= iters did no work).
-static void timed_collect(rf_ctx *c, int iters)
+// After a step: a launch did work iff the device logs say so (kernels
+// enqueued speculatively past the end of a PCG solve or of the Picard loop
+// return at once).  last_m: last Picard iteration that ran; cg[m]: PCG
+// iterations of iteration m; napply[m] / naccept: launches of the kind.
+static void timed_collect(rf_ctx *c, int last_m, const int *cg, const int *napply, int naccept)
 {
     if (!c->timing) return;
+    std::vector<int> seen_apply(RF_MAX_PICARD_LOG, 0);
+    int seen_accept = 0;
     for (auto &p : c->pending) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, p.a, p.b);
-        const bool idle = p.spec >= 0 && p.spec >= iters;
-        if (idle) {
-            c->tm.idle_launches[p.kernel]++;
-            c->tm.idle_ms[p.kernel] += ms;
-        } else {
+        bool work = true;
+        const int m = p.m;
+        const bool logged = m >= 0 && m < RF_MAX_PICARD_LOG;
+        switch (p.kernel) {
+        case K_COEFF: case K_RESID: case K_DECIDE:
+            work = m <= last_m;
+            break;
+        case K_SPMV: case K_UPDATE:
+            work = logged && m <= last_m && p.j < cg[m];
+            break;
+        case K_APPLYH:
+            work = logged && m <= last_m && ++seen_apply[m] == napply[m];
+            break;
+        case K_ACCEPT:
+            work = ++seen_accept == naccept;
+            break;
+        default:
+            break;
+        }
+        if (work) {
             c->tm.launches[p.kernel]++;
             c->tm.ms[p.kernel] += ms;
+        } else {
+            c->tm.idle_launches[p.kernel]++;
+            c->tm.idle_ms[p.kernel] += ms;
         }
         c->freelist.push_back(p);
     }
     c->pending.clear();
 }
 
-#define TIMED(ctx, kid, spec, call)                                     \
+static void timed_drop(rf_ctx *c)
+{
+    for (auto &p : c->pending) c->freelist.push_back(p);
+    c->pending.clear();
+}
+
+#define TIMED(ctx, kid, m, j, call)                                     \
     do {                                                                \
         EvPair ev_;                                                     \
-        timed_begin(ctx, kid, spec, ev_);                               \
+        timed_begin(ctx, kid, m, j, ev_);                               \
         hipError_t e_ = (call);                                         \
         if (e_ != hipSuccess)                                           \
             return fail(ctx, RF_ERR_HIP, "launch %s: %s", kKernelNames[kid], \
@@ -158,6 +193,14 @@ static void timed_collect(rf_ctx *c, int iters)
 // ---------------------------------------------------------------------------
 // layout
 // ---------------------------------------------------------------------------
+
+static size_t max_partial_blocks(const rf_ctx *c)
+{
+    const size_t ncol = (size_t)c->nx * c->ny;
+    size_t nb = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (nb >= 8) nb = (nb + 7) / 8 * 8;
+    return nb;
+}
 
 static size_t layout(const rf_ctx *c, char *base, Arrays *A)
 {
@@ -170,20 +213,49 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
         return p;
     };
     Arrays a{};
-    double **dbl[] = {&a.hn, &a.thn, &a.hm, &a.hnew, &a.K, &a.Dd, &a.bst, &a.diag, &a.r,
+    double **dbl[] = {&a.hn, &a.thn, &a.hb0, &a.hb1, &a.K, &a.Dd, &a.bst, &a.diag, &a.r,
                       &a.p0, &a.p1, &a.q, &a.e, &a.z, &a.Ks, &a.tz, &a.rdp};
     for (double **p : dbl) *p = (double *)take(N * sizeof(double));
     a.layer = c->layer.empty() ? nullptr : (uint8_t *)take(N);
     a.ktop = (int32_t *)take(ncol * sizeof(int32_t));
-    a.pr = (double *)take((size_t)kMaxBlocks * 2 * sizeof(double));
-    a.pq = (double *)take((size_t)kMaxBlocks * sizeof(double));
-    a.pd = (double *)take((size_t)kMaxBlocks * 2 * sizeof(double));
-    a.ps = (double *)take((size_t)kMaxBlocks * kRedSlots * sizeof(double));
+    const size_t nb1 = max_partial_blocks(c) + 1;
+    a.pr = (double *)take(nb1 * 2 * sizeof(double));
+    a.pq = (double *)take(nb1 * sizeof(double));
+    a.pd = (double *)take(nb1 * 2 * sizeof(double));
+    a.ps = (double *)take(nb1 * kRedSlots * sizeof(double));
     a.ks_layer = (double *)take(RF_MAX_LAYERS * sizeof(double));
+    a.krb = (double *)take(6 * RF_MAX_LAYERS * sizeof(double));
+    a.layers = (Layer *)take(RF_MAX_LAYERS * sizeof(Layer));
+    a.bt = (double *)take(24 * sizeof(double));
     a.sc = (Scalars *)take(sizeof(Scalars));
     if (A) *A = a;
     return off;
 }
+
+// Launch shapes of the grid (see Geo).  Partial arrays are sized for one
+// column per wave, so changing the shape never changes the workspace layout.
+static void set_shapes(rf_ctx *c)
+{
+    Geo &G = c->G;
+    const size_t ncol = (size_t)c->nx * c->ny;
+    // kernels without block partials: one column per wave
+    size_t nw = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
+    nw = std::min<size_t>(nw, (size_t)1 << 20);
+    if (nw >= 8) nw = (nw + 7) / 8 * 8;
+    G.nblk_w = (int)nw;
+    G.cpb_w = (int)((ncol + nw - 1) / nw);
+    // kernels with block partials: cols_per_wave columns per wave (latency
+    // hiding needs many waves; a large grid pays one fold kernel per reduction)
+    const int cpw = std::max(1, c->opt.cols_per_wave > 0 ? c->opt.cols_per_wave : 4);
+    size_t nb = (ncol + (size_t)kWavesPerBlock * cpw - 1) / ((size_t)kWavesPerBlock * cpw);
+    nb = std::min<size_t>(nb, (size_t)1 << 20);
+    if (nb >= 8) nb = (nb + 7) / 8 * 8;
+    G.nblk = (int)nb;
+    G.cpb = (int)((ncol + nb - 1) / nb);
+    G.np = (G.nblk > kPartialsMax) ? 1 : G.nblk;
+    G.foff = (G.np == 1 && G.nblk > 1) ? G.nblk : 0;
+}
+
 
 static Bc bc_at(const rf_ctx *c, double t)
 {
@@ -223,8 +295,8 @@ static rf_status sync_scalars(rf_ctx *c)
 // the host in block order (sum, or max where bit i of maxmask is set).
 static rf_status host_reduce(rf_ctx *c, const double *dev, int nv, unsigned maxmask, double *tot)
 {
-    const int nb = c->G.nblk;
-    HIPCHK(c, hipMemcpyAsync(c->hpart, dev, (size_t)nb * nv * sizeof(double),
+    const int nb = c->G.np;
+    HIPCHK(c, hipMemcpyAsync(c->hpart, dev + (size_t)c->G.foff * nv, (size_t)nb * nv * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < nv; i++) tot[i] = 0.0;
@@ -260,6 +332,7 @@ void rf_default_options(rf_options *o)
     o->few_iters = 3;
     o->max_iters = 8;
     o->factor = 1.3;
+    o->cols_per_wave = 0;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -274,7 +347,7 @@ rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
     c->dt_cur = c->opt.dt0;
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipHostMalloc((void **)&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->hpart, (size_t)kMaxBlocks * kRedSlots * sizeof(double),
+        hipHostMalloc((void **)&c->hpart, (size_t)kPartialsMax * kRedSlots * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         if (c->hsc) (void)hipHostFree(c->hsc);
         delete c;
@@ -283,6 +356,7 @@ rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
     memset(c->hsc, 0, sizeof(Scalars));
     c->tm.cells = 0;
     for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
+    for (int m = 0; m < RF_MAX_PICARD_LOG; m++) c->pred_cg[m] = 2;
     *out = c;
     return RF_OK;
 }
@@ -324,12 +398,11 @@ rf_status rf_setup_grid(rf_ctx *c, int nx, int ny, int nz, double dx, double dy,
     Geo &G = c->G;
     G.nx = nx; G.ny = ny; G.nz = nz;
     G.ncol = (int)ncol;
-    // enough blocks to fill the chip, few enough that every block of the next
-    // kernel can combine all block partials cheaply
-    int nb = (int)std::min<size_t>((ncol + kWavesPerBlock - 1) / kWavesPerBlock, kMaxBlocks);
-    if (nb >= 8) nb = (nb + 7) / 8 * 8;
-    G.nblk = nb;
-    G.cpb = (int)((ncol + nb - 1) / nb);
+    set_shapes(c);
+    {
+        const char *bm = getenv("RF_BLOCK_MAP");   // launch-shape experiments only
+        G.block_map = bm ? atoi(bm) : 1;
+    }
     G.V = dx * dy * dz;
     G.A[0] = dy * dz; G.A[1] = dx * dz; G.A[2] = dx * dy;
     G.Tk[0] = G.A[0] / dx; G.Tk[1] = G.A[1] / dy; G.Tk[2] = G.A[2] / dz;
@@ -360,6 +433,7 @@ static rf_status upload_soil(rf_ctx *c)
     double ksl[RF_MAX_LAYERS];
     for (int l = 0; l < c->nlayer; l++) ksl[l] = c->params[l][4];
     HIPCHK(c, hipMemcpyAsync(A.ks_layer, ksl, sizeof(ksl), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(A.layers, c->S.L, sizeof(c->S.L), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_init_ks(c->G, c->S, A, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RF_OK;
@@ -441,11 +515,13 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
     if (!(o->tol_picard > 0) || !(o->tol_cg > 0) || o->max_picard < 1 || o->max_cg < 1 ||
         !(o->chord_eps >= 0) || (o->precond != RF_PRECOND_JACOBI && o->precond != RF_PRECOND_ZLINE) ||
         o->check_every < 1 || !(o->dt0 > 0) || !(o->dt_max > 0) || !(o->dt_min > 0) ||
-        o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0))
+        o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0) ||
+        o->cols_per_wave < 0)
         return fail(c, RF_ERR_ARG, "invalid options");
     c->opt = *o;
     c->dt_cur = o->dt0;
     c->easy = 0;
+    if (c->have_grid) set_shapes(c);
     return RF_OK;
 }
 
@@ -505,7 +581,6 @@ rf_status rf_set_state(rf_ctx *c, const double *h_dev, double t)
     c->t = t;
     c->dt_cur = c->opt.dt0;
     c->easy = 0;
-    c->last_cg = c->opt.check_every;
     c->have_state = true;
     return RF_OK;
 }
@@ -525,40 +600,61 @@ rf_status rf_get_state(const rf_ctx *cc, double *h_dev, double *t)
     return RF_OK;
 }
 
-// One Picard iteration's PCG solve: enqueue PCG iterations in chunks (the
-// first sized by the previous solve) until the device reports that the
-// Picard update hnew = h^m + e has been written, or a failure.  Leaves
-// c->hsc current.
-static rf_status pcg_solve(rf_ctx *c)
+// Enqueues n more PCG iterations of Picard iteration m (the direction
+// buffers alternate with the iteration count).
+static rf_status enqueue_pairs(rf_ctx *c, int m, int n)
 {
-    const Geo &G = c->G;
     Arrays &A = c->A;
     const int pc = c->opt.precond;
-    double *pin = A.p0, *pout = A.p1;
-    int chunk = std::max(1, c->last_cg);
-    int launched = 0;
-    for (;;) {
-        for (int i = 0; i < chunk; i++) {
-            TIMED(c, K_SPMV, launched, launch_spmv(G, A, pc, pin, pout, c->opt.tol_cg, c->opt.max_cg,
-                                                   c->stream));
-            TIMED(c, K_UPDATE, launched, launch_update(G, A, pc, pout, c->stream));
-            std::swap(pin, pout);
-            launched++;
-        }
-        TIMED(c, K_APPLYH, -1, launch_apply_h(G, A, c->opt.tol_cg, c->opt.max_cg, c->stream));
-        rf_status s = sync_scalars(c);
-        if (s) return s;
-        if (c->hsc->applied || c->hsc->fail) {
-            timed_collect(c, c->hsc->final_iters);
-            break;
-        }
-        timed_collect(c, launched);
-        chunk = std::max(1, std::min(c->opt.check_every, c->last_cg / 2 + 1));
+    const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
+    for (int i = 0; i < n; i++) {
+        const int j = c->pairs_enq[mi]++;
+        double *pin = (j & 1) ? A.p1 : A.p0;
+        double *pout = (j & 1) ? A.p0 : A.p1;
+        TIMED(c, K_SPMV, m, j, launch_spmv(c->G, A, pc, pin, pout, c->opt.tol_cg, c->opt.max_cg,
+                                           c->stream));
+        TIMED(c, K_UPDATE, m, j, launch_update(c->G, A, pc, pout, c->stream));
     }
-    c->last_cg = std::max(1, c->hsc->final_iters);
     return RF_OK;
 }
 
+static rf_status enqueue_apply(rf_ctx *c, int m)
+{
+    const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
+    TIMED(c, K_APPLYH, m, c->apply_enq[mi]++,
+          launch_apply_h(c->G, c->A, m, c->opt.tol_cg, c->opt.max_cg, c->stream));
+    return RF_OK;
+}
+
+// Picard iteration m: exit test of iteration m-1, coefficients, residual,
+// a predicted number of PCG iterations, Picard update.  Every kernel returns
+// at once when an earlier one has ended the step.
+static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
+{
+    const Geo &G = c->G;
+    Arrays &A = c->A;
+    const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
+    if (m > 0) TIMED(c, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
+    TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps, c->stream));
+    TIMED(c, K_RESID, m, -1, launch_resid(G, A, c->opt.precond, m, nullptr, c->stream));
+    rf_status s = enqueue_pairs(c, m, std::max(1, c->pred_cg[mi]));
+    if (s) return s;
+    return enqueue_apply(c, m);
+}
+
+static rf_status enqueue_accept(rf_ctx *c, const Bc &bc, int M, int &naccept)
+{
+    TIMED(c, K_DECIDE, M, -1, launch_decide(c->G, c->A, M, c->opt.tol_picard, c->stream));
+    TIMED(c, K_ACCEPT, M, naccept, launch_accept(c->G, c->S, c->A, c->stream));
+    naccept++;
+    return RF_OK;
+}
+
+// One backward-Euler step.  The whole Picard loop is enqueued speculatively
+// (as many iterations and PCG iterations as the previous step needed); the
+// device decides, after every update, whether to go on, and the host waits
+// once.  If the guess fell short (a PCG solve not finished, or the Picard
+// test not yet met), the host enqueues more from where the device stopped.
 static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_picard,
                              rf_step_stats *st)
 {
@@ -567,52 +663,86 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     st->t = c->t;
     const Geo &G = c->G;
     Arrays &A = c->A;
-    const size_t N = (size_t)c->nx * c->ny * c->nz;
     const Bc bc = bc_at(c, c->t);
-    HIPCHK(c, hipMemcpyAsync(A.hm, guess ? guess : A.hn, N * sizeof(double),
-                             hipMemcpyDeviceToDevice, c->stream));
-    rf_status status = RF_ERR_NOT_CONVERGED;
-    for (int m = 0; m < max_picard; m++) {
-        TIMED(c, K_COEFF, -1, launch_coeff(G, c->S, bc, A, dt, c->opt.chord_eps, c->stream));
-        TIMED(c, K_RESID, -1, launch_resid(G, A, c->opt.precond, nullptr, c->stream));
-        rf_status s = pcg_solve(c);
+    for (int m = 0; m < RF_MAX_PICARD_LOG; m++) c->pairs_enq[m] = c->apply_enq[m] = 0;
+    int naccept = 0;
+    TIMED(c, K_BEGIN, -1, -1, launch_step_begin(G, c->S, bc, A, guess ? guess : A.hn, c->stream));
+    int M = std::max(1, std::min(max_picard, c->pred_picard));
+    for (int m = 0; m < M; m++) {
+        rf_status s = enqueue_iteration(c, bc, dt, m);
         if (s) return s;
-        const Scalars h = *c->hsc;
-        st->picard_iters = m + 1;
-        st->cg_iters_total += h.final_iters;
-        if (m < RF_MAX_PICARD_LOG) st->cg_iters[m] = h.final_iters;
+    }
+    rf_status s = enqueue_accept(c, bc, M, naccept);
+    if (s) return s;
+    rf_status status = RF_OK;
+    for (;;) {
+        s = sync_scalars(c);
+        if (s) return s;
+        const Scalars &h = *c->hsc;
+        if (h.accepted) break;
         if (h.fail) {
             status = (h.fail == 3) ? RF_ERR_NONFINITE : RF_ERR_LINEAR;
-            fail(c, status, "PCG %s in Picard iteration %d after %d iterations",
-                 h.fail == 1 ? "breakdown" : h.fail == 2 ? "hit max_cg" : "produced NaN/Inf", m,
-                 h.final_iters);
             break;
         }
-        double dd[2];
-        s = host_reduce(c, A.pd, 2, 1u, dd);
+        if (h.stall) {
+            // PCG of iteration ms needs more iterations than were enqueued
+            const int ms = h.stall_m;
+            HIPCHK(c, hipMemsetAsync(&A.sc->stall, 0, sizeof(int), c->stream));
+            s = enqueue_pairs(c, ms, std::max(1, c->opt.check_every / 2));
+            if (s) return s;
+            s = enqueue_apply(c, ms);
+            if (s) return s;
+            for (int m = ms + 1; m < M; m++) {
+                s = enqueue_iteration(c, bc, dt, m);
+                if (s) return s;
+            }
+            s = enqueue_accept(c, bc, M, naccept);
+            if (s) return s;
+            continue;
+        }
+        if (M >= max_picard) {
+            status = RF_ERR_NOT_CONVERGED;
+            break;
+        }
+        const int M2 = std::min(max_picard, M + std::max(1, M / 2));
+        for (int m = M; m < M2; m++) {
+            s = enqueue_iteration(c, bc, dt, m);
+            if (s) return s;
+        }
+        M = M2;
+        s = enqueue_accept(c, bc, M, naccept);
         if (s) return s;
-        if (m < RF_MAX_PICARD_LOG) st->delta[m] = dd[0];
-        std::swap(A.hm, A.hnew);      // h^{m+1} becomes the current iterate
-        if (dd[1] != 0.0 || !std::isfinite(dd[0])) {
-            status = fail(c, RF_ERR_NONFINITE, "non-finite Picard iterate");
-            break;
-        }
-        if (dd[0] < c->opt.tol_picard) {
-            status = RF_OK;
-            break;
-        }
     }
-    if (status == RF_ERR_NOT_CONVERGED)
-        fail(c, status, "Picard did not converge in %d iterations (dt %g)", max_picard, dt);
+    const Scalars h = *c->hsc;
+    const int last_m = h.accepted ? h.accept_m : (status == RF_ERR_NOT_CONVERGED ? M - 1 : h.cur_m);
+    st->picard_iters = last_m + 1;
+    for (int m = 0; m <= last_m && m < RF_MAX_PICARD_LOG; m++) {
+        const bool solved = m < last_m || h.accepted || status == RF_ERR_NOT_CONVERGED;
+        st->cg_iters[m] = solved ? h.cg_log[m] : h.final_iters;
+        st->delta[m] = solved ? h.delta_log[m] : 0.0;
+        st->cg_iters_total += st->cg_iters[m];
+    }
+    int cgl[RF_MAX_PICARD_LOG], napp[RF_MAX_PICARD_LOG];
+    for (int m = 0; m < RF_MAX_PICARD_LOG; m++) {
+        cgl[m] = (m <= last_m) ? st->cg_iters[m] : 0;
+        napp[m] = c->apply_enq[m];
+    }
+    timed_collect(c, last_m, cgl, napp, h.accepted ? naccept : -1);
     if (status != RF_OK) {
-        timed_collect(c, 0);
+        if (status == RF_ERR_NOT_CONVERGED)
+            fail(c, status, "Picard did not converge in %d iterations (dt %g)", max_picard, dt);
+        else
+            fail(c, status, "PCG %s in Picard iteration %d after %d iterations",
+                 h.fail == 1 ? "breakdown" : h.fail == 2 ? "hit max_cg" : "produced NaN/Inf",
+                 h.cur_m, h.final_iters);
         return status;
     }
-    TIMED(c, K_ACCEPT, -1, launch_accept(G, c->S, bc, A, c->stream));
+    // prediction for the next step
+    c->pred_picard = last_m + 1;
+    for (int m = 0; m <= last_m && m < RF_MAX_PICARD_LOG; m++) c->pred_cg[m] = std::max(1, st->cg_iters[m]);
     double sums[7];
-    rf_status s = host_reduce(c, A.ps, 7, 0u, sums);
+    s = host_reduce(c, A.ps, 7, 0u, sums);
     if (s) return s;
-    timed_collect(c, 0);
     c->storage = sums[0];
     for (int f = 0; f < 6; f++) c->inflow[f] += dt * sums[1 + f];
     c->t += dt;
@@ -715,9 +845,10 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     if (!(dt > 0)) return fail(c, RF_ERR_ARG, "invalid dt");
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     const Bc bc = bc_at(c, c->t);
-    HIPCHK(c, hipMemcpyAsync(c->A.hm, hm_dev, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_coeff(c->G, c->S, bc, c->A, dt, c->opt.chord_eps, c->stream));
-    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, rhs_dev, c->stream));
+    (void)N;
+    HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, c->stream));
+    HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->stream));
+    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, c->stream));
     if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->assembled = true;
@@ -742,12 +873,12 @@ rf_status rf_apply_precond(rf_ctx *c, const double *r_dev, double *z_dev)
     return RF_OK;
 }
 
-rf_status rf_set_timing(rf_ctx *c, int on)
+rf_status rf_set_timing(rf_ctx *c, int mask)
 {
     if (!c) return RF_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    timed_collect(c, 0);
-    c->timing = on != 0;
+    timed_drop(c);
+    c->timing = mask & 0xff;
     const long cells = c->active;
     memset(&c->tm, 0, sizeof(c->tm));
     for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
@@ -759,7 +890,6 @@ rf_status rf_get_timing(rf_ctx *c, rf_timing *out)
 {
     if (!c || !out) return RF_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    timed_collect(c, 0);
     *out = c->tm;
     return RF_OK;
 }

@@ -13,7 +13,7 @@ namespace rf {
 constexpr int kWave = 64;           // CDNA wavefront
 constexpr int kWavesPerBlock = 8;   // one column per wave at a time
 constexpr int kThreads = kWave * kWavesPerBlock;
-constexpr int kMaxBlocks = 512;     // 2 per CU on 256 CUs; one partial per thread when combined
+constexpr int kPartialsMax = 512;   // partials every block of a consumer kernel may combine
 constexpr int kRedSlots = 8;        // values per block partial
 
 // Per-layer van Genuchten parameters (Ks is per cell).
@@ -27,11 +27,18 @@ struct Soil {
     Layer L[RF_MAX_LAYERS];
 };
 
-// Geometry and launch shape of one grid.
+// Geometry and launch shapes of one grid.  Kernels that write block
+// partials use nblk blocks of cpb columns; when nblk exceeds kPartialsMax a
+// one-block fold kernel combines the partials first, so that every block of
+// the consumer combines np <= kPartialsMax values.  Kernels without a
+// reduction use nblk_w blocks of cpb_w columns (one column per wave).
 struct Geo {
     int nx, ny, nz, ncol;
-    int nblk;               // blocks launched (multiple of 8 when >= 8)
-    int cpb;                // columns per logical block
+    int nblk, cpb;          // kernels that write block partials
+    int np;                 // partials a consumer combines: nblk, or 1 after a fold kernel
+    int foff;               // where they start, in values of nv: 0, or nblk (the fold output)
+    int nblk_w, cpb_w;
+    int block_map;          // 0 identity, 1 one slab per XCD, 2 slabs entered at staggered points
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z
     double Tk[3];           // A / distance between centres, per unit K
@@ -44,11 +51,13 @@ struct Bc {
     double value[6];        // Dirichlet head or flux (already resolved at time t)
 };
 
-// Scalars kept on the device between kernels of the PCG loop.  Every field
-// is written by thread 0 of block 0 only, and never read by the other blocks
-// of the kernel that writes it (results reach them at the next kernel
-// boundary), so no inter-block fence or atomic is needed.
+// Scalars kept on the device across the kernels of one time step.  Every
+// field is written by thread 0 of block 0 only, and never read back by the
+// other blocks of the kernel that writes it except where all blocks take the
+// same decision anyway, so no inter-block fence or atomic is needed: values
+// reach other blocks at the next kernel boundary.
 struct Scalars {
+    // PCG of the current Picard iteration
     double rho[2];    // r.z of iteration j kept in slot j & 1
     double resmax;    // max |r / diag| seen by the last direction update
     double pq;
@@ -56,49 +65,71 @@ struct Scalars {
     int jcur;         // index of the direction update in flight (spmv kernel)
     int done;         // PCG finished (converged, hit max_cg or failed)
     int fail;         // 1 breakdown (p.q <= 0), 2 max_cg reached, 3 non-finite
-    int applied;      // Picard update h^{m+1} = h^m + e written
     int final_iters;  // PCG iterations of the finished solve
+    // Picard control of the step
+    int stall;        // PCG of iteration stall_m not finished within the enqueued chunk
+    int stall_m;
+    int picard_done;  // an update met tol_picard (decided by the next coefficient kernel)
+    int picard_m;     // Picard iteration whose update met tol_picard
+    int accepted;     // the step was accepted
+    int accept_m;
+    int cur_m;        // Picard iteration whose residual was formed last
     int pad[2];
+    int cg_log[RF_MAX_PICARD_LOG];       // PCG iterations of each Picard iteration
+    double delta_log[RF_MAX_PICARD_LOG]; // max |h^{m+1} - h^m| of each Picard iteration
 };
 
-// Device arrays inside the bound workspace.
+// Device arrays inside the bound workspace.  The Picard iterate h^m lives in
+// hb[m & 1]; iteration m writes h^{m+1} into hb[(m + 1) & 1].
 struct Arrays {
-    double *hn, *thn, *hm, *hnew, *K, *Dd, *bst, *diag, *r, *p0, *p1, *q, *e, *z, *Ks;
+    double *hn, *thn, *hb0, *hb1, *K, *Dd, *bst, *diag, *r, *p0, *p1, *q, *e, *z, *Ks;
     double *tz;               // z-line: coupling of cell k with k+1 (A_z K_f / dz)
     double *rdp;              // z-line: reciprocal pivots
     uint8_t *layer;           // may be null
     int32_t *ktop;
-    double *pr;               // block partials of (r.z, max|r/diag|)      [kMaxBlocks * 2]
-    double *pq;               // block partials of p.q                     [kMaxBlocks]
-    double *pd;               // block partials of (max|e|, non-finite)     [kMaxBlocks * 2]
-    double *ps;               // block partials of host-side sums           [kMaxBlocks * kRedSlots]
+    double *pr;               // block partials of (r.z, max|r/diag|)  [(nblk + 1) * 2]
+    double *pq;               // block partials of p.q                 [nblk + 1]
+    double *pd;               // block partials of (max|e|, non-finite) [(nblk + 1) * 2]
+    double *ps;               // block partials of host-side sums       [(nblk + 1) * kRedSlots]
     double *ks_layer;         // Ks of each layer                           [RF_MAX_LAYERS]
+    double *krb;              // K(h_b)/Ks of each Dirichlet face and layer [6 * RF_MAX_LAYERS]
+    Layer *layers;            // van Genuchten parameters of each layer     [RF_MAX_LAYERS]
+    double *bt;               // boundary coefficients of each face          [6 * 4]
     Scalars *sc;
 };
 
 // Kernel identifiers for timing.
-enum KernelId { K_COEFF = 0, K_RESID, K_SPMV, K_UPDATE, K_APPLYH, K_ACCEPT, K_MISC, K_COUNT };
+enum KernelId { K_COEFF = 0, K_RESID, K_SPMV, K_UPDATE, K_APPLYH, K_ACCEPT, K_DECIDE, K_BEGIN };
 
 // Launchers (rf_kernels.hip).  All enqueue on `s` and return the launch status.
 hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s);
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s);
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             hipStream_t s);
-hipError_t launch_coeff(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a, double dt,
+hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
+                             const double *h0, hipStream_t s);
+hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s);
+hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, hipStream_t s);
-hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, double *bout, hipStream_t s);
+hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
+                        hipStream_t s);
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, const double *p_in,
                        double *p_out, double tol_cg, int max_cg, hipStream_t s);
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, const double *p, hipStream_t s);
-hipError_t launch_apply_h(const Geo &g, const Arrays &a, double tol_cg, int max_cg, hipStream_t s);
-hipError_t launch_accept(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                         hipStream_t s);
+hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, double tol_cg, int max_cg,
+                          hipStream_t s);
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s);
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             double *theta, double *C, double *K, hipStream_t s);
 hipError_t launch_operator(const Geo &g, const Arrays &a, const double *x, double *y,
                            hipStream_t s);
 hipError_t launch_precond(const Geo &g, const Arrays &a, int precond, const double *r, double *z,
                           hipStream_t s);
+// Folds nblk partials of nv values (max where bit i of maxmask is set) into
+// the slot after them, P[nblk*nv ..], when g.np == 1; no-op otherwise.  The
+// fold reads only block partials, so folding again after a producer that
+// returned early gives the same total.
+hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s);
 hipError_t launch_copy_active(const Geo &g, const Arrays &a, const double *src, double *dst,
                               hipStream_t s);
 

@@ -13,7 +13,8 @@
 //
 // Global reductions are two-stage, deterministic and fence-free: every block
 // writes one partial per value, and the consumer -- every block of the next
-// kernel, or the host -- combines the (at most 512) partials in block order.
+// kernel, or the host -- combines the partials in block order (large grids
+// first fold them with a one-block kernel).
 // Cross-block visibility therefore only ever relies on kernel boundaries: an
 // agent-scope fence per block would write back the whole L2 of its XCD, and a
 // single ticket counter would serialise every block of the grid.  Scalars
@@ -29,12 +30,24 @@ namespace rf {
 // small helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void block_columns(const Geo &g, int &cb, int &ce)
+// Columns [cb, ce) of this block: logical block lb takes cpb consecutive
+// columns.  The hardware deals workgroups round-robin over the 8 XCDs
+// (block b runs on XCD b % 8); map 1 undoes that so each XCD works through
+// one contiguous slab (lateral neighbours stay in one L2), and map 2 also
+// starts each XCD at a different point of its slab, so that the eight
+// streams are not a power-of-two stride apart at every instant.
+__device__ __forceinline__ void block_columns(const Geo &g, int cpb, int &cb, int &ce)
 {
     const int b = blockIdx.x, G = gridDim.x;
-    const int lb = (G >= 8 && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
-    cb = lb * g.cpb;
-    ce = min(cb + g.cpb, g.ncol);
+    int lb = b;
+    if (g.block_map != 0 && G >= 8 && (G & 7) == 0) {
+        const int per = G >> 3, x = b & 7;
+        int r = b >> 3;
+        if (g.block_map == 2) r = (r + (x * per) / 8) % per;
+        lb = x * per + r;
+    }
+    cb = lb * cpb;
+    ce = min(cb + cpb, g.ncol);
 }
 
 __device__ __forceinline__ double wave_sum(double x)
@@ -106,7 +119,85 @@ __device__ __forceinline__ void reduce_partials(const double *P, int nblk, doubl
     }
 }
 
+// Columns of one wave processed together in the short-column paths (columns
+// of at most 64 cells), so that their loads are in flight at the same time:
+// every kernel there first gathers all values of the group with branch-free
+// loads, then computes.  Lanes without a cell read their own column's first
+// cell (no extra cache lines) and are masked at the stores.
+constexpr int kColGroup = 4;
+
+struct ColSlot {
+    int col;      // column (clamped into the block's range)
+    int kt;       // active cells (0 if the slot is past the block's columns)
+    bool act;     // this lane holds an active cell
+    size_t base;  // first cell of the column
+    size_t i;     // this lane's cell (base when inactive)
+};
+
+__device__ __forceinline__ ColSlot col_slot(const Geo &g, const int32_t *ktop, int col, int ce,
+                                            int lane)
+{
+    ColSlot c;
+    const bool valid = col < ce;
+    c.col = valid ? col : ce - 1;
+    const int kt = ktop[c.col];
+    c.kt = valid ? kt : 0;
+    c.act = lane < c.kt;
+    c.base = (size_t)c.col * g.nz;
+    c.i = c.base + (c.act ? lane : 0);
+    return c;
+}
+
+// Lateral neighbours (0 -x, 1 +x, 2 -y, 3 +y) of a slot: whether the
+// neighbour cell is active, and its index (this cell's index otherwise).
+__device__ __forceinline__ void lateral(const Geo &g, const int32_t *ktop, const ColSlot &c,
+                                        int lane, bool (&nb)[4], size_t (&in)[4])
+{
+    const int i = c.col % g.nx, j = c.col / g.nx;
+    const size_t sx = (size_t)g.nz, sy = (size_t)g.nz * g.nx;
+    const int cn[4] = {i > 0 ? c.col - 1 : c.col, i < g.nx - 1 ? c.col + 1 : c.col,
+                       j > 0 ? c.col - g.nx : c.col, j < g.ny - 1 ? c.col + g.nx : c.col};
+    const bool has[4] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1};
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        nb[d] = c.act && has[d] && lane < ktop[cn[d]];
+        const size_t off = (d < 2) ? sx : sy;
+        in[d] = nb[d] ? ((d & 1) ? c.i + off : c.i - off) : c.i;
+    }
+}
+
 __device__ __forceinline__ bool lead_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Boundary terms of a cell with face f on the domain boundary, in terms of
+// the face conductivity Kb = Ks * krb[f][layer] and the cell's K (Sec. 3.1,
+// 3.2, App. A, App. B):  diagonal += cD Kb;  right-hand side += cKb Kb +
+// cK K + c0, where Dirichlet h_b gives cD = 2 A/d (half-cell distance),
+// cKb = cD h_b + A g.n; flux q gives c0 = A q; free drainage gives cK = A g.n;
+// no-flow gives nothing.  The inflow through the face at head h is
+// (cKb - cD h) Kb + cK K + c0.
+struct FaceTab {
+    double cD, cKb, cK, c0;
+};
+
+// Stages the face table and the Dirichlet relative conductivities in LDS.
+__device__ __forceinline__ void stage_bc(const Arrays &a, FaceTab *sBT, double *sKR)
+{
+    const double *src = a.bt;
+    double *d = reinterpret_cast<double *>(sBT);
+    for (int i = threadIdx.x; i < 24; i += kThreads) d[i] = src[i];
+    for (int i = threadIdx.x; i < 6 * RF_MAX_LAYERS; i += kThreads) sKR[i] = a.krb[i];
+}
+
+// Copies the layer table into LDS (cells index it with their own layer, so
+// it must not stay in kernel arguments, which live in scalar registers).
+// Call from every thread of the block.
+__device__ __forceinline__ void stage_layers(const Arrays &a, int nlayer, Layer *sL)
+{
+    double *d = reinterpret_cast<double *>(sL);
+    const double *src = reinterpret_cast<const double *>(a.layers);
+    for (int i = threadIdx.x; i < nlayer * 6; i += kThreads) d[i] = src[i];
+    __syncthreads();
+}
 
 // van Genuchten-Mualem theta~ (Eq. 2 plus S*h above saturation), capacity
 // C (Eq. 3) and conductivity K (Eq. 4), or Gardner's exponential forms.
@@ -199,24 +290,28 @@ __device__ __forceinline__ double gdot(const Geo &g, int d)
 // set-up kernels
 // ---------------------------------------------------------------------------
 
+#define RF_WAVE_IDS                                                     \
+    const int lane = threadIdx.x & (kWave - 1);                         \
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave)
+
 // Ks per cell = Ks(layer) * exp(ln_ks_offset); Ks holds the offsets on entry
 // (zeros when none were given).
-__global__ void __launch_bounds__(kThreads) k_init_ks(Geo g, Soil so, Arrays a, const double *ks_layer)
+__global__ void __launch_bounds__(kThreads) k_init_ks(Geo g, Arrays a)
 {
     const size_t N = (size_t)g.ncol * g.nz;
     for (size_t c = (size_t)blockIdx.x * kThreads + threadIdx.x; c < N;
          c += (size_t)gridDim.x * kThreads) {
         const int l = a.layer ? a.layer[c] : 0;
-        a.Ks[c] = ks_layer[l] * exp(a.Ks[c]);
+        a.Ks[c] = a.ks_layer[l] * exp(a.Ks[c]);
     }
 }
 
-// Counts non-finite active values of h (sums[0]).
+// Block partials (ps) of the number of non-finite active values of h.
 __global__ void __launch_bounds__(kThreads) k_check_finite(Geo g, Arrays a, const double *h)
 {
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[1] = {0.0};
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
@@ -228,12 +323,15 @@ __global__ void __launch_bounds__(kThreads) k_check_finite(Geo g, Arrays a, cons
     block_partial<1, 0u>(v, a.ps);
 }
 
-// h^n <- h, theta~^n <- theta~(h), storage (sums[0]).
+// h^n <- h (every cell), theta~^n <- theta~(h) and block partials of the
+// storage sum V theta~ (active cells).
 __global__ void __launch_bounds__(kThreads) k_set_state(Geo g, Soil so, Arrays a, const double *h)
 {
+    __shared__ Layer sL[RF_MAX_LAYERS];
+    stage_layers(a, so.nlayer, sL);
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[1] = {0.0};
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
@@ -244,7 +342,7 @@ __global__ void __launch_bounds__(kThreads) k_set_state(Geo g, Soil so, Arrays a
             const double hv = h[idx];
             a.hn[idx] = hv;
             if (k < kt) {
-                const Layer &L = so.L[a.layer ? a.layer[idx] : 0];
+                const Layer &L = sL[a.layer ? a.layer[idx] : 0];
                 const double th = soil_theta(so.model, hv, L);
                 a.thn[idx] = th;
                 v[0] += g.V * th;
@@ -255,21 +353,111 @@ __global__ void __launch_bounds__(kThreads) k_set_state(Geo g, Soil so, Arrays a
 }
 
 // ---------------------------------------------------------------------------
-// Picard iteration: coefficients (row a1 of the loop) and boundary terms
+// Step control
 // ---------------------------------------------------------------------------
 
-// Per active cell: K = K(h^m); chord capacity C = (theta~(h^m) -
+// First Picard iterate h^0 = h0 (h^n or a caller's guess) into hb[0]; resets
+// the step flags; block 0 tabulates the relative conductivity K(h_b)/Ks of
+// every Dirichlet face for every layer (the face conductivity of a cell is
+// its own Ks times that entry).
+__global__ void __launch_bounds__(kThreads) k_step_begin(Geo g, Soil so, Bc bc, Arrays a,
+                                                         const double *h0)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 6 * RF_MAX_LAYERS) {
+        const int f = threadIdx.x / RF_MAX_LAYERS, l = threadIdx.x % RF_MAX_LAYERS;
+        double kr = 0.0;
+        if (bc.type[f] == RF_DIRICHLET && l < so.nlayer)
+            kr = soil_K(so.model, bc.value[f], a.layers[l], 1.0);
+        a.krb[threadIdx.x] = kr;
+        if (threadIdx.x < 6) {
+            const int ff = threadIdx.x, ax = ff >> 1;
+            const double gn = ((ff & 1) ? 1.0 : -1.0) * g.g[ax];
+            const double Tb = 2.0 * g.Tk[ax];
+            double cD = 0.0, cKb = 0.0, cK = 0.0, c0 = 0.0;
+            if (bc.type[ff] == RF_DIRICHLET) {
+                cD = Tb;
+                cKb = Tb * bc.value[ff] + g.A[ax] * gn;
+            } else if (bc.type[ff] == RF_FLUX) {
+                c0 = g.A[ax] * bc.value[ff];
+            } else if (bc.type[ff] == RF_FREE_DRAINAGE) {
+                cK = g.A[ax] * gn;
+            }
+            a.bt[4 * ff + 0] = cD;
+            a.bt[4 * ff + 1] = cKb;
+            a.bt[4 * ff + 2] = cK;
+            a.bt[4 * ff + 3] = c0;
+        }
+    }
+    int cb, ce;
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
+    for (int col = cb + w; col < ce; col += kWavesPerBlock) {
+        const int kt = a.ktop[col];
+        for (int k0 = 0; k0 < kt; k0 += kWave) {
+            const int k = k0 + lane;
+            if (k < kt) a.hb0[(size_t)col * g.nz + k] = h0[(size_t)col * g.nz + k];
+        }
+    }
+    if (lead_thread()) {
+        Scalars *s = a.sc;
+        s->done = 0;
+        s->fail = 0;
+        s->iters = 0;
+        s->final_iters = 0;
+        s->stall = 0;
+        s->stall_m = 0;
+        s->picard_done = 0;
+        s->picard_m = 0;
+        s->accepted = 0;
+        s->accept_m = 0;
+    }
+}
+
+// Global Picard exit test (Sec. 2.3) of the update written by iteration m-1:
+// one block combines the (max|e|, non-finite) partials; converged when
+// max |h^m - h^{m-1}| < tol_picard.
+__global__ void __launch_bounds__(kThreads) k_decide(Geo g, Arrays a, int m, double tol_picard)
+{
+    Scalars *s = a.sc;
+    if (s->fail || s->stall || s->picard_done) return;
+    double tot[2];
+    reduce_partials<2, 1u>(a.pd + 2 * g.foff, g.np, tot);
+    if (threadIdx.x == 0) {
+        if (m - 1 < RF_MAX_PICARD_LOG) s->delta_log[m - 1] = tot[0];
+        if (tot[1] > 0.0 || !isfinite(tot[0])) {
+            s->fail = 3;
+            s->done = 1;
+        } else if (tot[0] < tol_picard) {
+            s->picard_done = 1;
+            s->picard_m = m - 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Picard iteration: coefficients and boundary terms
+// ---------------------------------------------------------------------------
+
+// Per active cell of h^m: K = K(h^m); chord capacity C = (theta~(h^m) -
 // theta~(h^n)) / (h^m - h^n), or Eq. 3 when |h^m - h^n| < chord_eps;
-// Dd = V C / dt + sum of Dirichlet transmissibilities; bst = V C h^n / dt +
-// every boundary term of the cell (Dirichlet T h_b + A K(h_b) g.n, flux A q,
-// free drainage A K(h^m) g.n).  Interior-face terms are added in k_resid.
-__global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Bc bc, Arrays a, double dt,
+// Dd = V C / dt + the boundary diagonal terms; bst = V C h^n / dt + the
+// boundary right-hand-side terms (see FaceTab).  Interior-face terms are
+// added in k_resid.
+__global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
                                                     double chord_eps)
 {
+    Scalars *s = a.sc;
+    if (s->fail || s->stall || s->picard_done) return;
+    __shared__ Layer sL[RF_MAX_LAYERS];
+    __shared__ FaceTab sBT[6];
+    __shared__ double sKR[6 * RF_MAX_LAYERS];
+    stage_bc(a, sBT, sKR);
+    stage_layers(a, so.nlayer, sL);
+    const double *hmv = (m & 1) ? a.hb1 : a.hb0;
+    const double vdt = g.V / dt;
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const double dist[3] = {g.A[0] / g.Tk[0], g.A[1] / g.Tk[1], g.A[2] / g.Tk[2]};
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -278,33 +466,21 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Bc bc, Array
             Cell c;
             cell_setup(g, a.ktop, col, kt, k, c);
             const size_t idx = c.idx;
-            const Layer &L = so.L[a.layer ? a.layer[idx] : 0];
+            const int lay = a.layer ? a.layer[idx] : 0;
             const double ks = a.Ks[idx];
-            const double hm = a.hm[idx], hn = a.hn[idx];
+            const double hm = hmv[idx], hn = a.hn[idx];
             double th, C, K;
-            soil_eval(so.model, hm, L, ks, th, C, K);
+            soil_eval(so.model, hm, sL[lay], ks, th, C, K);
             const double dh = hm - hn;
             const double Cc = (fabs(dh) >= chord_eps) ? (th - a.thn[idx]) / dh : C;
-            double D = g.V * Cc / dt;
+            double D = vdt * Cc;
             double b = D * hn;
 #pragma unroll
             for (int d = 0; d < 6; d++) {
                 if (!c.bnd[d]) continue;
-                const int f = d;                  // direction d crosses face d
-                const int ax = d >> 1;
-                const double gn = gdot(g, d);
-                const int type = bc.type[f];
-                if (type == RF_DIRICHLET) {
-                    const double hb = bc.value[f];
-                    const double Kb = soil_K(so.model, hb, L, ks);
-                    const double T = g.A[ax] * Kb / (0.5 * dist[ax]);
-                    D += T;
-                    b += T * hb + g.A[ax] * Kb * gn;
-                } else if (type == RF_FLUX) {
-                    b += g.A[ax] * bc.value[f];
-                } else if (type == RF_FREE_DRAINAGE) {
-                    b += g.A[ax] * K * gn;
-                }
+                const double Kb = ks * sKR[d * RF_MAX_LAYERS + lay];
+                D += sBT[d].cD * Kb;
+                b += sBT[d].cKb * Kb + sBT[d].cK * K + sBT[d].c0;
             }
             a.K[idx] = K;
             a.Dd[idx] = D;
@@ -355,7 +531,6 @@ __device__ __forceinline__ double scan_affine_down(double b, double c, double ca
 // d_{k0-1} (0 for the first chunk).  Returns d_k.
 __device__ __forceinline__ double scan_pivots(double diag, double tprev2, double carry, int lane)
 {
-    // M = [[m00, m01], [m10, m11]] = [[diag, -tprev2], [1, 0]]
     double m00 = diag, m01 = -tprev2, m10 = 1.0, m11 = 0.0;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -368,27 +543,25 @@ __device__ __forceinline__ double scan_pivots(double diag, double tprev2, double
             const double n01 = m00 * o01 + m01 * o11;
             const double n10 = m10 * o00 + m11 * o10;
             const double n11 = m10 * o01 + m11 * o11;
-            const double s = fmax(fmax(fabs(n00), fabs(n01)), fmax(fabs(n10), fabs(n11)));
-            const double rs = (s > 0.0) ? 1.0 / s : 1.0;
-            m00 = n00 * rs; m01 = n01 * rs; m10 = n10 * rs; m11 = n11 * rs;
+            // rescale by a power of two (exact) to keep the product in range
+            const double sc = fmax(fmax(fabs(n00), fabs(n01)), fmax(fabs(n10), fabs(n11)));
+            const int ex = (sc > 0.0) ? ilogb(sc) : 0;
+            m00 = ldexp(n00, -ex); m01 = ldexp(n01, -ex); m10 = ldexp(n10, -ex); m11 = ldexp(n11, -ex);
         }
     }
-    // start vector (P_{k0-1}, P_{k0-2}) ~ (carry, 1), or (1, 0) on the first chunk
     const double v0 = (carry != 0.0) ? carry : 1.0;
     const double v1 = (carry != 0.0) ? 1.0 : 0.0;
     return (m00 * v0 + m01 * v1) / (m10 * v0 + m11 * v1);
 }
 
-// z = M^-1 r for one column with reciprocal pivots rdp and couplings t
-// (t_k couples k and k+1, zero at the top active cell).  Columns of up to 64
-// cells stay in registers; longer columns keep the forward sweep in z.
-template <bool ONE_CHUNK>
-__device__ __forceinline__ void zline_solve_column(const double *r, const double *rdp,
-                                                   const double *tz, double *zout, size_t base,
-                                                   int kt, int lane, double &z_reg)
+// z = M^-1 r for a column longer than one wave, from memory: forward sweep
+// w_k = (r_k + t_{k-1} w_{k-1}) rdp_k into zout, backward sweep
+// z_k = w_k + t_k rdp_k z_{k+1}.  Every lane re-reads only what it wrote.
+__device__ __forceinline__ void zline_solve_long(const double *r, const double *rdp,
+                                                 const double *tz, double *zout, size_t base,
+                                                 int kt, int lane)
 {
-    // forward: w_k = (r_k + t_{k-1} w_{k-1}) rdp_k
-    double carry = 0.0, wlast = 0.0;
+    double carry = 0.0;
     for (int k0 = 0; k0 < kt; k0 += kWave) {
         const int k = k0 + lane;
         const bool act = k < kt;
@@ -397,40 +570,134 @@ __device__ __forceinline__ void zline_solve_column(const double *r, const double
         const double tp = (act && k > 0) ? tz[base + k - 1] : 0.0;
         const double wk = scan_affine_up(tp * rd, rk * rd, carry, lane);
         carry = __shfl(wk, kWave - 1, kWave);
-        if (ONE_CHUNK) wlast = wk;
-        else if (act) zout[base + k] = wk;
+        if (act) zout[base + k] = wk;
     }
-    // backward: z_k = w_k + t_k rdp_k z_{k+1}
     carry = 0.0;
-    const int nch = (kt + kWave - 1) / kWave;
-    for (int ch = nch - 1; ch >= 0; ch--) {
+    for (int ch = (kt - 1) / kWave; ch >= 0; ch--) {
         const int k = ch * kWave + lane;
         const bool act = k < kt;
-        const double wk = ONE_CHUNK ? wlast : (act ? zout[base + k] : 0.0);
-        const double bk = (act && k + 1 < kt) ? tz[base + k] * rdp[base + k] : 0.0;
-        const double zk = scan_affine_down(bk, act ? wk : 0.0, carry, lane);
+        const double wk = act ? zout[base + k] : 0.0;
+        const double bk = act ? tz[base + k] * rdp[base + k] : 0.0;
+        const double zk = scan_affine_down(bk, wk, carry, lane);
         carry = __shfl(zk, 0, kWave);
         if (act) zout[base + k] = zk;
-        if (ONE_CHUNK) z_reg = zk;
     }
 }
 
+// The same for a column of at most 64 cells, entirely in registers: r, rdp
+// and t of lane k; returns z_k.
+__device__ __forceinline__ double zline_solve_short(double r, double rd, double t, int lane)
+{
+    double tp = __shfl_up(t, 1, kWave);
+    if (lane == 0) tp = 0.0;
+    const double wk = scan_affine_up(tp * rd, r * rd, 0.0, lane);
+    return scan_affine_down(t * rd, wk, 0.0, lane);
+}
+
 // ---------------------------------------------------------------------------
-// Residual of the Picard system and PCG start (rows a2, a3, a5)
+// Residual of the Picard system and PCG start
 // ---------------------------------------------------------------------------
 
 // Adds the interior faces: diag = Dd + sum T_f, b = bst + sum A_f K_f g.n_f
 // with K_f = (K_P + K_N)/2 and T_f = A_f K_f / d_f; r = b - A h^m (the
 // right-hand side of the increment system A e = r, e0 = 0); e = 0.
 // Jacobi: z = r / diag.  z-line: t_k (vertical couplings) and reciprocal
-// pivots of each column, z = M^-1 r.  Reduces rho = r.z and max|r/diag|.
+// pivots of each column, z = M^-1 r.  Block partials of (r.z, max|r/diag|).
 template <int PRECOND>
-__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, double *bout)
+__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, double *bout)
 {
+    Scalars *s = a.sc;
+    if (s->fail || s->stall || s->picard_done) return;
+    const double *hmv = (m & 1) ? a.hb1 : a.hb0;
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
+    if (g.nz <= kWave) {
+        // short columns: gather K and h^m at the cell and its lateral
+        // neighbours for G2 columns; vertical neighbours from adjacent lanes
+        constexpr int G2 = 2;
+        const double gz[2] = {gdot(g, 4), gdot(g, 5)};
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
+            ColSlot cs[G2];
+            bool nb[G2][4];
+            size_t in[G2][4];
+            double Kp[G2], hp[G2], Dp[G2], bp[G2], Kn[G2][4], hn[G2][4];
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+                lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const size_t i = cs[u].i;
+                Kp[u] = a.K[i];
+                hp[u] = hmv[i];
+                Dp[u] = a.Dd[i];
+                bp[u] = a.bst[i];
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    Kn[u][d] = a.K[in[u][d]];
+                    hn[u][d] = hmv[in[u][d]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const bool act = cs[u].act;
+                const int kt = cs[u].kt;
+                const size_t i = cs[u].i;
+                const double Kd = __shfl_up(Kp[u], 1, kWave), hd = __shfl_up(hp[u], 1, kWave);
+                const double Ku = __shfl_down(Kp[u], 1, kWave), hu = __shfl_down(hp[u], 1, kWave);
+                double diag = act ? Dp[u] : 1.0, Ap = Dp[u] * hp[u], b = bp[u], tup = 0.0;
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    if (!nb[u][d]) continue;
+                    const double Kf = 0.5 * (Kp[u] + Kn[u][d]);
+                    const double T = g.Tk[d >> 1] * Kf;
+                    diag += T;
+                    Ap += T * (hp[u] - hn[u][d]);
+                    b += g.A[d >> 1] * Kf * gdot(g, d);
+                }
+                if (act && lane > 0) {
+                    const double Kf = 0.5 * (Kp[u] + Kd);
+                    const double T = g.Tk[2] * Kf;
+                    diag += T;
+                    Ap += T * (hp[u] - hd);
+                    b += g.A[2] * Kf * gz[0];
+                }
+                if (act && lane + 1 < kt) {
+                    const double Kf = 0.5 * (Kp[u] + Ku);
+                    tup = g.Tk[2] * Kf;
+                    diag += tup;
+                    Ap += tup * (hp[u] - hu);
+                    b += g.A[2] * Kf * gz[1];
+                }
+                const double r = act ? b - Ap : 0.0;
+                if (act) {
+                    if (bout) bout[i] = b;
+                    a.r[i] = r;
+                    a.e[i] = 0.0;
+                    a.diag[i] = diag;
+                    v[1] = fmax(v[1], fabs(r / diag));
+                    if (PRECOND == RF_PRECOND_JACOBI) v[0] += r * (r / diag);
+                }
+                if (PRECOND == RF_PRECOND_ZLINE) {
+                    double tprev = __shfl_up(tup, 1, kWave);
+                    if (lane == 0) tprev = 0.0;
+                    const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
+                    const double rdp = act ? 1.0 / dpiv : 0.0;
+                    const double wk = scan_affine_up(tprev * rdp, r * rdp, 0.0, lane);
+                    const double zk = scan_affine_down(tup * rdp, wk, 0.0, lane);
+                    if (act) {
+                        a.tz[i] = tup;
+                        a.rdp[i] = rdp;
+                        a.z[i] = zk;
+                        v[0] += r * zk;
+                    }
+                }
+            }
+        }
+    } else
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         const size_t base = (size_t)col * g.nz;
@@ -446,7 +713,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, double *bou
             if (act) {
                 Cell c;
                 cell_setup(g, a.ktop, col, kt, k, c);
-                const double Kp = a.K[c.idx], hp = a.hm[c.idx];
+                const double Kp = a.K[c.idx], hp = hmv[c.idx];
                 diag = a.Dd[c.idx];
                 double Ap = diag * hp, b = a.bst[c.idx];
 #pragma unroll
@@ -455,7 +722,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, double *bou
                     const double Kf = 0.5 * (Kp + a.K[c.off[d]]);
                     const double T = g.Tk[d >> 1] * Kf;
                     diag += T;
-                    Ap += T * (hp - a.hm[c.off[d]]);
+                    Ap += T * (hp - hmv[c.off[d]]);
                     b += g.A[d >> 1] * Kf * gdot(g, d);
                     if (d == 5) tup = T;
                 }
@@ -513,22 +780,21 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, double *bou
     }
     block_partial<2, 2u>(v, a.pr);
     if (lead_thread()) {
-        Scalars *s = a.sc;
         s->rho[0] = 0.0;
-        s->rho[1] = 1.0;     // beta of the first direction multiplies nothing
+        s->rho[1] = 1.0;
         s->resmax = 0.0;
         s->pq = 0.0;
         s->iters = 0;
         s->jcur = 0;
         s->done = 0;
         s->fail = 0;
-        s->applied = 0;
         s->final_iters = 0;
+        s->cur_m = m;
     }
 }
 
 // ---------------------------------------------------------------------------
-// PCG iteration (row a4): kernel A = direction update + SpMV + p.q
+// PCG iteration, kernel A: exit test, direction update, SpMV, p.q
 // ---------------------------------------------------------------------------
 
 template <int PRECOND>
@@ -541,18 +807,18 @@ __device__ __forceinline__ double pnew_at(const Arrays &a, size_t i, double beta
 
 // Starts PCG iteration j = (updates done so far).  Every block combines the
 // (r.z, max|r/diag|) partials of the last update and takes the same exit
-// decision; otherwise p = z + beta p_old (z = M^-1 r) at the cell and its
-// neighbours, q = A p with A = Dd + sum_f T_f (I - shift_f) rebuilt from
-// (K, Dd); writes p, q and the block partials of p.q.
+// decision (max|r/diag| <= tol_cg); otherwise p = z + beta p_old (z = M^-1 r)
+// at the cell and its neighbours, q = A p with A = Dd + sum_f T_f (I -
+// shift_f) rebuilt from (K, Dd); writes p, q and the block partials of p.q.
 template <int PRECOND>
 __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double *p_in, double *p_out,
                                                    double tol_cg, int max_cg)
 {
     Scalars *s = a.sc;
-    if (s->done) return;
+    if (s->done || s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
     double tot[2];
-    reduce_partials<2, 2u>(a.pr, gridDim.x, tot);
+    reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
     const double rho = tot[0], resmax = tot[1];
     const bool bad = !isfinite(rho) || !isfinite(resmax);
     const bool done = bad || resmax <= tol_cg || j >= max_cg;
@@ -571,9 +837,57 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
     const bool first = (j == 0);
     const double beta = first ? 0.0 : rho / s->rho[(j + 1) & 1];
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
+    const double tz2 = 0.5 * g.Tk[2];
     double v[1] = {0.0};
+    if (g.nz <= kWave) {
+        // gather p_new = z + beta p_old and K at the cell and its lateral
+        // neighbours for G2 columns, then apply the stencil; the vertical
+        // neighbours come from the adjacent lanes
+        constexpr int G2 = 2;
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
+            ColSlot cs[G2];
+            bool nb[G2][4];
+            size_t in[G2][4];
+            double Kp[G2], Dp[G2], pp[G2], Kn[G2][4], pn[G2][4];
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+                lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const size_t i = cs[u].i;
+                Kp[u] = a.K[i];
+                Dp[u] = a.Dd[i];
+                pp[u] = pnew_at<PRECOND>(a, i, beta, first, p_in);
+#pragma unroll
+                for (int d = 0; d < 4; d++) {
+                    Kn[u][d] = a.K[in[u][d]];
+                    pn[u][d] = pnew_at<PRECOND>(a, in[u][d], beta, first, p_in);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const int kt = cs[u].kt;
+                const double Kd = __shfl_up(Kp[u], 1, kWave), pdn = __shfl_up(pp[u], 1, kWave);
+                const double Ku = __shfl_down(Kp[u], 1, kWave), pup = __shfl_down(pp[u], 1, kWave);
+                if (!cs[u].act) continue;
+                double q = Dp[u] * pp[u];
+#pragma unroll
+                for (int d = 0; d < 4; d++)
+                    if (nb[u][d]) q += g.Tk[d >> 1] * 0.5 * (Kp[u] + Kn[u][d]) * (pp[u] - pn[u][d]);
+                if (lane > 0) q += tz2 * (Kp[u] + Kd) * (pp[u] - pdn);
+                if (lane + 1 < kt) q += tz2 * (Kp[u] + Ku) * (pp[u] - pup);
+                p_out[cs[u].i] = pp[u];
+                a.q[cs[u].i] = q;
+                v[0] += pp[u] * q;
+            }
+        }
+        block_partial<1, 0u>(v, a.pq);
+        return;
+    }
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -599,19 +913,19 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
 }
 
 // ---------------------------------------------------------------------------
-// PCG iteration: kernel B = e += alpha p, r -= alpha q, z = M^-1 r, r.z
+// PCG iteration, kernel B: e += alpha p, r -= alpha q, z = M^-1 r, r.z
 // ---------------------------------------------------------------------------
 
-// alpha = rho_j / p.q (every block combines the p.q partials); e += alpha p,
-// r -= alpha q, z = M^-1 r; block partials of (r.z, max|r/diag|).
+// alpha = rho_j / p.q (every block combines the p.q partials); block
+// partials of (r.z, max|r/diag|).
 template <int PRECOND>
 __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const double *p)
 {
     Scalars *s = a.sc;
-    if (s->done) return;
+    if (s->done || s->fail || s->stall || s->picard_done) return;
     const int j = s->jcur;
     double tot[1];
-    reduce_partials<1, 0u>(a.pq, gridDim.x, tot);
+    reduce_partials<1, 0u>(a.pq + g.foff, g.np, tot);
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (lead_thread()) {
@@ -628,9 +942,56 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
         s->iters = j + 1;
     }
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
+    if (g.nz <= kWave) {
+        constexpr int G2 = 2;
+        double *__restrict__ ev = a.e;
+        double *__restrict__ rv = a.r;
+        double *__restrict__ zv = a.z;
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
+            ColSlot cs[G2];
+            double pu[G2], ru[G2], qu[G2], du[G2], eu[G2], rdu[G2], tu[G2];
+#pragma unroll
+            for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const size_t i = cs[u].i;
+                pu[u] = p[i];
+                ru[u] = rv[i];
+                qu[u] = a.q[i];
+                du[u] = a.diag[i];
+                eu[u] = ev[i];
+                if (PRECOND == RF_PRECOND_ZLINE) {
+                    rdu[u] = a.rdp[i];
+                    tu[u] = a.tz[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const bool act = cs[u].act;
+                const size_t i = cs[u].i;
+                const double r = act ? ru[u] - alpha * qu[u] : 0.0;
+                if (act) {
+                    ev[i] = eu[u] + alpha * pu[u];
+                    rv[i] = r;
+                    v[1] = fmax(v[1], fabs(r / du[u]));
+                }
+                if (PRECOND == RF_PRECOND_JACOBI) {
+                    if (act) v[0] += r * (r / du[u]);
+                } else {
+                    const double zk = zline_solve_short(r, act ? rdu[u] : 0.0, act ? tu[u] : 0.0, lane);
+                    if (act) {
+                        zv[i] = zk;
+                        v[0] += r * zk;
+                    }
+                }
+            }
+        }
+        block_partial<2, 2u>(v, a.pr);
+        return;
+    }
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         const size_t base = (size_t)col * g.nz;
@@ -646,9 +1007,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
             v[1] = fmax(v[1], fabs(r / dg));
         }
         if (PRECOND == RF_PRECOND_ZLINE && kt > 0) {
-            double zr;
-            if (kt <= kWave) zline_solve_column<true>(a.r, a.rdp, a.tz, a.z, base, kt, lane, zr);
-            else zline_solve_column<false>(a.r, a.rdp, a.tz, a.z, base, kt, lane, zr);
+            zline_solve_long(a.r, a.rdp, a.tz, a.z, base, kt, lane);
             for (int k0 = 0; k0 < kt; k0 += kWave) {
                 const int k = k0 + lane;
                 if (k < kt) v[0] += a.r[base + k] * a.z[base + k];
@@ -659,67 +1018,143 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Picard update and exit test (row a6): h^{m+1} = h^m + e, delta = max|e|
+// Picard update: h^{m+1} = h^m + e
 // ---------------------------------------------------------------------------
 
-// Enqueued after every chunk of PCG iterations.  Every block combines the
-// last (r.z, max|r/diag|) partials and decides, as the next direction update
-// would, whether the solve has finished; if so it writes hnew = h^m + e
-// (idempotent, so a repeated launch changes nothing) and the block partials
-// of (max|e|, non-finite count), which the host combines.
-__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, double tol_cg, int max_cg)
+// Enqueued after a chunk of PCG iterations.  Every block combines the last
+// (r.z, max|r/diag|) partials and decides, as the next direction update
+// would, whether the solve has finished.  If not, the step stalls until the
+// host enqueues more iterations; if so, hb[(m+1)&1] = hb[m&1] + e and block
+// partials of (max|e|, non-finite count).
+__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, double tol_cg, int max_cg)
 {
     Scalars *s = a.sc;
-    if (s->fail) return;
+    if (s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
     double tot[2];
-    reduce_partials<2, 2u>(a.pr, gridDim.x, tot);
-    const bool finished = s->done || !(tot[1] > tol_cg) || j >= max_cg;
-    if (!finished) return;
-    if (!isfinite(tot[0]) || !isfinite(tot[1]) || (!s->done && tot[1] > tol_cg)) {
+    reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
+    const bool bad = !isfinite(tot[0]) || !isfinite(tot[1]);
+    const bool finished = s->done || bad || !(tot[1] > tol_cg) || j >= max_cg;
+    if (!finished) {
+        if (lead_thread()) {
+            s->stall = 1;
+            s->stall_m = m;
+        }
+        return;
+    }
+    if (!s->done && (bad || tot[1] > tol_cg)) {
         if (lead_thread()) {   // the next direction update would stop with this status
-            s->fail = (!isfinite(tot[0]) || !isfinite(tot[1])) ? 3 : 2;
+            s->fail = bad ? 3 : 2;
+            s->done = 1;
             s->final_iters = j;
         }
         return;
     }
+    const double *__restrict__ hmv = (m & 1) ? a.hb1 : a.hb0;
+    double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
+    const double *__restrict__ ev = a.e;
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
-    for (int col = cb + w; col < ce; col += kWavesPerBlock) {
-        const int kt = a.ktop[col];
-        for (int k0 = 0; k0 < kt; k0 += kWave) {
-            const int k = k0 + lane;
-            if (k >= kt) continue;
-            const size_t i = (size_t)col * g.nz + k;
-            const double e = a.e[i];
-            const double h = a.hm[i] + e;
-            a.hnew[i] = h;
-            v[0] = fmax(v[0], fabs(e));
-            if (!isfinite(h)) v[1] += 1.0;
+    if (g.nz <= kWave) {
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * kColGroup) {
+            ColSlot cs[kColGroup];
+            double e[kColGroup], hv[kColGroup];
+#pragma unroll
+            for (int u = 0; u < kColGroup; u++)
+                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+            for (int u = 0; u < kColGroup; u++) {
+                e[u] = ev[cs[u].i];
+                hv[u] = hmv[cs[u].i];
+            }
+#pragma unroll
+            for (int u = 0; u < kColGroup; u++) {
+                if (!cs[u].act) continue;
+                const double h = hv[u] + e[u];
+                hnext[cs[u].i] = h;
+                v[0] = fmax(v[0], fabs(e[u]));
+                if (!isfinite(h)) v[1] += 1.0;
+            }
+        }
+    } else {
+        for (int col = cb + w; col < ce; col += kWavesPerBlock) {
+            const int kt = a.ktop[col];
+            for (int k0 = 0; k0 < kt; k0 += kWave) {
+                const int k = k0 + lane;
+                if (k >= kt) continue;
+                const size_t i = (size_t)col * g.nz + k;
+                const double e = ev[i];
+                const double h = hmv[i] + e;
+                hnext[i] = h;
+                v[0] = fmax(v[0], fabs(e));
+                if (!isfinite(h)) v[1] += 1.0;
+            }
         }
     }
     block_partial<2, 1u>(v, a.pd);
-    if (lead_thread()) {
-        s->applied = 1;
-        s->final_iters = j;
-    }
+    if (lead_thread() && m < RF_MAX_PICARD_LOG) s->cg_log[m] = j;
 }
 
 // ---------------------------------------------------------------------------
-// Step acceptance (row a7): h^n <- h^{m+1}, theta~^n, storage, face inflows
+// Step acceptance: h^n <- h^{m+1}, theta~^n, storage, face inflows
 // ---------------------------------------------------------------------------
 
-// Block partials: [0] storage sum V theta~(h); [1+f] inflow rate through
+// Runs when the Picard exit test has passed (the flag comes from k_decide).
+// Block partials (ps): [0] storage sum V theta~(h); [1+f] inflow rate through
 // face f with h = h^{m+1} and K = K(h^m) (the converged system).
-__global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Bc bc, Arrays a)
+__global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
 {
+    Scalars *s = a.sc;
+    if (s->fail || s->stall || !s->picard_done) return;
+    __shared__ Layer sL[RF_MAX_LAYERS];
+    __shared__ FaceTab sBT[6];
+    __shared__ double sKR[6 * RF_MAX_LAYERS];
+    stage_bc(a, sBT, sKR);
+    stage_layers(a, so.nlayer, sL);
+    const int mf = s->picard_m;
+    const double *hf = ((mf + 1) & 1) ? a.hb1 : a.hb0;
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const double dist[3] = {g.A[0] / g.Tk[0], g.A[1] / g.Tk[1], g.A[2] / g.Tk[2]};
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (g.nz <= kWave) {
+        constexpr int G2 = 2;
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
+            ColSlot cs[G2];
+            double hu[G2], Ku[G2], ksu[G2];
+            int lu[G2];
+#pragma unroll
+            for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                const size_t i = cs[u].i;
+                hu[u] = hf[i];
+                Ku[u] = a.K[i];
+                ksu[u] = a.Ks[i];
+                lu[u] = a.layer ? a.layer[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                if (!cs[u].act) continue;
+                const size_t i = cs[u].i;
+                const int ci = cs[u].col % g.nx, cj = cs[u].col / g.nx;
+                const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, lane == 0,
+                                     lane == cs[u].kt - 1};
+                a.hn[i] = hu[u];
+                const double th = soil_theta(so.model, hu[u], sL[lu[u]]);
+                a.thn[i] = th;
+                v[0] += g.V * th;
+#pragma unroll
+                for (int d = 0; d < 6; d++) {
+                    if (!bnd[d]) continue;
+                    const double Kb = ksu[u] * sKR[d * RF_MAX_LAYERS + lu[u]];
+                    v[1 + d] += (sBT[d].cKb - sBT[d].cD * hu[u]) * Kb + sBT[d].cK * Ku[u] + sBT[d].c0;
+                }
+            }
+        }
+    } else
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -728,33 +1163,25 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Bc bc, Arra
             Cell c;
             cell_setup(g, a.ktop, col, kt, k, c);
             const size_t idx = c.idx;
-            const Layer &L = so.L[a.layer ? a.layer[idx] : 0];
-            const double h = a.hm[idx];
+            const int lay = a.layer ? a.layer[idx] : 0;
+            const double h = hf[idx];
             a.hn[idx] = h;
-            const double th = soil_theta(so.model, h, L);
+            const double th = soil_theta(so.model, h, sL[lay]);
             a.thn[idx] = th;
             v[0] += g.V * th;
 #pragma unroll
             for (int d = 0; d < 6; d++) {
                 if (!c.bnd[d]) continue;
-                const int ax = d >> 1;
-                const double gn = gdot(g, d);
-                const int type = bc.type[d];
-                double q = 0.0;
-                if (type == RF_DIRICHLET) {
-                    const double hb = bc.value[d];
-                    const double Kb = soil_K(so.model, hb, L, a.Ks[idx]);
-                    q = g.A[ax] * Kb / (0.5 * dist[ax]) * (hb - h) + g.A[ax] * Kb * gn;
-                } else if (type == RF_FLUX) {
-                    q = g.A[ax] * bc.value[d];
-                } else if (type == RF_FREE_DRAINAGE) {
-                    q = g.A[ax] * a.K[idx] * gn;
-                }
-                v[1 + d] += q;
+                const double Kb = a.Ks[idx] * sKR[d * RF_MAX_LAYERS + lay];
+                v[1 + d] += (sBT[d].cKb - sBT[d].cD * h) * Kb + sBT[d].cK * a.K[idx] + sBT[d].c0;
             }
         }
     }
     block_partial<7, 0u>(v, a.ps);
+    if (lead_thread()) {
+        s->accepted = 1;
+        s->accept_m = mf;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -764,16 +1191,18 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Bc bc, Arra
 __global__ void __launch_bounds__(kThreads) k_eval_soil(Geo g, Soil so, Arrays a, const double *h,
                                                         double *theta, double *Cout, double *Kout)
 {
+    __shared__ Layer sL[RF_MAX_LAYERS];
+    stage_layers(a, so.nlayer, sL);
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
             const int k = k0 + lane;
             if (k >= kt) continue;
             const size_t idx = (size_t)col * g.nz + k;
-            const Layer &L = so.L[a.layer ? a.layer[idx] : 0];
+            const Layer &L = sL[a.layer ? a.layer[idx] : 0];
             double th, C, K;
             soil_eval(so.model, h[idx], L, a.Ks[idx], th, C, K);
             if (theta) theta[idx] = th;
@@ -787,8 +1216,8 @@ __global__ void __launch_bounds__(kThreads) k_eval_soil(Geo g, Soil so, Arrays a
 __global__ void __launch_bounds__(kThreads) k_operator(Geo g, Arrays a, const double *x, double *y)
 {
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -813,8 +1242,8 @@ template <int PRECOND>
 __global__ void __launch_bounds__(kThreads) k_precond(Geo g, Arrays a, const double *r, double *z)
 {
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         const size_t base = (size_t)col * g.nz;
@@ -823,10 +1252,14 @@ __global__ void __launch_bounds__(kThreads) k_precond(Geo g, Arrays a, const dou
                 const int k = k0 + lane;
                 if (k < kt) z[base + k] = r[base + k] / a.diag[base + k];
             }
+        } else if (kt > kWave) {
+            zline_solve_long(r, a.rdp, a.tz, z, base, kt, lane);
         } else if (kt > 0) {
-            double zr;
-            if (kt <= kWave) zline_solve_column<true>(r, a.rdp, a.tz, z, base, kt, lane, zr);
-            else zline_solve_column<false>(r, a.rdp, a.tz, z, base, kt, lane, zr);
+            const bool act = lane < kt;
+            const double zk = zline_solve_short(act ? r[base + lane] : 0.0,
+                                                act ? a.rdp[base + lane] : 0.0,
+                                                act ? a.tz[base + lane] : 0.0, lane);
+            if (act) z[base + lane] = zk;
         }
     }
 }
@@ -834,8 +1267,8 @@ __global__ void __launch_bounds__(kThreads) k_precond(Geo g, Arrays a, const dou
 __global__ void __launch_bounds__(kThreads) k_copy_active(Geo g, Arrays a, const double *src, double *dst)
 {
     int cb, ce;
-    block_columns(g, cb, ce);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    block_columns(g, g.cpb_w, cb, ce);
+    RF_WAVE_IDS;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -845,92 +1278,138 @@ __global__ void __launch_bounds__(kThreads) k_copy_active(Geo g, Arrays a, const
     }
 }
 
+template <int NV, unsigned MAXMASK>
+__global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk)
+{
+    double tot[NV];
+    reduce_partials<NV, MAXMASK>(P, nblk, tot);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; i++) P[(size_t)nblk * NV + i] = tot[i];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
-#define RF_LAUNCH(kern, ...)                                                            \
+#define RF_LAUNCH_N(nb, kern, ...)                                                      \
     do {                                                                                \
-        hipLaunchKernelGGL(kern, dim3(g.nblk), dim3(kThreads), 0, s, __VA_ARGS__);     \
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, __VA_ARGS__);          \
         return hipGetLastError();                                                       \
     } while (0)
+// reducing kernels (partials combined later) and wide kernels
+#define RF_LAUNCH(kern, ...) RF_LAUNCH_N(g.nblk, kern, __VA_ARGS__)
+#define RF_LAUNCH_W(kern, ...) RF_LAUNCH_N(g.nblk_w, kern, __VA_ARGS__)
 
 hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s)
 {
-    RF_LAUNCH(k_init_ks, g, so, a, (const double *)a.ks_layer);
+    (void)so;
+    RF_LAUNCH_W(k_init_ks, g, a);
 }
+
+#define RF_LAUNCH_FOLD(P, nv, mask, kern, ...)                                          \
+    do {                                                                                \
+        hipLaunchKernelGGL(kern, dim3(g.nblk), dim3(kThreads), 0, s, __VA_ARGS__);      \
+        const hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess) return e_;                                                \
+        return launch_fold(g, P, nv, mask, s);                                          \
+    } while (0)
 
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s)
 {
-    RF_LAUNCH(k_check_finite, g, a, h);
+    RF_LAUNCH_FOLD(a.ps, 1, 0u, k_check_finite, g, a, h);
 }
 
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             hipStream_t s)
 {
-    RF_LAUNCH(k_set_state, g, so, a, h);
+    RF_LAUNCH_FOLD(a.ps, 1, 0u, k_set_state, g, so, a, h);
 }
 
-hipError_t launch_coeff(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a, double dt,
+hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
+                             const double *h0, hipStream_t s)
+{
+    RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0);
+}
+
+hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s)
+{
+    RF_LAUNCH_N(1, k_decide, g, a, m, tol_picard);
+}
+
+hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, hipStream_t s)
 {
-    RF_LAUNCH(k_coeff, g, so, bc, a, dt, chord_eps);
+    RF_LAUNCH_W(k_coeff, g, so, a, m, dt, chord_eps);
 }
 
-hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, double *bout, hipStream_t s)
+hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
+                        hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH(k_resid<RF_PRECOND_ZLINE>, g, a, bout);
-    RF_LAUNCH(k_resid<RF_PRECOND_JACOBI>, g, a, bout);
+    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH_FOLD(a.pr, 2, 2u, k_resid<RF_PRECOND_ZLINE>, g, a, m, bout);
+    RF_LAUNCH_FOLD(a.pr, 2, 2u, k_resid<RF_PRECOND_JACOBI>, g, a, m, bout);
 }
 
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, const double *p_in,
                        double *p_out, double tol_cg, int max_cg, hipStream_t s)
 {
     if (precond == RF_PRECOND_ZLINE)
-        RF_LAUNCH(k_spmv<RF_PRECOND_ZLINE>, g, a, p_in, p_out, tol_cg, max_cg);
-    RF_LAUNCH(k_spmv<RF_PRECOND_JACOBI>, g, a, p_in, p_out, tol_cg, max_cg);
+        RF_LAUNCH_FOLD(a.pq, 1, 0u, k_spmv<RF_PRECOND_ZLINE>, g, a, p_in, p_out, tol_cg, max_cg);
+    RF_LAUNCH_FOLD(a.pq, 1, 0u, k_spmv<RF_PRECOND_JACOBI>, g, a, p_in, p_out, tol_cg, max_cg);
 }
 
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, const double *p, hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH(k_update<RF_PRECOND_ZLINE>, g, a, p);
-    RF_LAUNCH(k_update<RF_PRECOND_JACOBI>, g, a, p);
+    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH_FOLD(a.pr, 2, 2u, k_update<RF_PRECOND_ZLINE>, g, a, p);
+    RF_LAUNCH_FOLD(a.pr, 2, 2u, k_update<RF_PRECOND_JACOBI>, g, a, p);
 }
 
-hipError_t launch_apply_h(const Geo &g, const Arrays &a, double tol_cg, int max_cg, hipStream_t s)
+hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, double tol_cg, int max_cg,
+                          hipStream_t s)
 {
-    RF_LAUNCH(k_apply_h, g, a, tol_cg, max_cg);
+    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h, g, a, m, tol_cg, max_cg);
 }
 
-hipError_t launch_accept(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                         hipStream_t s)
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s)
 {
-    RF_LAUNCH(k_accept, g, so, bc, a);
+    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept, g, so, a);
 }
 
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             double *theta, double *C, double *K, hipStream_t s)
 {
-    RF_LAUNCH(k_eval_soil, g, so, a, h, theta, C, K);
+    RF_LAUNCH_W(k_eval_soil, g, so, a, h, theta, C, K);
 }
 
 hipError_t launch_operator(const Geo &g, const Arrays &a, const double *x, double *y,
                            hipStream_t s)
 {
-    RF_LAUNCH(k_operator, g, a, x, y);
+    RF_LAUNCH_W(k_operator, g, a, x, y);
 }
 
 hipError_t launch_precond(const Geo &g, const Arrays &a, int precond, const double *r, double *z,
                           hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH(k_precond<RF_PRECOND_ZLINE>, g, a, r, z);
-    RF_LAUNCH(k_precond<RF_PRECOND_JACOBI>, g, a, r, z);
+    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH_W(k_precond<RF_PRECOND_ZLINE>, g, a, r, z);
+    RF_LAUNCH_W(k_precond<RF_PRECOND_JACOBI>, g, a, r, z);
+}
+
+hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s)
+{
+    if (g.np != 1 || g.nblk == 1) return hipSuccess;
+    switch (nv * 16 + (int)maxmask) {
+    case 1 * 16 + 0: RF_LAUNCH_N(1, (k_fold<1, 0u>), P, g.nblk);
+    case 2 * 16 + 1: RF_LAUNCH_N(1, (k_fold<2, 1u>), P, g.nblk);
+    case 2 * 16 + 2: RF_LAUNCH_N(1, (k_fold<2, 2u>), P, g.nblk);
+    case 7 * 16 + 0: RF_LAUNCH_N(1, (k_fold<7, 0u>), P, g.nblk);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_copy_active(const Geo &g, const Arrays &a, const double *src, double *dst,
                               hipStream_t s)
 {
-    RF_LAUNCH(k_copy_active, g, a, src, dst);
+    RF_LAUNCH_W(k_copy_active, g, a, src, dst);
 }
 
 }  // namespace rf
