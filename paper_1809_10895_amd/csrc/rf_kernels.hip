@@ -131,38 +131,45 @@ struct ColSlot {
     int kt;       // active cells (0 if the slot is past the block's columns)
     bool act;     // this lane holds an active cell
     size_t base;  // first cell of the column
-    size_t i;     // this lane's cell (base when inactive)
+    size_t i;     // this lane's cell (always inside the column, active or not)
 };
 
-__device__ __forceinline__ ColSlot col_slot(const Geo &g, const int32_t *ktop, int col, int ce,
-                                            int lane)
+// Addresses do not wait for k_top: every lane of a column reads its own cell
+// (masked cells are valid memory), so the data loads and the k_top loads of
+// a group are all in flight together; the masks apply to the results.
+__device__ __forceinline__ ColSlot col_slot(const Geo &g, const int32_t *__restrict__ ktop, int col,
+                                            int ce, int lane)
 {
     ColSlot c;
     const bool valid = col < ce;
     c.col = valid ? col : ce - 1;
+    c.base = (size_t)c.col * g.nz;
+    c.i = c.base + min(lane, g.nz - 1);
     const int kt = ktop[c.col];
     c.kt = valid ? kt : 0;
     c.act = lane < c.kt;
-    c.base = (size_t)c.col * g.nz;
-    c.i = c.base + (c.act ? lane : 0);
     return c;
 }
 
 // Lateral neighbours (0 -x, 1 +x, 2 -y, 3 +y) of a slot: whether the
-// neighbour cell is active, and its index (this cell's index otherwise).
-__device__ __forceinline__ void lateral(const Geo &g, const int32_t *ktop, const ColSlot &c,
-                                        int lane, bool (&nb)[4], size_t (&in)[4])
+// neighbour cell is active, and its index (this cell's index where the
+// domain ends).
+__device__ __forceinline__ void lateral(const Geo &g, const int32_t *__restrict__ ktop,
+                                        const ColSlot &c, int lane, bool (&nb)[4], size_t (&in)[4])
 {
     const int i = c.col % g.nx, j = c.col / g.nx;
     const size_t sx = (size_t)g.nz, sy = (size_t)g.nz * g.nx;
-    const int cn[4] = {i > 0 ? c.col - 1 : c.col, i < g.nx - 1 ? c.col + 1 : c.col,
-                       j > 0 ? c.col - g.nx : c.col, j < g.ny - 1 ? c.col + g.nx : c.col};
     const bool has[4] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1};
+    const int cn[4] = {has[0] ? c.col - 1 : c.col, has[1] ? c.col + 1 : c.col,
+                       has[2] ? c.col - g.nx : c.col, has[3] ? c.col + g.nx : c.col};
+    int ktn[4];
+#pragma unroll
+    for (int d = 0; d < 4; d++) ktn[d] = ktop[cn[d]];      // unconditional: all in flight
 #pragma unroll
     for (int d = 0; d < 4; d++) {
-        nb[d] = c.act && has[d] && lane < ktop[cn[d]];
         const size_t off = (d < 2) ? sx : sy;
-        in[d] = nb[d] ? ((d & 1) ? c.i + off : c.i - off) : c.i;
+        in[d] = has[d] ? ((d & 1) ? c.i + off : c.i - off) : c.i;
+        nb[d] = c.act & has[d] & (lane < ktn[d]);            // no short-circuit branches
     }
 }
 
@@ -856,17 +863,29 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
                 cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
                 lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
             }
+            // every load of the group is unconditional (first iteration: the
+            // old direction is read but not used), so all are in flight at once
+            double zc[G2], pc[G2], zn[G2][4], po[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 const size_t i = cs[u].i;
                 Kp[u] = a.K[i];
                 Dp[u] = a.Dd[i];
-                pp[u] = pnew_at<PRECOND>(a, i, beta, first, p_in);
+                zc[u] = (PRECOND == RF_PRECOND_JACOBI) ? a.r[i] / a.diag[i] : a.z[i];
+                pc[u] = p_in[i];
 #pragma unroll
                 for (int d = 0; d < 4; d++) {
-                    Kn[u][d] = a.K[in[u][d]];
-                    pn[u][d] = pnew_at<PRECOND>(a, in[u][d], beta, first, p_in);
+                    const size_t jn = in[u][d];
+                    Kn[u][d] = a.K[jn];
+                    zn[u][d] = (PRECOND == RF_PRECOND_JACOBI) ? a.r[jn] / a.diag[jn] : a.z[jn];
+                    po[u][d] = p_in[jn];
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < G2; u++) {
+                pp[u] = first ? zc[u] : zc[u] + beta * pc[u];
+#pragma unroll
+                for (int d = 0; d < 4; d++) pn[u][d] = first ? zn[u][d] : zn[u][d] + beta * po[u][d];
             }
 #pragma unroll
             for (int u = 0; u < G2; u++) {
