@@ -8,7 +8,12 @@ inputs resident in HBM.  Prints ONE JSON line with the throughput in
 cell-steps/s, the roofline of the dominant kernel (HIP events on the library
 stream, inside the timed region) and the CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps 144] [--warmup 3] [--workload hillslope]
+    python bench.py [--gpus 1] [--steps 144] [--warmup 5] [--workload hillslope]
+                    [--precision fp64|mixed]
+
+The headline line is FP64 (the paper's arithmetic); the same steps are then
+timed in the other precision and reported under "other_precision", with the
+largest head difference between the two final states.
 """
 import argparse
 import hashlib
@@ -23,16 +28,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_TFLOPS = 78.6
 
-# Algorithmic bytes per active cell and launch (FP64 arrays, one pass each;
+# Algorithmic bytes per active cell and launch (one pass over each array;
 # neighbour values are reuse, not extra traffic).  Kernel -> (jacobi, zline).
 ALGO_BYTES = {
-    "spmv": (56, 48),      # read r, diag (z), p_old, K, Dd; write p, q
-    "update": (56, 80),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z)
-    "coeff": (56, 56),     # read h^m, h^n, theta^n, Ks; write K, Dd, bst
-    "resid": (56, 80),     # read K, h^m, Dd, bst; write r, e, diag (+ tz, rdp, z)
-    "apply_h": (24, 24),   # read e, h^m; write h^m
-    "accept": (24, 24),    # read h^m; write h^n, theta^n
+    "fp64": {
+        "spmv": (56, 48),      # read r, diag (z), p_old, K, Dd; write p, q
+        "update": (56, 80),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z)
+        "coeff": (56, 56),     # read h^m, h^n, theta^n, Ks; write K, Dd, bst
+        "resid": (56, 80),     # read K, h^m, Dd, bst; write r, e, diag (+ tz, rdp, z)
+        "apply_h": (24, 24),   # read e, h^m; write h^m
+        "accept": (24, 24),    # read h^m; write h^n, theta^n
+    },
+    # PCG vectors and the operator / preconditioner copies in FP32
+    "mixed": {
+        "spmv": (28, 24),      # read r, diag (z), p_old, K, Dd (4 B); write p, q (4 B)
+        "update": (28, 40),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z), 4 B each
+        "coeff": (56, 56),     # FP64 as above
+        "resid": (52, 64),     # read K, h^m, Dd, bst (8 B); write r, e, diag, K, Dd (+ tz, rdp, z) (4 B)
+        "apply_h": (20, 20),   # read e (4 B), h^m; write h^m
+        "accept": (24, 24),
+    },
 }
+PRECISION = {"fp64": 0, "mixed": 1}
 
 
 def parse():
@@ -42,6 +59,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="hillslope", choices=["hillslope", "watershed", "column100"])
     ap.add_argument("--precond", default="zline", choices=["zline", "jacobi"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="arithmetic of the timed line (fp64 = the paper's)")
+    ap.add_argument("--cg-rel-tol", type=float, default=0.0,
+                    help="relative PCG exit test (0 = absolute tol_cg only)")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the extra run in the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -100,10 +123,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, precision):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel, workload))
+    tag = "" if precision == "fp64" else "_" + precision
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s%s.json" % (kernel, workload, tag))
     try:
         with open(path) as f:
             d = json.load(f)
@@ -114,42 +138,32 @@ def measured_traffic(workload, kernel):
     return d.get("bytes_per_launch")
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def timed_case(args, w, precision):
+    """Warm-up, then `args.steps` timed steps of `w` in the given precision.
+    Returns the measured figures and the final state (host copy)."""
     import torch
     from paper_1809_10895_amd import Solver, workloads as W
-
-    if args.calibrate_copy_mib > 0:
-        n = args.calibrate_copy_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    w, desc = make_workload(args.workload)
     pc = 1 if args.precond == "zline" else 0
     S = Solver(0)
     S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
     W.configure(w, S)
     S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt, ebats=0,
-                  cols_per_wave=args.cols_per_wave)
+                  cols_per_wave=args.cols_per_wave, precision=PRECISION[precision],
+                  cg_rel_tol=args.cg_rel_tol)
     S.bind()
     h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
     assert S.set_state(h0) == 0, S.last_error()
+    algo_bytes = ALGO_BYTES[precision]
 
     picard = cg = 0
-    # warm-up steps, the first ones timing every kernel to find the dominant one
+    # warm-up steps, timing every kernel to find the dominant one
     S.set_timing(True)
     for _ in range(args.warmup):
         s, st = S.step(w.dt)
         assert s == 0, S.last_error()
     tm_all = S.get_timing()
     tot_all = sum(v["ms"] for v in tm_all.values() if isinstance(v, dict))
-    kern = max((k for k in ALGO_BYTES if k in tm_all and tm_all[k]["launches"]),
+    kern = max((k for k in algo_bytes if k in tm_all and tm_all[k]["launches"]),
                key=lambda k: tm_all[k]["ms"], default=None)
     # timed region: HIP events bracket only the dominant kernel's launches
     S.set_timing([kern] if (kern and not args.no_timing) else False)
@@ -165,14 +179,13 @@ def main():
     el = time.perf_counter() - t0
     tm = S.get_timing()
     cells = w.active_cells
-    value = cells * args.steps / el
 
     roof = None
     if kern is not None and not args.no_timing and tm[kern]["launches"]:
         avg_s = tm[kern]["ms"] / tm[kern]["launches"] * 1e-3
-        algo = ALGO_BYTES[kern][pc] * cells
+        algo = algo_bytes[kern][pc] * cells
         achieved = algo / avg_s / 1e9
-        traffic = measured_traffic(args.workload, kern)
+        traffic = measured_traffic(args.workload, kern, precision)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern, "avg_us": round(avg_s * 1e6, 2),
@@ -183,21 +196,59 @@ def main():
                    "share": round(v["ms"] / tot_all, 3) if tot_all > 0 else None,
                    "idle_launches": v["idle_launches"]}
                for k, v in tm_all.items() if isinstance(v, dict)}
+    h = S.get_state()[0].cpu().numpy()
+    return {"value": cells * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+            "picard_per_step": picard / args.steps, "cg_per_picard": cg / max(picard, 1),
+            "wall_s_per_simulated_day": el / (args.steps * w.dt) * 86400.0,
+            "roofline": roof, "kernels_warmup": kernels}, h
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w, desc = make_workload(args.workload)
+    cells = w.active_cells
+    main_r, h_main = timed_case(args, w, args.precision)
+    variant = None
+    if not args.no_variant:
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        r, h_other = timed_case(args, w, other)
+        m = w.active_mask()
+        variant = {"precision": other, "value": r["value"], "ms_per_step": r["ms_per_step"],
+                   "picard_per_step": r["picard_per_step"], "cg_per_picard": r["cg_per_picard"],
+                   "max_abs_h_diff_m": float(np.abs(h_other[m] - h_main[m]).max()),
+                   "roofline": r["roofline"]}
 
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
-        "metric": "cell-steps/s at Picard tol 1e-6", "value": value, "unit": "cell-steps/s",
+        "metric": "cell-steps/s at Picard tol 1e-6", "value": main_r["value"], "unit": "cell-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "ms_per_step": main_r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
         "config": {"workload": desc, "active_cells": cells, "grid": [w.nx, w.ny, w.nz],
                    "dt_s": w.dt, "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
+                   "cg_rel_tol": args.cg_rel_tol, "precision": args.precision,
                    "precond": args.precond, "cols_per_wave": args.cols_per_wave,
-                   "picard_per_step": picard / args.steps,
-                   "cg_per_picard": cg / max(picard, 1),
-                   "wall_s_per_simulated_day": el / (args.steps * w.dt) * 86400.0},
-        "roofline": roof,
-        "kernels_warmup": kernels,
+                   "picard_per_step": main_r["picard_per_step"],
+                   "cg_per_picard": main_r["cg_per_picard"],
+                   "wall_s_per_simulated_day": main_r["wall_s_per_simulated_day"]},
+        "roofline": main_r["roofline"],
+        "kernels_warmup": main_r["kernels_warmup"],
+        "other_precision": variant,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -57,6 +57,15 @@ enum { RF_VGM = 0, RF_GARDNER = 1 };                           /* soil model */
 enum { RF_XMIN = 0, RF_XMAX, RF_YMIN, RF_YMAX, RF_ZMIN, RF_ZMAX }; /* faces */
 enum { RF_NOFLOW = 0, RF_DIRICHLET = 1, RF_FLUX = 2, RF_FREE_DRAINAGE = 3 };
 enum { RF_PRECOND_JACOBI = 0, RF_PRECOND_ZLINE = 1 };
+/* Arithmetic of the Picard / PCG loop.  RF_PREC_FP64: every array and
+ * operation FP64.  RF_PREC_MIXED: soil coefficients, the Picard residual
+ * b - A h^m and h stay FP64 (each Picard iteration is then one step of
+ * iterative refinement of the FP32 solve); the PCG vectors, the operator's
+ * K and D copies and the preconditioner are FP32; PCG reductions and
+ * scalars stay FP64.  The paper's solver is FP64 throughout (Sec. 2.2):
+ * RF_PREC_MIXED is an extension, with results that differ from FP64 by
+ * about the PCG and Picard tolerances. */
+enum { RF_PREC_FP64 = 0, RF_PREC_MIXED = 1 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -81,6 +90,12 @@ typedef struct {
     double factor;      /* EBATS growth / shrink factor (default 1.3) */
     int cols_per_wave;  /* launch shape of the PCG kernels: z-columns per wavefront
                            (0 = chosen from the grid size) */
+    int precision;      /* RF_PREC_FP64 (default) or RF_PREC_MIXED.  Sizes the
+                           workspace: changing it on a bound context unbinds the
+                           workspace (rf_bind_workspace and rf_set_state again) */
+    double cg_rel_tol;  /* PCG also exits once max |r_c / A_cc| has fallen to
+                           cg_rel_tol times its value at the start of the solve
+                           (0 = the absolute test alone, the default) */
 } rf_options;
 
 typedef struct {
@@ -152,9 +167,12 @@ rf_status rf_set_bc(rf_ctx *ctx, int face, int type, double value);
 rf_status rf_set_forcing(rf_ctx *ctx, int face, int nseg, const double *t_start,
                          const double *flux);
 
+/* RF_ERR_ARG for an out-of-range field (the options are then unchanged).
+ * A different `precision` on a bound context unbinds its workspace. */
 rf_status rf_set_options(rf_ctx *ctx, const rf_options *opt);
 
-/* Device workspace the caller must provide for the current grid. */
+/* Device workspace the caller must provide for the current grid, soil
+ * layering and precision option. */
 rf_status rf_workspace_bytes(const rf_ctx *ctx, size_t *bytes);
 /* Binds `bytes` bytes of device memory at dev_ptr (256-byte aligned) as the
  * workspace; uploads grid and soil tables into it. */

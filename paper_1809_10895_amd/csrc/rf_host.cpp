@@ -222,6 +222,11 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
     // channels.
     int ia = 0;
     for (double **p : dbl) *p = (double *)take(N * sizeof(double) + kArraySkew * (size_t)(++ia % 8));
+    if (c->opt.precision == RF_PREC_MIXED) {
+        CgVec<float> &f = a.f;
+        float **flt[] = {&f.K, &f.Dd, &f.diag, &f.tz, &f.rdp, &f.r, &f.p0, &f.p1, &f.q, &f.e, &f.z};
+        for (float **p : flt) *p = (float *)take(N * sizeof(float) + kArraySkew * (size_t)(++ia % 8));
+    }
     a.layer = c->layer.empty() ? nullptr : (uint8_t *)take(N);
     a.ktop = (int32_t *)take(ncol * sizeof(int32_t));
     const size_t nb1 = max_partial_blocks(c) + 1;
@@ -339,6 +344,8 @@ void rf_default_options(rf_options *o)
     o->max_iters = 8;
     o->factor = 1.3;
     o->cols_per_wave = 0;
+    o->precision = RF_PREC_FP64;
+    o->cg_rel_tol = 0.0;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -519,8 +526,15 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         !(o->chord_eps >= 0) || (o->precond != RF_PRECOND_JACOBI && o->precond != RF_PRECOND_ZLINE) ||
         o->check_every < 1 || !(o->dt0 > 0) || !(o->dt_max > 0) || !(o->dt_min > 0) ||
         o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0) ||
-        o->cols_per_wave < 0)
+        o->cols_per_wave < 0 || (o->precision != RF_PREC_FP64 && o->precision != RF_PREC_MIXED) ||
+        !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0))
         return fail(c, RF_ERR_ARG, "invalid options");
+    if (c->have_ws && o->precision != c->opt.precision) {
+        // the FP32 arrays exist only in a workspace laid out for them
+        c->have_ws = false;
+        c->have_state = false;
+        c->assembled = false;
+    }
     c->opt = *o;
     c->dt_cur = o->dt0;
     c->easy = 0;
@@ -603,6 +617,10 @@ rf_status rf_get_state(const rf_ctx *cc, double *h_dev, double *t)
     return RF_OK;
 }
 
+static bool mixed(const rf_ctx *c) { return c->opt.precision == RF_PREC_MIXED; }
+
+static CgTol cg_tol(const rf_ctx *c) { return CgTol{c->opt.tol_cg, c->opt.cg_rel_tol, c->opt.max_cg}; }
+
 // Enqueues n more PCG iterations of Picard iteration m (the direction
 // buffers alternate with the iteration count).
 static rf_status enqueue_pairs(rf_ctx *c, int m, int n)
@@ -612,11 +630,8 @@ static rf_status enqueue_pairs(rf_ctx *c, int m, int n)
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     for (int i = 0; i < n; i++) {
         const int j = c->pairs_enq[mi]++;
-        double *pin = (j & 1) ? A.p1 : A.p0;
-        double *pout = (j & 1) ? A.p0 : A.p1;
-        TIMED(c, K_SPMV, m, j, launch_spmv(c->G, A, pc, pin, pout, c->opt.tol_cg, c->opt.max_cg,
-                                           c->stream));
-        TIMED(c, K_UPDATE, m, j, launch_update(c->G, A, pc, pout, c->stream));
+        TIMED(c, K_SPMV, m, j, launch_spmv(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
+        TIMED(c, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, c->stream));
     }
     return RF_OK;
 }
@@ -625,7 +640,7 @@ static rf_status enqueue_apply(rf_ctx *c, int m)
 {
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     TIMED(c, K_APPLYH, m, c->apply_enq[mi]++,
-          launch_apply_h(c->G, c->A, m, c->opt.tol_cg, c->opt.max_cg, c->stream));
+          launch_apply_h(c->G, c->A, m, mixed(c), cg_tol(c), c->stream));
     return RF_OK;
 }
 
@@ -639,7 +654,7 @@ static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     if (m > 0) TIMED(c, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
     TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps, c->stream));
-    TIMED(c, K_RESID, m, -1, launch_resid(G, A, c->opt.precond, m, nullptr, c->stream));
+    TIMED(c, K_RESID, m, -1, launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), c->stream));
     rf_status s = enqueue_pairs(c, m, std::max(1, c->pred_cg[mi]));
     if (s) return s;
     return enqueue_apply(c, m);
@@ -851,7 +866,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     (void)N;
     HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->stream));
-    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, c->stream));
+    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, c->stream));
     if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->assembled = true;

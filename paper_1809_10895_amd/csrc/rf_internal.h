@@ -75,8 +75,17 @@ struct Scalars {
     int accept_m;
     int cur_m;        // Picard iteration whose residual was formed last
     int pad[2];
+    double tol_eff;   // PCG exit tolerance of the current solve (absolute, or relative in FP32)
     int cg_log[RF_MAX_PICARD_LOG];       // PCG iterations of each Picard iteration
     double delta_log[RF_MAX_PICARD_LOG]; // max |h^{m+1} - h^m| of each Picard iteration
+};
+
+// The arrays one PCG solve works on, in the precision T of that solve: the
+// FP64 arrays, or (mixed precision) FP32 copies of the operator and
+// preconditioner with FP32 vectors.
+template <typename T>
+struct CgVec {
+    T *K, *Dd, *diag, *tz, *rdp, *r, *p0, *p1, *q, *e, *z;
 };
 
 // Device arrays inside the bound workspace.  The Picard iterate h^m lives in
@@ -95,6 +104,7 @@ struct Arrays {
     double *krb;              // K(h_b)/Ks of each Dirichlet face and layer [6 * RF_MAX_LAYERS]
     Layer *layers;            // van Genuchten parameters of each layer     [RF_MAX_LAYERS]
     double *bt;               // boundary coefficients of each face          [6 * 4]
+    CgVec<float> f;           // FP32 PCG arrays (mixed precision only; null otherwise)
     Scalars *sc;
 };
 
@@ -111,12 +121,20 @@ hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const A
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s);
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, hipStream_t s);
+// PCG tolerances of one solve: exit when max|r/diag| <= max(tol_cg,
+// rel * (its value at the start)); rel = 0 in FP64.
+struct CgTol {
+    double tol_cg, rel;
+    int max_cg;
+};
+
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        hipStream_t s);
-hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, const double *p_in,
-                       double *p_out, double tol_cg, int max_cg, hipStream_t s);
-hipError_t launch_update(const Geo &g, const Arrays &a, int precond, const double *p, hipStream_t s);
-hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, double tol_cg, int max_cg,
+                        bool mixed, hipStream_t s);
+hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
+                       const CgTol &t, hipStream_t s);
+hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
+                         hipStream_t s);
+hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s);
 hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s);
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,

@@ -5,11 +5,11 @@
 // walked in chunks of 64).  With z the fastest index every column is one
 // contiguous run of doubles, so each chunk is a single coalesced 512-byte
 // access per array, the vertical coupling stays inside the wave (shuffles),
-// and the lateral neighbours are the adjacent columns.  Blocks of 4 waves
-// take contiguous runs of columns; the block -> columns map is XCD-aware
-// (the hardware deals workgroups round-robin over the 8 XCDs, so logical
-// block (b % 8) * (G / 8) + b / 8 gives each XCD one contiguous slab of the
-// grid and keeps lateral reuse inside one L2).
+// and the lateral neighbours are the adjacent columns.  Blocks of 8 waves
+// take contiguous runs of columns (optionally remapped per XCD, see
+// block_columns).  The PCG kernels are templated on the precision of their
+// vectors: FP64, or FP32 under FP64 Picard refinement (mixed precision); their
+// reductions are FP64 in both.
 //
 // Global reductions are two-stage, deterministic and fence-free: every block
 // writes one partial per value, and the consumer -- every block of the next
@@ -21,6 +21,8 @@
 // such as alpha and beta never leave the device during the PCG loop.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "rf_internal.h"
 
@@ -502,12 +504,13 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
 
 // Inclusive upward scan of affine maps x_k = a_k x_{k-1} + c_k over the
 // wave; returns x_k for the given carry x_{k0-1}.
-__device__ __forceinline__ double scan_affine_up(double a, double c, double carry, int lane)
+template <typename T>
+__device__ __forceinline__ T scan_affine_up(T a, T c, T carry, int lane)
 {
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const double ao = __shfl_up(a, off, kWave);
-        const double co = __shfl_up(c, off, kWave);
+        const T ao = __shfl_up(a, off, kWave);
+        const T co = __shfl_up(c, off, kWave);
         if (lane >= off) {
             c = a * co + c;
             a = a * ao;
@@ -517,12 +520,13 @@ __device__ __forceinline__ double scan_affine_up(double a, double c, double carr
 }
 
 // Inclusive downward scan of x_k = b_k x_{k+1} + c_k.
-__device__ __forceinline__ double scan_affine_down(double b, double c, double carry, int lane)
+template <typename T>
+__device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
 {
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
-        const double bo = __shfl_down(b, off, kWave);
-        const double co = __shfl_down(c, off, kWave);
+        const T bo = __shfl_down(b, off, kWave);
+        const T co = __shfl_down(c, off, kWave);
         if (lane + off < kWave) {
             c = b * co + c;
             b = b * bo;
@@ -564,28 +568,28 @@ __device__ __forceinline__ double scan_pivots(double diag, double tprev2, double
 // z = M^-1 r for a column longer than one wave, from memory: forward sweep
 // w_k = (r_k + t_{k-1} w_{k-1}) rdp_k into zout, backward sweep
 // z_k = w_k + t_k rdp_k z_{k+1}.  Every lane re-reads only what it wrote.
-__device__ __forceinline__ void zline_solve_long(const double *r, const double *rdp,
-                                                 const double *tz, double *zout, size_t base,
-                                                 int kt, int lane)
+template <typename T>
+__device__ __forceinline__ void zline_solve_long(const T *r, const T *rdp, const T *tz, T *zout,
+                                                 size_t base, int kt, int lane)
 {
-    double carry = 0.0;
+    T carry = 0;
     for (int k0 = 0; k0 < kt; k0 += kWave) {
         const int k = k0 + lane;
         const bool act = k < kt;
-        const double rk = act ? r[base + k] : 0.0;
-        const double rd = act ? rdp[base + k] : 0.0;
-        const double tp = (act && k > 0) ? tz[base + k - 1] : 0.0;
-        const double wk = scan_affine_up(tp * rd, rk * rd, carry, lane);
+        const T rk = act ? r[base + k] : T(0);
+        const T rd = act ? rdp[base + k] : T(0);
+        const T tp = (act && k > 0) ? tz[base + k - 1] : T(0);
+        const T wk = scan_affine_up<T>(tp * rd, rk * rd, carry, lane);
         carry = __shfl(wk, kWave - 1, kWave);
         if (act) zout[base + k] = wk;
     }
-    carry = 0.0;
+    carry = 0;
     for (int ch = (kt - 1) / kWave; ch >= 0; ch--) {
         const int k = ch * kWave + lane;
         const bool act = k < kt;
-        const double wk = act ? zout[base + k] : 0.0;
-        const double bk = act ? tz[base + k] * rdp[base + k] : 0.0;
-        const double zk = scan_affine_down(bk, wk, carry, lane);
+        const T wk = act ? zout[base + k] : T(0);
+        const T bk = act ? tz[base + k] * rdp[base + k] : T(0);
+        const T zk = scan_affine_down<T>(bk, wk, carry, lane);
         carry = __shfl(zk, 0, kWave);
         if (act) zout[base + k] = zk;
     }
@@ -593,12 +597,13 @@ __device__ __forceinline__ void zline_solve_long(const double *r, const double *
 
 // The same for a column of at most 64 cells, entirely in registers: r, rdp
 // and t of lane k; returns z_k.
-__device__ __forceinline__ double zline_solve_short(double r, double rd, double t, int lane)
+template <typename T>
+__device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 {
-    double tp = __shfl_up(t, 1, kWave);
-    if (lane == 0) tp = 0.0;
-    const double wk = scan_affine_up(tp * rd, r * rd, 0.0, lane);
-    return scan_affine_down(t * rd, wk, 0.0, lane);
+    T tp = __shfl_up(t, 1, kWave);
+    if (lane == 0) tp = 0;
+    const T wk = scan_affine_up<T>(tp * rd, r * rd, T(0), lane);
+    return scan_affine_down<T>(t * rd, wk, T(0), lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,9 +615,12 @@ __device__ __forceinline__ double zline_solve_short(double r, double rd, double 
 // right-hand side of the increment system A e = r, e0 = 0); e = 0.
 // Jacobi: z = r / diag.  z-line: t_k (vertical couplings) and reciprocal
 // pivots of each column, z = M^-1 r.  Block partials of (r.z, max|r/diag|).
-template <int PRECOND>
-__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, double *bout)
+// Everything is computed in FP64; the PCG arrays v receive it in the
+// precision T of the solve (FP32 copies of K and Dd as well when T is float).
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv, int m, double *bout)
 {
+    constexpr bool kCopyKD = !std::is_same<T, double>::value;
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
     const double *hmv = (m & 1) ? a.hb1 : a.hb0;
@@ -660,16 +668,16 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
                 for (int d = 0; d < 4; d++) {
                     if (!nb[u][d]) continue;
                     const double Kf = 0.5 * (Kp[u] + Kn[u][d]);
-                    const double T = g.Tk[d >> 1] * Kf;
-                    diag += T;
-                    Ap += T * (hp[u] - hn[u][d]);
+                    const double Tf = g.Tk[d >> 1] * Kf;
+                    diag += Tf;
+                    Ap += Tf * (hp[u] - hn[u][d]);
                     b += g.A[d >> 1] * Kf * gdot(g, d);
                 }
                 if (act && lane > 0) {
                     const double Kf = 0.5 * (Kp[u] + Kd);
-                    const double T = g.Tk[2] * Kf;
-                    diag += T;
-                    Ap += T * (hp[u] - hd);
+                    const double Tf = g.Tk[2] * Kf;
+                    diag += Tf;
+                    Ap += Tf * (hp[u] - hd);
                     b += g.A[2] * Kf * gz[0];
                 }
                 if (act && lane + 1 < kt) {
@@ -680,26 +688,32 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
                     b += g.A[2] * Kf * gz[1];
                 }
                 const double r = act ? b - Ap : 0.0;
+                const T rs = (T)r, ds = (T)diag;
                 if (act) {
                     if (bout) bout[i] = b;
-                    a.r[i] = r;
-                    a.e[i] = 0.0;
-                    a.diag[i] = diag;
+                    cv.r[i] = rs;
+                    cv.e[i] = T(0);
+                    cv.diag[i] = ds;
+                    if (kCopyKD) {
+                        cv.K[i] = (T)Kp[u];
+                        cv.Dd[i] = (T)Dp[u];
+                    }
                     v[1] = fmax(v[1], fabs(r / diag));
-                    if (PRECOND == RF_PRECOND_JACOBI) v[0] += r * (r / diag);
+                    if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
                 }
                 if (PRECOND == RF_PRECOND_ZLINE) {
                     double tprev = __shfl_up(tup, 1, kWave);
                     if (lane == 0) tprev = 0.0;
                     const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
                     const double rdp = act ? 1.0 / dpiv : 0.0;
-                    const double wk = scan_affine_up(tprev * rdp, r * rdp, 0.0, lane);
-                    const double zk = scan_affine_down(tup * rdp, wk, 0.0, lane);
+                    const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
+                    const double zk = scan_affine_down<double>(tup * rdp, wk, 0.0, lane);
                     if (act) {
-                        a.tz[i] = tup;
-                        a.rdp[i] = rdp;
-                        a.z[i] = zk;
-                        v[0] += r * zk;
+                        const T zs = (T)zk;
+                        cv.tz[i] = (T)tup;
+                        cv.rdp[i] = (T)rdp;
+                        cv.z[i] = zs;
+                        v[0] += (double)rs * (double)zs;
                     }
                 }
             }
@@ -727,19 +741,23 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
                 for (int d = 0; d < 6; d++) {
                     if (!c.nb[d]) continue;
                     const double Kf = 0.5 * (Kp + a.K[c.off[d]]);
-                    const double T = g.Tk[d >> 1] * Kf;
-                    diag += T;
-                    Ap += T * (hp - hmv[c.off[d]]);
+                    const double Tf = g.Tk[d >> 1] * Kf;
+                    diag += Tf;
+                    Ap += Tf * (hp - hmv[c.off[d]]);
                     b += g.A[d >> 1] * Kf * gdot(g, d);
-                    if (d == 5) tup = T;
+                    if (d == 5) tup = Tf;
                 }
                 r = b - Ap;
                 if (bout) bout[c.idx] = b;
-                a.r[c.idx] = r;
-                a.e[c.idx] = 0.0;
-                a.diag[c.idx] = diag;
+                cv.r[c.idx] = (T)r;
+                cv.e[c.idx] = T(0);
+                cv.diag[c.idx] = (T)diag;
+                if (kCopyKD) {
+                    cv.K[c.idx] = (T)Kp;
+                    cv.Dd[c.idx] = (T)a.Dd[c.idx];
+                }
                 v[1] = fmax(v[1], fabs(r / diag));
-                if (PRECOND == RF_PRECOND_JACOBI) v[0] += r * (r / diag);
+                if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)(T)r * (double)((T)r / (T)diag);
             }
             if (PRECOND == RF_PRECOND_ZLINE) {
                 // couplings and pivots of the column tridiagonal, in registers
@@ -748,14 +766,14 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
                 const double dpiv = scan_pivots(act ? diag : 1.0, act ? tprev * tprev : 0.0,
                                                 d_carry, lane);
                 rdp = act ? 1.0 / dpiv : 0.0;
-                wk = scan_affine_up(tprev * rdp, r * rdp, w_carry, lane);
+                wk = scan_affine_up<double>(tprev * rdp, r * rdp, w_carry, lane);
                 t_carry = __shfl(tup, kWave - 1, kWave);
                 d_carry = __shfl(dpiv, kWave - 1, kWave);
                 w_carry = __shfl(wk, kWave - 1, kWave);
                 if (act) {
-                    a.tz[base + k] = tup;
-                    a.rdp[base + k] = rdp;
-                    if (kt > kWave) a.z[base + k] = wk;   // forward sweep, re-read by this lane
+                    cv.tz[base + k] = (T)tup;
+                    cv.rdp[base + k] = (T)rdp;
+                    if (kt > kWave) cv.z[base + k] = (T)wk;   // forward sweep, re-read by this lane
                 }
             }
         }
@@ -763,23 +781,26 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
             // backward sweep z_k = w_k + t_k rdp_k z_{k+1}
             if (kt <= kWave) {
                 const bool act = lane < kt;
-                const double zk = scan_affine_down(act ? tup * rdp : 0.0, act ? wk : 0.0, 0.0, lane);
+                const double zk = scan_affine_down<double>(act ? tup * rdp : 0.0, act ? wk : 0.0,
+                                                           0.0, lane);
                 if (act) {
-                    a.z[base + lane] = zk;
-                    v[0] += r * zk;
+                    const T zs = (T)zk;
+                    cv.z[base + lane] = zs;
+                    v[0] += (double)(T)r * (double)zs;
                 }
             } else {
-                double carry = 0.0;
+                // backward sweep in the precision of the stored sweep values
+                T carry = 0;
                 for (int ch = (kt - 1) / kWave; ch >= 0; ch--) {
                     const int k = ch * kWave + lane;
                     const bool act = k < kt;
-                    const double wv = act ? a.z[base + k] : 0.0;
-                    const double bk = act ? a.tz[base + k] * a.rdp[base + k] : 0.0;
-                    const double zk = scan_affine_down(bk, wv, carry, lane);
+                    const T wv = act ? cv.z[base + k] : T(0);
+                    const T bk = act ? cv.tz[base + k] * cv.rdp[base + k] : T(0);
+                    const T zk = scan_affine_down<T>(bk, wv, carry, lane);
                     carry = __shfl(zk, 0, kWave);
                     if (act) {
-                        a.z[base + k] = zk;
-                        v[0] += a.r[base + k] * zk;
+                        cv.z[base + k] = zk;
+                        v[0] += (double)cv.r[base + k] * (double)zk;
                     }
                 }
             }
@@ -804,22 +825,24 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, int m, doub
 // PCG iteration, kernel A: exit test, direction update, SpMV, p.q
 // ---------------------------------------------------------------------------
 
-template <int PRECOND>
-__device__ __forceinline__ double pnew_at(const Arrays &a, size_t i, double beta, bool first,
-                                          const double *p_in)
+template <int PRECOND, typename T>
+__device__ __forceinline__ T pnew_at(const CgVec<T> &cv, size_t i, T beta, bool first, const T *p_in)
 {
-    const double z = (PRECOND == RF_PRECOND_JACOBI) ? a.r[i] / a.diag[i] : a.z[i];
+    const T z = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
     return first ? z : z + beta * p_in[i];
 }
 
 // Starts PCG iteration j = (updates done so far).  Every block combines the
 // (r.z, max|r/diag|) partials of the last update and takes the same exit
-// decision (max|r/diag| <= tol_cg); otherwise p = z + beta p_old (z = M^-1 r)
-// at the cell and its neighbours, q = A p with A = Dd + sum_f T_f (I -
-// shift_f) rebuilt from (K, Dd); writes p, q and the block partials of p.q.
-template <int PRECOND>
-__global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double *p_in, double *p_out,
-                                                   double tol_cg, int max_cg)
+// decision (max|r/diag| <= tol, with tol = max(tol_cg, rel * the value at
+// j = 0) fixed at j = 0); otherwise p = z + beta p_old (z = M^-1 r) at the
+// cell and its neighbours, q = A p with A = Dd + sum_f T_f (I - shift_f)
+// rebuilt from (K, Dd); writes p, q and the block partials of p.q.  Vector
+// arithmetic in T, reductions and the scalars rho, beta in FP64.  The
+// direction buffers alternate: parity 0 reads p0 and writes p1.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv, int parity,
+                                                   double tol_cg, double rel, int max_cg)
 {
     Scalars *s = a.sc;
     if (s->done || s->fail || s->stall || s->picard_done) return;
@@ -827,26 +850,31 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
     double tot[2];
     reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
     const double rho = tot[0], resmax = tot[1];
+    const double tol = (j == 0) ? fmax(tol_cg, rel * resmax) : s->tol_eff;
     const bool bad = !isfinite(rho) || !isfinite(resmax);
-    const bool done = bad || resmax <= tol_cg || j >= max_cg;
+    const bool done = bad || resmax <= tol || j >= max_cg;
     if (lead_thread()) {
         s->rho[j & 1] = rho;
         s->resmax = resmax;
         s->jcur = j;
+        if (j == 0) s->tol_eff = tol;
         if (done) {
             s->done = 1;
             s->final_iters = j;
             if (bad) s->fail = 3;
-            else if (resmax > tol_cg) s->fail = 2;
+            else if (resmax > tol) s->fail = 2;
         }
     }
     if (done) return;
+    const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
+    T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
     const bool first = (j == 0);
-    const double beta = first ? 0.0 : rho / s->rho[(j + 1) & 1];
+    const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
-    const double tz2 = 0.5 * g.Tk[2];
+    const T tz2 = (T)(0.5 * g.Tk[2]);
+    const T tx2[2] = {(T)(0.5 * g.Tk[0]), (T)(0.5 * g.Tk[1])};
     double v[1] = {0.0};
     if (g.nz <= kWave) {
         // gather p_new = z + beta p_old and K at the cell and its lateral
@@ -857,7 +885,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
             ColSlot cs[G2];
             bool nb[G2][4];
             size_t in[G2][4];
-            double Kp[G2], Dp[G2], pp[G2], Kn[G2][4], pn[G2][4];
+            T Kp[G2], Dp[G2], pp[G2], Kn[G2][4], pn[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
@@ -865,19 +893,19 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
             }
             // every load of the group is unconditional (first iteration: the
             // old direction is read but not used), so all are in flight at once
-            double zc[G2], pc[G2], zn[G2][4], po[G2][4];
+            T zc[G2], pc[G2], zn[G2][4], po[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 const size_t i = cs[u].i;
-                Kp[u] = a.K[i];
-                Dp[u] = a.Dd[i];
-                zc[u] = (PRECOND == RF_PRECOND_JACOBI) ? a.r[i] / a.diag[i] : a.z[i];
+                Kp[u] = cv.K[i];
+                Dp[u] = cv.Dd[i];
+                zc[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
                 pc[u] = p_in[i];
 #pragma unroll
                 for (int d = 0; d < 4; d++) {
                     const size_t jn = in[u][d];
-                    Kn[u][d] = a.K[jn];
-                    zn[u][d] = (PRECOND == RF_PRECOND_JACOBI) ? a.r[jn] / a.diag[jn] : a.z[jn];
+                    Kn[u][d] = cv.K[jn];
+                    zn[u][d] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[jn] / cv.diag[jn] : cv.z[jn];
                     po[u][d] = p_in[jn];
                 }
             }
@@ -890,18 +918,18 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 const int kt = cs[u].kt;
-                const double Kd = __shfl_up(Kp[u], 1, kWave), pdn = __shfl_up(pp[u], 1, kWave);
-                const double Ku = __shfl_down(Kp[u], 1, kWave), pup = __shfl_down(pp[u], 1, kWave);
+                const T Kd = __shfl_up(Kp[u], 1, kWave), pdn = __shfl_up(pp[u], 1, kWave);
+                const T Ku = __shfl_down(Kp[u], 1, kWave), pup = __shfl_down(pp[u], 1, kWave);
                 if (!cs[u].act) continue;
-                double q = Dp[u] * pp[u];
+                T q = Dp[u] * pp[u];
 #pragma unroll
                 for (int d = 0; d < 4; d++)
-                    if (nb[u][d]) q += g.Tk[d >> 1] * 0.5 * (Kp[u] + Kn[u][d]) * (pp[u] - pn[u][d]);
+                    if (nb[u][d]) q += tx2[d >> 1] * (Kp[u] + Kn[u][d]) * (pp[u] - pn[u][d]);
                 if (lane > 0) q += tz2 * (Kp[u] + Kd) * (pp[u] - pdn);
                 if (lane + 1 < kt) q += tz2 * (Kp[u] + Ku) * (pp[u] - pup);
                 p_out[cs[u].i] = pp[u];
-                a.q[cs[u].i] = q;
-                v[0] += pp[u] * q;
+                cv.q[cs[u].i] = q;
+                v[0] += (double)pp[u] * (double)q;
             }
         }
         block_partial<1, 0u>(v, a.pq);
@@ -914,18 +942,18 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
             if (k >= kt) continue;
             Cell c;
             cell_setup(g, a.ktop, col, kt, k, c);
-            const double Kp = a.K[c.idx];
-            const double pp = pnew_at<PRECOND>(a, c.idx, beta, first, p_in);
-            double q = a.Dd[c.idx] * pp;
+            const T Kp = cv.K[c.idx];
+            const T pp = pnew_at<PRECOND, T>(cv, c.idx, beta, first, p_in);
+            T q = cv.Dd[c.idx] * pp;
 #pragma unroll
             for (int d = 0; d < 6; d++) {
                 if (!c.nb[d]) continue;
-                const double T = g.Tk[d >> 1] * 0.5 * (Kp + a.K[c.off[d]]);
-                q += T * (pp - pnew_at<PRECOND>(a, c.off[d], beta, first, p_in));
+                const T tf = (d < 4) ? tx2[d >> 1] : tz2;
+                q += tf * (Kp + cv.K[c.off[d]]) * (pp - pnew_at<PRECOND, T>(cv, c.off[d], beta, first, p_in));
             }
             p_out[c.idx] = pp;
-            a.q[c.idx] = q;
-            v[0] += pp * q;
+            cv.q[c.idx] = q;
+            v[0] += (double)pp * (double)q;
         }
     }
     block_partial<1, 0u>(v, a.pq);
@@ -936,9 +964,10 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, const double
 // ---------------------------------------------------------------------------
 
 // alpha = rho_j / p.q (every block combines the p.q partials); block
-// partials of (r.z, max|r/diag|).
-template <int PRECOND>
-__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const double *p)
+// partials of (r.z, max|r/diag|).  p is the direction the spmv kernel of the
+// same parity wrote.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
 {
     Scalars *s = a.sc;
     if (s->done || s->fail || s->stall || s->picard_done) return;
@@ -955,23 +984,24 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
         }
         return;
     }
-    const double alpha = s->rho[j & 1] / pq;
+    const T alpha = (T)(s->rho[j & 1] / pq);
     if (lead_thread()) {
         s->pq = pq;
         s->iters = j + 1;
     }
+    const T *__restrict__ p = parity ? cv.p0 : cv.p1;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
     if (g.nz <= kWave) {
         constexpr int G2 = 2;
-        double *__restrict__ ev = a.e;
-        double *__restrict__ rv = a.r;
-        double *__restrict__ zv = a.z;
+        T *__restrict__ ev = cv.e;
+        T *__restrict__ rv = cv.r;
+        T *__restrict__ zv = cv.z;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
             ColSlot cs[G2];
-            double pu[G2], ru[G2], qu[G2], du[G2], eu[G2], rdu[G2], tu[G2];
+            T pu[G2], ru[G2], qu[G2], du[G2], eu[G2], rdu[G2], tu[G2];
 #pragma unroll
             for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
 #pragma unroll
@@ -979,31 +1009,31 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
                 const size_t i = cs[u].i;
                 pu[u] = p[i];
                 ru[u] = rv[i];
-                qu[u] = a.q[i];
-                du[u] = a.diag[i];
+                qu[u] = cv.q[i];
+                du[u] = cv.diag[i];
                 eu[u] = ev[i];
                 if (PRECOND == RF_PRECOND_ZLINE) {
-                    rdu[u] = a.rdp[i];
-                    tu[u] = a.tz[i];
+                    rdu[u] = cv.rdp[i];
+                    tu[u] = cv.tz[i];
                 }
             }
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 const bool act = cs[u].act;
                 const size_t i = cs[u].i;
-                const double r = act ? ru[u] - alpha * qu[u] : 0.0;
+                const T r = act ? ru[u] - alpha * qu[u] : T(0);
                 if (act) {
                     ev[i] = eu[u] + alpha * pu[u];
                     rv[i] = r;
-                    v[1] = fmax(v[1], fabs(r / du[u]));
+                    v[1] = fmax(v[1], (double)fabs(r / du[u]));
                 }
                 if (PRECOND == RF_PRECOND_JACOBI) {
-                    if (act) v[0] += r * (r / du[u]);
+                    if (act) v[0] += (double)r * (double)(r / du[u]);
                 } else {
-                    const double zk = zline_solve_short(r, act ? rdu[u] : 0.0, act ? tu[u] : 0.0, lane);
+                    const T zk = zline_solve_short<T>(r, act ? rdu[u] : T(0), act ? tu[u] : T(0), lane);
                     if (act) {
                         zv[i] = zk;
-                        v[0] += r * zk;
+                        v[0] += (double)r * (double)zk;
                     }
                 }
             }
@@ -1018,18 +1048,18 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
             const int k = k0 + lane;
             if (k >= kt) continue;
             const size_t i = base + k;
-            a.e[i] += alpha * p[i];
-            const double r = a.r[i] - alpha * a.q[i];
-            a.r[i] = r;
-            const double dg = a.diag[i];
-            if (PRECOND == RF_PRECOND_JACOBI) v[0] += r * (r / dg);
-            v[1] = fmax(v[1], fabs(r / dg));
+            cv.e[i] += alpha * p[i];
+            const T r = cv.r[i] - alpha * cv.q[i];
+            cv.r[i] = r;
+            const T dg = cv.diag[i];
+            if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)r * (double)(r / dg);
+            v[1] = fmax(v[1], (double)fabs(r / dg));
         }
         if (PRECOND == RF_PRECOND_ZLINE && kt > 0) {
-            zline_solve_long(a.r, a.rdp, a.tz, a.z, base, kt, lane);
+            zline_solve_long<T>(cv.r, cv.rdp, cv.tz, cv.z, base, kt, lane);
             for (int k0 = 0; k0 < kt; k0 += kWave) {
                 const int k = k0 + lane;
-                if (k < kt) v[0] += a.r[base + k] * a.z[base + k];
+                if (k < kt) v[0] += (double)cv.r[base + k] * (double)cv.z[base + k];
             }
         }
     }
@@ -1044,16 +1074,21 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, const doub
 // (r.z, max|r/diag|) partials and decides, as the next direction update
 // would, whether the solve has finished.  If not, the step stalls until the
 // host enqueues more iterations; if so, hb[(m+1)&1] = hb[m&1] + e and block
-// partials of (max|e|, non-finite count).
-__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, double tol_cg, int max_cg)
+// partials of (max|e|, non-finite count).  The increment e is in the
+// precision T of the solve; h stays FP64.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *e_in, int m,
+                                                      double tol_cg, double rel, int max_cg)
 {
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
     double tot[2];
     reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
+    // the exit tolerance of this solve (fixed by its first direction update)
+    const double tol = (j == 0 && !s->done) ? fmax(tol_cg, rel * tot[1]) : s->tol_eff;
     const bool bad = !isfinite(tot[0]) || !isfinite(tot[1]);
-    const bool finished = s->done || bad || !(tot[1] > tol_cg) || j >= max_cg;
+    const bool finished = s->done || bad || !(tot[1] > tol) || j >= max_cg;
     if (!finished) {
         if (lead_thread()) {
             s->stall = 1;
@@ -1061,7 +1096,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, do
         }
         return;
     }
-    if (!s->done && (bad || tot[1] > tol_cg)) {
+    if (!s->done && (bad || tot[1] > tol)) {
         if (lead_thread()) {   // the next direction update would stop with this status
             s->fail = bad ? 3 : 2;
             s->done = 1;
@@ -1071,7 +1106,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, do
     }
     const double *__restrict__ hmv = (m & 1) ? a.hb1 : a.hb0;
     double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
-    const double *__restrict__ ev = a.e;
+    const T *__restrict__ ev = e_in;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
@@ -1079,13 +1114,13 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, do
     if (g.nz <= kWave) {
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * kColGroup) {
             ColSlot cs[kColGroup];
-            double e[kColGroup], hv[kColGroup];
+            double e[kColGroup], hv[kColGroup];   // e widened to FP64
 #pragma unroll
             for (int u = 0; u < kColGroup; u++)
                 cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
 #pragma unroll
             for (int u = 0; u < kColGroup; u++) {
-                e[u] = ev[cs[u].i];
+                e[u] = (double)ev[cs[u].i];
                 hv[u] = hmv[cs[u].i];
             }
 #pragma unroll
@@ -1104,7 +1139,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, int m, do
                 const int k = k0 + lane;
                 if (k >= kt) continue;
                 const size_t i = (size_t)col * g.nz + k;
-                const double e = ev[i];
+                const double e = (double)ev[i];
                 const double h = hmv[i] + e;
                 hnext[i] = h;
                 v[0] = fmax(v[0], fabs(e));
@@ -1362,31 +1397,57 @@ hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, do
     RF_LAUNCH_W(k_coeff, g, so, a, m, dt, chord_eps);
 }
 
+// The PCG arrays of the FP64 solve: the workspace arrays themselves.
+static CgVec<double> dvec(const Arrays &a)
+{
+    return CgVec<double>{a.K, a.Dd, a.diag, a.tz, a.rdp, a.r, a.p0, a.p1, a.q, a.e, a.z};
+}
+
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        hipStream_t s)
+                        bool mixed, hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH_FOLD(a.pr, 2, 2u, k_resid<RF_PRECOND_ZLINE>, g, a, m, bout);
-    RF_LAUNCH_FOLD(a.pr, 2, 2u, k_resid<RF_PRECOND_JACOBI>, g, a, m, bout);
+    const bool zl = precond == RF_PRECOND_ZLINE;
+    if (mixed && zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout);
+    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout);
+    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m, bout);
+    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m, bout);
 }
 
-hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, const double *p_in,
-                       double *p_out, double tol_cg, int max_cg, hipStream_t s)
+hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
+                       const CgTol &t, hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE)
-        RF_LAUNCH_FOLD(a.pq, 1, 0u, k_spmv<RF_PRECOND_ZLINE>, g, a, p_in, p_out, tol_cg, max_cg);
-    RF_LAUNCH_FOLD(a.pq, 1, 0u, k_spmv<RF_PRECOND_JACOBI>, g, a, p_in, p_out, tol_cg, max_cg);
+    const bool zl = precond == RF_PRECOND_ZLINE;
+    if (mixed && zl)
+        RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_ZLINE, float>), g, a, a.f, parity, t.tol_cg,
+                       t.rel, t.max_cg);
+    if (mixed)
+        RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_JACOBI, float>), g, a, a.f, parity, t.tol_cg,
+                       t.rel, t.max_cg);
+    if (zl)
+        RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity,
+                       t.tol_cg, t.rel, t.max_cg);
+    RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity, t.tol_cg,
+                   t.rel, t.max_cg);
 }
 
-hipError_t launch_update(const Geo &g, const Arrays &a, int precond, const double *p, hipStream_t s)
+hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
+                         hipStream_t s)
 {
-    if (precond == RF_PRECOND_ZLINE) RF_LAUNCH_FOLD(a.pr, 2, 2u, k_update<RF_PRECOND_ZLINE>, g, a, p);
-    RF_LAUNCH_FOLD(a.pr, 2, 2u, k_update<RF_PRECOND_JACOBI>, g, a, p);
+    const bool zl = precond == RF_PRECOND_ZLINE;
+    if (mixed && zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_ZLINE, float>), g, a, a.f, parity);
+    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_JACOBI, float>), g, a, a.f, parity);
+    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity);
+    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity);
 }
 
-hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, double tol_cg, int max_cg,
+hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s)
 {
-    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h, g, a, m, tol_cg, max_cg);
+    if (mixed)
+        RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<float>, g, a, (const float *)a.f.e, m, t.tol_cg, t.rel,
+                       t.max_cg);
+    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<double>, g, a, (const double *)a.e, m, t.tol_cg, t.rel,
+                   t.max_cg);
 }
 
 hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s)
