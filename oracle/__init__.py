@@ -33,6 +33,7 @@ SRC = os.path.join(HERE, "rf_oracle.c")
 LIB = os.path.join(HERE, "liboracle_rf.so")
 
 VGM, GARDNER = 0, 1
+PICARD_CHORD, PICARD_MODIFIED = 0, 1
 XMIN, XMAX, YMIN, YMAX, ZMIN, ZMAX = range(6)
 NOFLOW, DIRICHLET, FLUX, FREE_DRAINAGE = range(4)
 OK, ERR_ARG, ERR_NOT_CONVERGED, ERR_LINEAR, ERR_NONFINITE = 0, -1, -5, -6, -7
@@ -54,7 +55,7 @@ class Options(C.Structure):
                 ("max_picard", C.c_int), ("max_cg", C.c_int), ("chord_eps", C.c_double),
                 ("dt0", C.c_double), ("dt_max", C.c_double), ("dt_min", C.c_double),
                 ("ebats", C.c_int), ("inc_after", C.c_int), ("few_iters", C.c_int),
-                ("max_iters", C.c_int), ("factor", C.c_double)]
+                ("max_iters", C.c_int), ("factor", C.c_double), ("picard_variant", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -192,8 +193,10 @@ class Problem:
     def set_options(self, **kw):
         o = Options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, max_cg=10000, chord_eps=1e-9,
                     dt0=1.0, dt_max=3600.0, dt_min=1e-6, ebats=1, inc_after=10, few_iters=3,
-                    max_iters=8, factor=1.3)
+                    max_iters=8, factor=1.3, picard_variant=0)
         for k, v in kw.items():
+            if k not in dict(Options._fields_):
+                raise KeyError("unknown oracle option %r" % k)
             setattr(o, k, v)
         lib().orc_set_options(self.h, C.byref(o))
 

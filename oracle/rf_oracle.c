@@ -42,6 +42,7 @@
 enum { ORC_VGM = 0, ORC_GARDNER = 1 };
 enum { ORC_XMIN = 0, ORC_XMAX, ORC_YMIN, ORC_YMAX, ORC_ZMIN, ORC_ZMAX };
 enum { ORC_NOFLOW = 0, ORC_DIRICHLET = 1, ORC_FLUX = 2, ORC_FREE_DRAINAGE = 3 };
+enum { ORC_PICARD_CHORD = 0, ORC_PICARD_MODIFIED = 1 };   /* linearisation, Sec. 2.2 */
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_NOT_CONVERGED = -5,
        ORC_ERR_LINEAR = -6, ORC_ERR_NONFINITE = -7 };
 
@@ -60,6 +61,8 @@ typedef struct {
     int few_iters;       /* an easy step used at most this many Picard its */
     int max_iters;       /* a step needing more Picard its is rerun */
     double factor;       /* EBATS scaling factor */
+    int picard_variant;  /* ORC_PICARD_CHORD (classical Picard, chord-slope
+                            capacity) or ORC_PICARD_MODIFIED (Celia et al.) */
 } orc_options;
 
 typedef struct {
@@ -177,6 +180,7 @@ orc_problem *orc_create(int nx, int ny, int nz, double dx, double dy, double dz,
     P->opt.dt0 = 1.0; P->opt.dt_max = 3600.0; P->opt.dt_min = 1e-6;
     P->opt.ebats = 1; P->opt.inc_after = 10; P->opt.few_iters = 3;
     P->opt.max_iters = 8; P->opt.factor = 1.3;
+    P->opt.picard_variant = ORC_PICARD_CHORD;
     P->dt_cur = P->opt.dt0;
     return P;
 }
@@ -329,7 +333,11 @@ typedef struct {
  *                             + sum_f A_f K_f (g . n_f) + boundary terms
  * with K_f = (K_P + K_N)/2 at h^m, T_f = A_f K_f / d_f, C^m the chord slope
  * (theta~(h^m)-theta~(h^n))/(h^m-h^n) (analytic Eq. 3 when |h^m-h^n| <
- * chord_eps).  Boundary faces: Dirichlet h_b with K(h_b) over a half cell;
+ * chord_eps).  The modified Picard variant (Sec. 2.2; Celia et al. 1990)
+ * replaces the storage term by
+ *   V [C(h^m) (h^{m+1} - h^m) + theta~(h^m) - theta~(h^n)] / dt
+ * with the analytic capacity of Eq. 3; both reach the same fixed point,
+ * V (theta~(h) - theta~(h^n)) / dt = fluxes.  Boundary faces: Dirichlet h_b with K(h_b) over a half cell;
  * prescribed flux q (positive into the domain) as A q; free drainage as the
  * gravity flux A K(h_P^m) (g . n) with zero pressure gradient; no-flow and
  * faces towards inactive cells carry nothing.  Inactive cells get the
@@ -357,6 +365,14 @@ static void assemble(const orc_problem *P, const double *hm, const double *hn,
                 }
                 cell_params(P, c, p);
                 S->K[c] = orc_conductivity(P->model, hm[c], p);
+                if (P->opt.picard_variant == ORC_PICARD_MODIFIED) {
+                    double C = orc_capacity(P->model, hm[c], p);
+                    double dtheta = orc_theta(P->model, hm[c], p) - orc_theta(P->model, hn[c], p);
+                    S->C[c] = C;
+                    S->diag[c] = V * C / dt;
+                    S->b[c] = V * (C * hm[c] - dtheta) / dt;
+                    continue;
+                }
                 double dh = hm[c] - hn[c];
                 double C;
                 if (fabs(dh) >= P->opt.chord_eps)
