@@ -66,6 +66,15 @@ enum { RF_PRECOND_JACOBI = 0, RF_PRECOND_ZLINE = 1 };
  * RF_PREC_MIXED is an extension, with results that differ from FP64 by
  * about the PCG and Picard tolerances. */
 enum { RF_PREC_FP64 = 0, RF_PREC_MIXED = 1 };
+/* Picard linearisation of the storage term (Sec. 2.2).  RF_PICARD_CHORD, the
+ * paper's choice: V C (h^{m+1} - h^n) / dt with the chord slope
+ * C = (theta~(h^m) - theta~(h^n)) / (h^m - h^n) (Eq. 3 when the two heads are
+ * closer than chord_eps).  RF_PICARD_MODIFIED, the mass-conservative form of
+ * Celia et al. that Sec. 2.2 also mentions:
+ * V [C(h^m) (h^{m+1} - h^m) + theta~(h^m) - theta~(h^n)] / dt with the
+ * analytic capacity of Eq. 3.  Both converge to the same backward-Euler
+ * solution; the iterations differ. */
+enum { RF_PICARD_CHORD = 0, RF_PICARD_MODIFIED = 1 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -96,6 +105,7 @@ typedef struct {
     double cg_rel_tol;  /* PCG also exits once max |r_c / A_cc| has fallen to
                            cg_rel_tol times its value at the start of the solve
                            (0 = the absolute test alone, the default) */
+    int picard_variant; /* RF_PICARD_CHORD (default) or RF_PICARD_MODIFIED */
 } rf_options;
 
 typedef struct {

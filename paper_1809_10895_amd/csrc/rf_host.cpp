@@ -346,6 +346,7 @@ void rf_default_options(rf_options *o)
     o->cols_per_wave = 0;
     o->precision = RF_PREC_FP64;
     o->cg_rel_tol = 0.0;
+    o->picard_variant = RF_PICARD_CHORD;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -527,7 +528,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         o->check_every < 1 || !(o->dt0 > 0) || !(o->dt_max > 0) || !(o->dt_min > 0) ||
         o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0) ||
         o->cols_per_wave < 0 || (o->precision != RF_PREC_FP64 && o->precision != RF_PREC_MIXED) ||
-        !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0))
+        !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0) ||
+        (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {
         // the FP32 arrays exist only in a workspace laid out for them
@@ -653,7 +655,8 @@ static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
     Arrays &A = c->A;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     if (m > 0) TIMED(c, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
-    TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps, c->stream));
+    TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps,
+                                          c->opt.picard_variant, c->stream));
     TIMED(c, K_RESID, m, -1, launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), c->stream));
     rf_status s = enqueue_pairs(c, m, std::max(1, c->pred_cg[mi]));
     if (s) return s;
@@ -865,7 +868,8 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     const Bc bc = bc_at(c, c->t);
     (void)N;
     HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, c->stream));
-    HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->stream));
+    HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
+                           c->stream));
     HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, c->stream));
     if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

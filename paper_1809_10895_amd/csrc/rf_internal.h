@@ -120,7 +120,7 @@ hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const A
                              const double *h0, hipStream_t s);
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s);
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
-                        double chord_eps, hipStream_t s);
+                        double chord_eps, int variant, hipStream_t s);
 // PCG tolerances of one solve: exit when max|r/diag| <= max(tol_cg,
 // rel * (its value at the start)); rel = 0 in FP64.
 struct CgTol {

@@ -450,10 +450,11 @@ __global__ void __launch_bounds__(kThreads) k_decide(Geo g, Arrays a, int m, dou
 // Per active cell of h^m: K = K(h^m); chord capacity C = (theta~(h^m) -
 // theta~(h^n)) / (h^m - h^n), or Eq. 3 when |h^m - h^n| < chord_eps;
 // Dd = V C / dt + the boundary diagonal terms; bst = V C h^n / dt + the
-// boundary right-hand-side terms (see FaceTab).  Interior-face terms are
-// added in k_resid.
+// boundary right-hand-side terms (see FaceTab).  Modified Picard: C = Eq. 3
+// at h^m and bst = V (C h^m - (theta~(h^m) - theta~^n)) / dt + boundary
+// terms.  Interior-face terms are added in k_resid.
 __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
-                                                    double chord_eps)
+                                                    double chord_eps, int variant)
 {
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
@@ -480,10 +481,17 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
             const double hm = hmv[idx], hn = a.hn[idx];
             double th, C, K;
             soil_eval(so.model, hm, sL[lay], ks, th, C, K);
-            const double dh = hm - hn;
-            const double Cc = (fabs(dh) >= chord_eps) ? (th - a.thn[idx]) / dh : C;
-            double D = vdt * Cc;
-            double b = D * hn;
+            const double thn = a.thn[idx];
+            double D, b;
+            if (variant == RF_PICARD_MODIFIED) {
+                D = vdt * C;
+                b = vdt * (C * hm - (th - thn));
+            } else {
+                const double dh = hm - hn;
+                const double Cc = (fabs(dh) >= chord_eps) ? (th - thn) / dh : C;
+                D = vdt * Cc;
+                b = D * hn;
+            }
 #pragma unroll
             for (int d = 0; d < 6; d++) {
                 if (!c.bnd[d]) continue;
@@ -1392,9 +1400,9 @@ hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard
 }
 
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
-                        double chord_eps, hipStream_t s)
+                        double chord_eps, int variant, hipStream_t s)
 {
-    RF_LAUNCH_W(k_coeff, g, so, a, m, dt, chord_eps);
+    RF_LAUNCH_W(k_coeff, g, so, a, m, dt, chord_eps, variant);
 }
 
 // The PCG arrays of the FP64 solve: the workspace arrays themselves.
