@@ -34,7 +34,13 @@ EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf
            "rf_set_soil", "rf_set_bc", "rf_set_forcing", "rf_set_options", "rf_workspace_bytes",
            "rf_bind_workspace", "rf_set_state", "rf_get_state", "rf_step", "rf_run",
            "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
-           "rf_apply_precond", "rf_set_timing", "rf_get_timing"]
+           "rf_apply_precond", "rf_set_timing", "rf_get_timing",
+           # include/rf_ensemble.h
+           "rf_ens_create", "rf_ens_destroy", "rf_ens_last_error", "rf_ens_setup", "rf_ens_set_bc",
+           "rf_ens_set_options", "rf_ens_set_tile", "rf_ens_set_limits", "rf_ens_get_tile",
+           "rf_ens_cells", "rf_ens_workspace_bytes", "rf_ens_bind_workspace", "rf_ens_set_state",
+           "rf_ens_get_state", "rf_ens_run", "rf_ens_get_columns", "rf_ens_autotune"]
+RF_ENS_MAX_LEN = 448
 
 
 class RfOptions(C.Structure):
@@ -67,6 +73,23 @@ class RfTiming(C.Structure):
     _fields_ = [("name", C.c_char_p * RF_NKERNELS), ("launches", C.c_long * RF_NKERNELS),
                 ("ms", C.c_double * RF_NKERNELS), ("idle_launches", C.c_long * RF_NKERNELS),
                 ("idle_ms", C.c_double * RF_NKERNELS), ("cells", C.c_long)]
+
+
+class RfEnsTile(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int), ("blocks_per_cu", C.c_int)]
+
+
+class RfEnsColumn(C.Structure):
+    _fields_ = [("status", C.c_int), ("accepted", C.c_int), ("rejected", C.c_int),
+                ("easy", C.c_int), ("picard_total", C.c_long), ("t", C.c_double),
+                ("dt_next", C.c_double), ("storage0", C.c_double), ("storage", C.c_double),
+                ("inflow_top", C.c_double), ("inflow_bottom", C.c_double)]
+
+
+class RfEnsSummary(C.Structure):
+    _fields_ = [("accepted", C.c_long), ("rejected", C.c_long), ("picard_total", C.c_long),
+                ("cell_steps", C.c_long), ("failed", C.c_int), ("t_min", C.c_double),
+                ("max_balance_error", C.c_double)]
 
 
 class RfError(RuntimeError):
@@ -112,8 +135,26 @@ def load_library(path: str = LIB):
     L.rf_apply_precond.argtypes = [vp, vp, vp]
     L.rf_set_timing.argtypes = [vp, ip]
     L.rf_get_timing.argtypes = [vp, C.POINTER(RfTiming)]
+    L.rf_ens_create.argtypes = [C.POINTER(vp), ip, vp]
+    L.rf_ens_destroy.argtypes = [vp]
+    L.rf_ens_last_error.argtypes = [vp]
+    L.rf_ens_last_error.restype = C.c_char_p
+    L.rf_ens_setup.argtypes = [vp, ip, vp, dp, ip, vp]
+    L.rf_ens_set_bc.argtypes = [vp, ip, ip, dp]
+    L.rf_ens_set_options.argtypes = [vp, C.POINTER(RfOptions)]
+    L.rf_ens_set_tile.argtypes = [vp, C.POINTER(RfEnsTile)]
+    L.rf_ens_set_limits.argtypes = [vp, C.c_long, dp]
+    L.rf_ens_get_tile.argtypes = [vp, C.POINTER(RfEnsTile)]
+    L.rf_ens_cells.argtypes = [vp, C.POINTER(C.c_long)]
+    L.rf_ens_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.rf_ens_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    L.rf_ens_set_state.argtypes = [vp, vp, dp]
+    L.rf_ens_get_state.argtypes = [vp, vp]
+    L.rf_ens_run.argtypes = [vp, dp, C.POINTER(RfEnsSummary)]
+    L.rf_ens_get_columns.argtypes = [vp, C.POINTER(RfEnsColumn)]
+    L.rf_ens_autotune.argtypes = [vp, dp, C.POINTER(RfEnsTile)]
     for name in EXPORTS:
-        if name not in ("rf_default_options", "rf_destroy", "rf_last_error"):
+        if name not in ("rf_default_options", "rf_destroy", "rf_last_error", "rf_ens_last_error"):
             getattr(L, name).restype = C.c_int      # rf_status
     _lib = L
     return L
@@ -305,3 +346,106 @@ class Solver:
                 out[name] = {"launches": tm.launches[k], "ms": tm.ms[k],
                              "idle_launches": tm.idle_launches[k], "idle_ms": tm.idle_ms[k]}
         return out
+
+
+def _struct_dict(st):
+    return {name: getattr(st, name) for name, _ in st._fields_}
+
+
+class Ensemble:
+    """Many independent 1-D columns (include/rf_ensemble.h) on one GPU.
+
+    lengths: cells per column; soil: ncol x 6 (theta_r, theta_s, alpha, n,
+    Ks, S); the packed state is column after column, bottom cell first."""
+
+    def __init__(self, lengths, dz, soil, model=RF_VGM, device: int = 0, stream=None):
+        import numpy as np
+        import torch
+        self.torch = torch
+        self.L = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        s = self.L.rf_ens_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if s != RF_OK:
+            raise RfError(s, "rf_ens_create failed")
+        self.h = h
+        self.lengths = np.ascontiguousarray(lengths, dtype=np.int32)
+        self.offsets = np.concatenate([[0], np.cumsum(self.lengths)[:-1]]).astype(np.int64)
+        sp = np.ascontiguousarray(np.atleast_2d(soil), dtype=np.float64)
+        self._check(self.L.rf_ens_setup(self.h, len(self.lengths),
+                                        self.lengths.ctypes.data_as(C.c_void_p), float(dz), model,
+                                        sp.ctypes.data_as(C.c_void_p)))
+        n = C.c_long()
+        self._check(self.L.rf_ens_cells(self.h, C.byref(n)))
+        self.ncell = n.value
+        self.ncol = len(self.lengths)
+        self.ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rf_ens_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, s):
+        if s != RF_OK:
+            raise RfError(s, self.L.rf_ens_last_error(self.h).decode())
+        return s
+
+    def last_error(self) -> str:
+        return self.L.rf_ens_last_error(self.h).decode()
+
+    def set_bc(self, face, kind, value=0.0):
+        self._check(self.L.rf_ens_set_bc(self.h, face, kind, float(value)))
+
+    def set_options(self, **kw):
+        o = RfOptions()
+        self.L.rf_default_options(C.byref(o))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self._check(self.L.rf_ens_set_options(self.h, C.byref(o)))
+
+    def set_tile(self, waves_per_block, blocks_per_cu=0):
+        t = RfEnsTile(waves_per_block, blocks_per_cu)
+        self._check(self.L.rf_ens_set_tile(self.h, C.byref(t)))
+
+    def get_tile(self):
+        t = RfEnsTile()
+        self._check(self.L.rf_ens_get_tile(self.h, C.byref(t)))
+        return (t.waves_per_block, t.blocks_per_cu)
+
+    def set_limits(self, max_steps, max_seconds):
+        self._check(self.L.rf_ens_set_limits(self.h, int(max_steps), float(max_seconds)))
+
+    def bind(self):
+        n = C.c_size_t()
+        self._check(self.L.rf_ens_workspace_bytes(self.h, C.byref(n)))
+        self.ws = self.torch.empty(n.value, dtype=self.torch.uint8, device=self.device)
+        self._check(self.L.rf_ens_bind_workspace(self.h, _ptr(self.ws), n.value))
+
+    def set_state(self, h, t=0.0):
+        return self.L.rf_ens_set_state(self.h, _ptr(h), float(t))
+
+    def get_state(self):
+        out = self.torch.empty(self.ncell, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.rf_ens_get_state(self.h, _ptr(out)))
+        return out
+
+    def run(self, t_end):
+        sm = RfEnsSummary()
+        s = self.L.rf_ens_run(self.h, float(t_end), C.byref(sm))
+        return s, _struct_dict(sm)
+
+    def columns(self):
+        arr = (RfEnsColumn * self.ncol)()
+        self._check(self.L.rf_ens_get_columns(self.h, arr))
+        return [_struct_dict(c) for c in arr]
+
+    def autotune(self, t_span):
+        t = RfEnsTile()
+        s = self.L.rf_ens_autotune(self.h, float(t_span), C.byref(t))
+        return s, (t.waves_per_block, t.blocks_per_cu)

@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "rf_internal.h"
+#include "rf_soil.h"
 
 namespace rf {
 
@@ -206,60 +207,6 @@ __device__ __forceinline__ void stage_layers(const Arrays &a, int nlayer, Layer 
     const double *src = reinterpret_cast<const double *>(a.layers);
     for (int i = threadIdx.x; i < nlayer * 6; i += kThreads) d[i] = src[i];
     __syncthreads();
-}
-
-// van Genuchten-Mualem theta~ (Eq. 2 plus S*h above saturation), capacity
-// C (Eq. 3) and conductivity K (Eq. 4), or Gardner's exponential forms.
-// With u = (alpha |h|)^n and m = 1 - 1/n:  Se = (1+u)^-m,
-// 1 - (1 - Se^(1/m))^m = 1 - (u/(1+u))^m = -expm1(-m log(1 + 1/u)), and
-// C = (ts-tr) alpha n m (alpha|h|)^(n-1) (1+u)^-(1+m) = (ts-tr) n m Se u / ((1+u)|h|).
-// log(1+u) and log(1+1/u) come from one log1p of min(u, 1/u); no branch of
-// the formula cancels.  Five transcendentals per cell.
-__device__ __forceinline__ void soil_eval(int model, double h, const Layer &L, double ks,
-                                          double &th, double &C, double &K)
-{
-    if (h >= 0.0) {
-        th = L.ts + L.S * h;
-        C = L.S;
-        K = ks;
-        return;
-    }
-    if (model == RF_GARDNER) {
-        const double e = exp(L.a * h);
-        th = L.tr + (L.ts - L.tr) * e;
-        C = L.a * (L.ts - L.tr) * e;
-        K = ks * e;
-        return;
-    }
-    const double lu = L.n * log(-L.a * h);     // log u
-    const double u = exp(lu);
-    const bool small = u <= 1.0;
-    const double t = small ? u : 1.0 / u;      // min(u, 1/u)
-    const double lp = log1p(t);
-    const double l1 = small ? lp : lu + lp;    // log(1 + u)
-    const double lq = small ? lp - lu : lp;    // log(1 + 1/u)
-    const double sqSe = exp(-0.5 * L.m * l1);  // Se^(1/2)
-    const double Se = sqSe * sqSe;
-    th = L.tr + (L.ts - L.tr) * Se;
-    const double frac = 1.0 / (1.0 + (small ? 1.0 / u : t));   // u / (1 + u)
-    C = (L.ts - L.tr) * L.n * L.m * Se * frac / (-h);
-    const double w = -expm1(-L.m * lq);
-    K = ks * sqSe * w * w;
-}
-
-__device__ __forceinline__ double soil_theta(int model, double h, const Layer &L)
-{
-    if (h >= 0.0) return L.ts + L.S * h;
-    if (model == RF_GARDNER) return L.tr + (L.ts - L.tr) * exp(L.a * h);
-    const double lu = L.n * log(-L.a * h);
-    return L.tr + (L.ts - L.tr) * exp(-L.m * log1p(exp(lu)));
-}
-
-__device__ __forceinline__ double soil_K(int model, double h, const Layer &L, double ks)
-{
-    double th, C, K;
-    soil_eval(model, h, L, ks, th, C, K);
-    return K;
 }
 
 // Cell neighbourhood inside a column chunk.  Direction d: 0 -x, 1 +x, 2 -y,

@@ -20,6 +20,11 @@ synthetic stand-ins carry the shapes and parameter ranges of its cases):
   soil layers with the parameters of Eq. 5 plus a lognormal Ks field, hourly
   rain (10% wet hours, exponential depths of mean 2 mm); EBATS from 60 s up
   to 3600 s.
+* ensemble   -- 4096 independent 1-D columns of 1 cm cells, lengths uniform
+  in 50..400 cells, per-column van Genuchten n in [1.3, 3], alpha in
+  [0.5, 5] 1/m, log10 Ks in [-7, -4] (uniform), theta_r/theta_s of column100;
+  h0 = -10 m, top Dirichlet -0.75 m, free drainage (the column100 set-up);
+  EBATS from 10 s.
 """
 from __future__ import annotations
 
@@ -168,4 +173,52 @@ def configure(w: Workload, target):
         target.set_bc(face, kind, value)
     for face, (t0, q) in w.forcing.items():
         target.set_forcing(face, t0, q)
+    return target
+
+
+@dataclass
+class EnsembleWorkload:
+    name: str
+    lengths: np.ndarray                  # ncol int32
+    dz: float
+    soil: np.ndarray                     # ncol x 6
+    h0: np.ndarray                       # packed, sum(lengths)
+    bcs: list                            # [(face, type, value)], faces ZMIN / ZMAX
+    dt: float                            # dt0
+    t_end: float
+    ebats: bool = True
+    dt_max: float = 3600.0
+
+    @property
+    def ncol(self):
+        return len(self.lengths)
+
+    @property
+    def offsets(self):
+        return np.concatenate([[0], np.cumsum(self.lengths)[:-1]]).astype(np.int64)
+
+    def column(self, c):
+        """(length, soil row, initial heads) of column c."""
+        o = self.offsets[c]
+        return int(self.lengths[c]), self.soil[c], self.h0[o:o + self.lengths[c]]
+
+
+def ensemble(ncol=4096, seed=5, lmin=50, lmax=400, t_end=3600.0, dt_max=3600.0):
+    rng = np.random.default_rng(seed)
+    lengths = rng.integers(lmin, lmax + 1, size=ncol).astype(np.int32)
+    n = rng.uniform(1.3, 3.0, ncol)
+    alpha = rng.uniform(0.5, 5.0, ncol)
+    ks = 10.0 ** rng.uniform(-7.0, -4.0, ncol)
+    tr, ts, _, _, _, S = SOIL_COLUMN100
+    soil = np.stack([np.full(ncol, tr), np.full(ncol, ts), alpha, n, ks, np.full(ncol, S)], 1)
+    return EnsembleWorkload(name="ensemble", lengths=lengths, dz=0.01, soil=soil,
+                            h0=np.full(int(lengths.sum()), -10.0),
+                            bcs=[(ZMAX, DIRICHLET, -0.75), (ZMIN, FREE_DRAINAGE, 0.0)],
+                            dt=10.0, t_end=t_end, ebats=True, dt_max=dt_max)
+
+
+def configure_ensemble(w: EnsembleWorkload, target):
+    """Hands an ensemble's boundary conditions to an object with set_bc."""
+    for face, kind, value in w.bcs:
+        target.set_bc(face, kind, value)
     return target

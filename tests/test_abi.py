@@ -1,19 +1,22 @@
 """The C-ABI library loads without a GPU and exports every function that
 include/rf.h declares; host-only entry points behave as documented."""
 import ctypes as C
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rf.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(rf_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(rf_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_lists_the_boundary():
@@ -46,6 +49,9 @@ def test_null_arguments_rejected_without_gpu():
     assert L.rf_setup_grid(None, 1, 1, 1, 1.0, 1.0, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_step(None, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_mass_balance(None, None) == binding.RF_ERR_ARG
+    assert L.rf_ens_create(None, 0, None) == binding.RF_ERR_ARG
+    assert L.rf_ens_setup(None, 1, None, 0.01, 0, None) == binding.RF_ERR_ARG
+    assert L.rf_ens_run(None, 1.0, None) == binding.RF_ERR_ARG
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -1,0 +1,254 @@
+"""GPU parity of the column ensemble (include/rf_ensemble.h) against the FP64
+oracle run column by column (a 1 x 1 x L problem each, DIC-PCG): heads to
+1e-8 relative, identical EBATS decisions (accepted, rejected and Picard
+counts per column), water balances; ragged lengths at every boundary of the
+blocked layout (1, 2, 63..65, 127..129, 447, 448 cells), failure isolation,
+run budgets, the autotuner and the FP32-solve (mixed) variant."""
+import numpy as np
+import pytest
+
+from paper_1809_10895_amd import workloads as W
+from paper_1809_10895_amd.binding import Ensemble
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ORACLE_OPTS = dict(tol_cg=1e-13, max_cg=1000)
+
+
+def small_ensemble(lengths, seed=11, t_end=600.0, ks_max=-5.0):
+    rng = np.random.default_rng(seed)
+    nc = len(lengths)
+    lengths = np.asarray(lengths, np.int32)
+    n = rng.uniform(1.3, 3.0, nc)
+    alpha = rng.uniform(0.5, 5.0, nc)
+    ks = 10.0 ** rng.uniform(-7.0, ks_max, nc)
+    soil = np.stack([np.full(nc, 0.102), np.full(nc, 0.368), alpha, n, ks, np.full(nc, 1e-5)], 1)
+    return W.EnsembleWorkload(name="ens", lengths=lengths, dz=0.01, soil=soil,
+                              h0=np.full(int(lengths.sum()), -10.0),
+                              bcs=[(W.ZMAX, W.DIRICHLET, -0.75), (W.ZMIN, W.FREE_DRAINAGE, 0.0)],
+                              dt=10.0, t_end=t_end, ebats=True, dt_max=3600.0)
+
+
+def gpu_ensemble(w, **opts):
+    E = Ensemble(w.lengths, w.dz, w.soil)
+    W.configure_ensemble(w, E)
+    o = dict(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max, ebats=int(w.ebats))
+    o.update(opts)
+    E.set_options(**o)
+    E.bind()
+    assert E.set_state(torch.tensor(w.h0, dtype=torch.float64, device="cuda")) == 0, E.last_error()
+    return E
+
+
+def oracle_column(orc, w, c, t_end, **opts):
+    L, soil, h0 = w.column(c)
+    P = orc.Problem(1, 1, L, 1.0, 1.0, w.dz)
+    P.set_soil(np.array([soil]))
+    for face, kind, value in w.bcs:
+        P.set_bc(face, kind, value)
+    o = dict(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max, ebats=int(w.ebats),
+             **ORACLE_OPTS)
+    o.update(opts)
+    P.set_options(**o)
+    P.set_state(h0)
+    s, rs = P.run(t_end)
+    h, t = P.get_state()
+    return s, rs, h, P.mass_balance()
+
+
+def compare(orc, w, E, cols, t_end, **opts):
+    h = E.get_state().cpu().numpy()
+    recs = E.columns()
+    off = w.offsets
+    for c in cols:
+        s, rs, h_o, mb = oracle_column(orc, w, c, t_end, **opts)
+        r = recs[c]
+        assert (r["accepted"], r["rejected"], r["picard_total"]) == \
+            (rs["accepted"], rs["rejected"], rs["picard_total"]), (c, r, rs)
+        assert (r["status"] == 0) == (s == 0), (c, r["status"], s)
+        hg = h[off[c]:off[c] + w.lengths[c]]
+        err = np.abs(hg - h_o).max() / max(np.abs(h_o).max(), 1.0)
+        assert err <= 1e-8, (c, err)
+        assert r["storage"] == pytest.approx(mb["storage"], rel=1e-10), c
+        assert r["storage0"] == pytest.approx(mb["storage0"], rel=1e-12), c
+        assert r["inflow_top"] == pytest.approx(mb["inflow"][W.ZMAX], rel=1e-8, abs=1e-15), c
+        assert r["inflow_bottom"] == pytest.approx(mb["inflow"][W.ZMIN], rel=1e-8, abs=1e-15), c
+    return recs
+
+
+EDGE_LENGTHS = [1, 2, 5, 63, 64, 65, 100, 127, 128, 129, 191, 192, 193, 255, 256, 257,
+                319, 320, 321, 383, 384, 385, 447, 448]
+
+
+def test_ragged_lengths_match_oracle_under_ebats(orc):
+    w = small_ensemble(EDGE_LENGTHS)
+    E = gpu_ensemble(w)
+    s, sm = E.run(w.t_end)
+    assert s == 0, E.last_error()
+    assert sm["failed"] == 0 and sm["t_min"] == w.t_end
+    recs = compare(orc, w, E, range(w.ncol), w.t_end)
+    assert sm["accepted"] == sum(r["accepted"] for r in recs)
+    assert sm["cell_steps"] == sum(r["accepted"] * int(L) for r, L in zip(recs, w.lengths))
+    assert sm["max_balance_error"] <= 1e-9
+
+
+def test_repeated_runs_replay_the_graph(orc):
+    """Three runs in a row (one graph, replayed) equal the oracle's single
+    run over the same span only if every column carries its EBATS state
+    across calls; a clipped step at each intermediate end is part of both."""
+    w = small_ensemble([30, 70, 150, 300], seed=3)
+    E = gpu_ensemble(w)
+    for t in (100.0, 250.0, 600.0):
+        s, _ = E.run(t)
+        assert s == 0, E.last_error()
+    # the oracle with the same three stops
+    off = w.offsets
+    h = E.get_state().cpu().numpy()
+    for c in range(w.ncol):
+        L, soil, h0 = w.column(c)
+        P = orc.Problem(1, 1, L, 1.0, 1.0, w.dz)
+        P.set_soil(np.array([soil]))
+        W.configure_ensemble(w, P)
+        P.set_options(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max, ebats=1,
+                      **ORACLE_OPTS)
+        P.set_state(h0)
+        acc = 0
+        for t in (100.0, 250.0, 600.0):
+            s, rs = P.run(t)
+            assert s == 0
+            acc += rs["accepted"]
+        h_o, _ = P.get_state()
+        assert E.columns()[c]["accepted"] == acc
+        assert np.abs(h[off[c]:off[c] + L] - h_o).max() <= 1e-8 * max(np.abs(h_o).max(), 1.0)
+
+
+def test_modified_picard_and_gardner(orc):
+    w = small_ensemble([40, 64, 65, 200], seed=4)
+    E = gpu_ensemble(w, picard_variant=1)
+    assert E.run(w.t_end)[0] == 0, E.last_error()
+    compare(orc, w, E, range(w.ncol), w.t_end, picard_variant=1)
+    # Gardner soils (App. A) with a flux top
+    wg = small_ensemble([50, 129], seed=6)
+    wg.soil[:, 2] = [0.5, 3.0]
+    wg.bcs = [(W.ZMAX, W.FLUX, 5e-7), (W.ZMIN, W.DIRICHLET, 0.0)]
+    wg.h0 = -np.concatenate([np.linspace(0.0, 0.5, 50), np.linspace(0.0, 1.29, 129)])
+    Eg = Ensemble(wg.lengths, wg.dz, wg.soil, model=1)
+    W.configure_ensemble(wg, Eg)
+    Eg.set_options(tol_picard=1e-6, max_picard=50, dt0=wg.dt, dt_max=wg.dt_max, ebats=1)
+    Eg.bind()
+    assert Eg.set_state(torch.tensor(wg.h0, dtype=torch.float64, device="cuda")) == 0
+    assert Eg.run(wg.t_end)[0] == 0, Eg.last_error()
+    h = Eg.get_state().cpu().numpy()
+    for c in range(2):
+        L, soil, h0 = wg.column(c)
+        P = orc.Problem(1, 1, L, 1.0, 1.0, wg.dz)
+        P.set_soil(np.array([soil]), model=1)
+        W.configure_ensemble(wg, P)
+        P.set_options(tol_picard=1e-6, max_picard=50, dt0=wg.dt, dt_max=wg.dt_max, ebats=1,
+                      **ORACLE_OPTS)
+        P.set_state(h0)
+        assert P.run(wg.t_end)[0] == 0
+        h_o, _ = P.get_state()
+        o = wg.offsets[c]
+        assert np.abs(h[o:o + L] - h_o).max() <= 1e-8 * max(np.abs(h_o).max(), 1.0)
+
+
+def test_failed_column_is_isolated(orc):
+    """Fixed 10 s steps: a steep, permeable column cannot converge and stops
+    at its last accepted state with its status; the others finish."""
+    w = small_ensemble([120, 200, 90], seed=7, t_end=300.0)
+    w.soil[1, 2:5] = [0.5, 3.0, 1e-4]          # alpha, n, Ks: fails at dt = 10 s
+    w.ebats = False
+    E = gpu_ensemble(w)
+    s, sm = E.run(w.t_end)
+    assert s == -5 and sm["failed"] == 1
+    recs = compare(orc, w, E, range(w.ncol), w.t_end)
+    assert recs[1]["status"] == -5 and recs[0]["status"] == 0 and recs[2]["status"] == 0
+    assert recs[1]["t"] < w.t_end and recs[0]["t"] == w.t_end
+
+
+def test_step_budget_then_resume_is_bitwise_identical():
+    w = small_ensemble([80, 160, 320], seed=8)
+    E1 = gpu_ensemble(w)
+    assert E1.run(w.t_end)[0] == 0
+    E2 = gpu_ensemble(w)
+    E2.set_limits(7, 60.0)
+    s, sm = E2.run(w.t_end)
+    assert s == -5 and sm["failed"] == 0 and sm["t_min"] < w.t_end
+    assert all(r["accepted"] + r["rejected"] <= 7 for r in E2.columns())
+    E2.set_limits(10 ** 8, 60.0)
+    assert E2.run(w.t_end)[0] == 0
+    assert torch.equal(E1.get_state(), E2.get_state())
+    c1, c2 = E1.columns(), E2.columns()
+    assert [(r["accepted"], r["picard_total"]) for r in c1] == \
+        [(r["accepted"], r["picard_total"]) for r in c2]
+
+
+def test_autotune_keeps_the_state_and_results():
+    w = small_ensemble(list(range(40, 440, 25)), seed=9, t_end=300.0)
+    E1 = gpu_ensemble(w)
+    assert E1.run(w.t_end)[0] == 0
+    E2 = gpu_ensemble(w)
+    h0 = E2.get_state().clone()
+    s, tile = E2.autotune(60.0)
+    assert s == 0, E2.last_error()
+    assert tile == E2.get_tile() and tile[0] in (1, 2, 4, 8)
+    assert torch.equal(E2.get_state(), h0)
+    assert all(r["accepted"] == 0 for r in E2.columns())
+    assert E2.run(w.t_end)[0] == 0
+    assert torch.equal(E1.get_state(), E2.get_state())
+
+
+def test_mixed_precision_solve(orc):
+    """FP32 tridiagonal solves under FP64 Picard refinement, fixed steps on
+    benign columns: heads within 10 tol_picard of the FP64 oracle, Picard
+    counts within one per step on average (totals within the step count)."""
+    w = small_ensemble([50, 64, 65, 150, 300, 448], seed=11, t_end=300.0, ks_max=-6.0)
+    w.ebats = False
+    E = gpu_ensemble(w, precision=1)
+    s, sm = E.run(w.t_end)
+    assert s == 0, E.last_error()
+    h = E.get_state().cpu().numpy()
+    recs = E.columns()
+    for c in range(w.ncol):
+        so, rs, h_o, mb = oracle_column(orc, w, c, w.t_end)
+        assert so == 0
+        L = w.lengths[c]
+        o = w.offsets[c]
+        assert np.abs(h[o:o + L] - h_o).max() <= 1e-5, c
+        assert abs(recs[c]["picard_total"] - rs["picard_total"]) <= rs["accepted"], c
+        assert recs[c]["storage"] == pytest.approx(mb["storage"], rel=1e-6)
+
+
+def test_bench_size_ensemble_sampled(orc):
+    """The 4096-column ensemble in the benchmark's launch shape over 120 s,
+    32 sampled columns against the oracle."""
+    w = W.ensemble(t_end=120.0)
+    E = gpu_ensemble(w)
+    s, sm = E.run(w.t_end)
+    assert s == 0, E.last_error()
+    assert sm["failed"] == 0 and sm["t_min"] == w.t_end
+    rng = np.random.default_rng(0)
+    compare(orc, w, E, sorted(rng.choice(w.ncol, 32, replace=False)), w.t_end)
+
+
+def test_error_paths():
+    lengths = np.array([10, 20], np.int32)
+    soil = np.tile([0.1, 0.4, 2.0, 1.5, 1e-6, 1e-5], (2, 1))
+    with pytest.raises(Exception):
+        Ensemble(np.array([0, 20], np.int32), 0.01, soil)          # length 0
+    with pytest.raises(Exception):
+        Ensemble(np.array([10, 449], np.int32), 0.01, soil)        # beyond the limit
+    bad = soil.copy()
+    bad[1, 3] = 1.0                                                 # n must exceed 1
+    with pytest.raises(Exception):
+        Ensemble(lengths, 0.01, bad)
+    E = Ensemble(lengths, 0.01, soil)
+    assert E.L.rf_ens_run(E.h, 1.0, None) == -2                     # before a state
+    E.bind()
+    h = torch.full((30,), -1.0, dtype=torch.float64, device="cuda")
+    h[12] = float("nan")
+    assert E.set_state(h) == -7
+    h[12] = -1.0
+    assert E.set_state(h) == 0
