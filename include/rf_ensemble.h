@@ -113,9 +113,8 @@ rf_status rf_ens_get_state(const rf_ens *e, double *h_dev);
 /* Advances every column from its own time to t_end in ONE persistent kernel
  * launch: each wavefront takes a column from the queue and runs its whole
  * time loop (steps, Picard iterations, EBATS) with the column held in
- * registers.  The launch sequence (queue reset, the run, the summary) is
- * captured once into a HIP graph and replayed.  A column that fails keeps
- * its last accepted state and its status; the others go on.  Returns
+ * registers.  A column that fails keeps its last accepted state and its
+ * status; the others go on.  Returns
  * RF_ERR_NOT_CONVERGED or RF_ERR_NONFINITE if any column failed (the
  * summary says how many), RF_OK otherwise.  *out may be NULL. */
 rf_status rf_ens_run(rf_ens *e, double t_end, rf_ens_summary *out);

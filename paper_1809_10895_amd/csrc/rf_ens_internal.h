@@ -28,8 +28,7 @@ struct EnsOpt {
     double bc_value[2];
 };
 
-// Values the host hands to one run through pinned memory (a graph node
-// copies them to the device at each replay).
+// Bounds of one run (kernel arguments).
 struct EnsRunParams {
     double t_end;
     long long max_steps;    // accepted + rejected steps per column and run
@@ -45,7 +44,6 @@ struct EnsArrays {
     int32_t *order;         // [ncol] queue order (decreasing length)
     rf_ens_column *col;     // [ncol] per-column state and counters
     rf_ens_summary *sum;    // totals of the last run
-    EnsRunParams *run;      // parameters of the run in flight
     unsigned int *queue;    // next queue position
     long long *t0;          // wall clock at the start of the run
     double *h_bak;          // autotuner: copy of h
@@ -55,8 +53,8 @@ struct EnsArrays {
 hipError_t launch_ens_init(const EnsArrays &a, int ncol, const EnsOpt &o, double t, hipStream_t s);
 hipError_t launch_ens_check(const EnsArrays &a, long ncell, hipStream_t s);
 hipError_t launch_ens_reset(const EnsArrays &a, hipStream_t s);
-hipError_t launch_ens_run(const EnsArrays &a, int ncol, const EnsOpt &o, bool mixed,
-                          int nblocks, int waves_per_block, hipStream_t s);
+hipError_t launch_ens_run(const EnsArrays &a, int ncol, const EnsOpt &o, const EnsRunParams &rp,
+                          bool mixed, int nblocks, int waves_per_block, hipStream_t s);
 hipError_t launch_ens_summary(const EnsArrays &a, int ncol, hipStream_t s);
 // Largest dynamic occupancy (blocks per CU) of the run kernel for a block size.
 int ens_max_blocks_per_cu(bool mixed, int waves_per_block);

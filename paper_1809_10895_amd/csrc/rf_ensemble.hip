@@ -387,10 +387,10 @@ __device__ void run_column(const EnsArrays &a, const EnsOpt &o, const EnsRunPara
 }
 
 template <typename TS>
-__global__ void __launch_bounds__(kEnsThreadsMax) k_ens_run(EnsArrays a, int ncol, EnsOpt o)
+__global__ void __launch_bounds__(kEnsThreadsMax) k_ens_run(EnsArrays a, int ncol, EnsOpt o,
+                                                            EnsRunParams rp)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const EnsRunParams rp = *a.run;
     const long long t0 = *a.t0;
     for (;;) {
         unsigned int q = 0;
@@ -537,16 +537,16 @@ hipError_t launch_ens_reset(const EnsArrays &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ens_run(const EnsArrays &a, int ncol, const EnsOpt &o, bool mixed, int nblocks,
-                          int waves_per_block, hipStream_t s)
+hipError_t launch_ens_run(const EnsArrays &a, int ncol, const EnsOpt &o, const EnsRunParams &rp,
+                          bool mixed, int nblocks, int waves_per_block, hipStream_t s)
 {
     if (waves_per_block < 1 || waves_per_block * kWave > kEnsThreadsMax || nblocks < 1)
         return hipErrorInvalidValue;
     const dim3 grid(nblocks), block(waves_per_block * kWave);
     if (mixed)
-        hipLaunchKernelGGL(k_ens_run<float>, grid, block, 0, s, a, ncol, o);
+        hipLaunchKernelGGL(k_ens_run<float>, grid, block, 0, s, a, ncol, o, rp);
     else
-        hipLaunchKernelGGL(k_ens_run<double>, grid, block, 0, s, a, ncol, o);
+        hipLaunchKernelGGL(k_ens_run<double>, grid, block, 0, s, a, ncol, o, rp);
     return hipGetLastError();
 }
 

@@ -2,11 +2,9 @@
 //
 // The host validates the column table, lays out the caller's workspace,
 // orders the queue (decreasing length) and launches runs.  A run is four
-// stream operations -- copy the run parameters from pinned host memory,
-// reset the queue, the persistent kernel, the summary kernel, copy the
-// summary back -- captured once into a HIP graph on a private capture
-// stream and replayed on the caller's stream; options, tile or workspace
-// changes drop the graph.
+// stream operations on the caller's stream: reset the queue, the persistent
+// kernel (run bounds as kernel arguments), the summary kernel, and the copy
+// of the summary to pinned host memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +29,6 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct rf_ens {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipStream_t cap = nullptr;      // private stream the graph is captured on
     char err[512] = {0};
 
     bool have_setup = false, have_ws = false, have_state = false;
@@ -54,10 +51,7 @@ struct rf_ens {
     size_t ws_bytes = 0;
     EnsArrays A{};
 
-    EnsRunParams *hrun = nullptr;    // pinned
     rf_ens_summary *hsum = nullptr;  // pinned
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     int n_cu = 0;
     double tick_hz = 1e8;
 };
@@ -76,14 +70,6 @@ static rf_status efail(rf_ens *e, rf_status s, const char *fmt, ...)
         hipError_t r_ = (call);                                                            \
         if (r_ != hipSuccess) return efail(e, RF_ERR_HIP, "%s: %s", #call, hipGetErrorString(r_)); \
     } while (0)
-
-static void drop_graph(rf_ens *e)
-{
-    if (e->exec) (void)hipGraphExecDestroy(e->exec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->exec = nullptr;
-    e->graph = nullptr;
-}
 
 static EnsOpt make_opt(const rf_ens *e)
 {
@@ -127,7 +113,6 @@ static size_t ens_layout(const rf_ens *e, char *base, EnsArrays *A)
     a.order = (int32_t *)take(nc * sizeof(int32_t));
     a.col = (rf_ens_column *)take(nc * sizeof(rf_ens_column));
     a.sum = (rf_ens_summary *)take(sizeof(rf_ens_summary));
-    a.run = (EnsRunParams *)take(sizeof(EnsRunParams));
     a.queue = (unsigned int *)take(sizeof(unsigned int));
     a.t0 = (long long *)take(sizeof(long long));
     a.h_bak = (double *)take(ncell * sizeof(double));
@@ -145,33 +130,6 @@ static int blocks_for(const rf_ens *e, int waves_per_block, int blocks_per_cu)
     return std::max(1, per_cu * e->n_cu);
 }
 
-static rf_status build_graph(rf_ens *e)
-{
-    drop_graph(e);
-    const bool mixed = e->opt.precision == RF_PREC_MIXED;
-    const EnsOpt o = make_opt(e);
-    const int nblk = blocks_for(e, e->tile.waves_per_block, e->tile.blocks_per_cu);
-    EHIP(e, hipStreamBeginCapture(e->cap, hipStreamCaptureModeRelaxed));
-    hipError_t r = hipMemcpyAsync(e->A.run, e->hrun, sizeof(EnsRunParams), hipMemcpyHostToDevice,
-                                  e->cap);
-    if (r == hipSuccess) r = launch_ens_reset(e->A, e->cap);
-    if (r == hipSuccess)
-        r = launch_ens_run(e->A, e->ncol, o, mixed, nblk, e->tile.waves_per_block, e->cap);
-    if (r == hipSuccess) r = launch_ens_summary(e->A, e->ncol, e->cap);
-    if (r == hipSuccess)
-        r = hipMemcpyAsync(e->hsum, e->A.sum, sizeof(rf_ens_summary), hipMemcpyDeviceToHost, e->cap);
-    hipGraph_t g = nullptr;
-    const hipError_t r2 = hipStreamEndCapture(e->cap, &g);
-    if (r != hipSuccess || r2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return efail(e, RF_ERR_HIP, "graph capture: %s",
-                     hipGetErrorString(r != hipSuccess ? r : r2));
-    }
-    e->graph = g;
-    EHIP(e, hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0));
-    return RF_OK;
-}
-
 extern "C" {
 
 rf_status rf_ens_create(rf_ens **out, int hip_device, void *hip_stream)
@@ -187,11 +145,7 @@ rf_status rf_ens_create(rf_ens **out, int hip_device, void *hip_stream)
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&e->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, hip_device) != hipSuccess ||
-        hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void **)&e->hrun, sizeof(EnsRunParams), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&e->hsum, sizeof(rf_ens_summary), hipHostMallocDefault) != hipSuccess) {
-        if (e->hrun) (void)hipHostFree(e->hrun);
-        if (e->cap) (void)hipStreamDestroy(e->cap);
         delete e;
         return RF_ERR_HIP;
     }
@@ -204,10 +158,7 @@ rf_status rf_ens_destroy(rf_ens *e)
 {
     if (!e) return RF_ERR_ARG;
     (void)hipSetDevice(e->device);
-    drop_graph(e);
-    if (e->hrun) (void)hipHostFree(e->hrun);
     if (e->hsum) (void)hipHostFree(e->hsum);
-    if (e->cap) (void)hipStreamDestroy(e->cap);
     delete e;
     return RF_OK;
 }
@@ -234,7 +185,6 @@ rf_status rf_ens_setup(rf_ens *e, int ncol, const int32_t *len, double dz, int m
         sp[c].ks = ks;
         sp[c].pad = 0.0;
     }
-    drop_graph(e);
     e->ncol = ncol;
     e->len.assign(len, len + ncol);
     e->off.resize(ncol);
@@ -266,7 +216,6 @@ rf_status rf_ens_set_bc(rf_ens *e, int face, int type, double value)
     const int f = face == RF_ZMAX ? 1 : 0;
     e->bc_type[f] = type;
     e->bc_value[f] = value;
-    drop_graph(e);
     return RF_OK;
 }
 
@@ -280,7 +229,6 @@ rf_status rf_ens_set_options(rf_ens *e, const rf_options *o)
         (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED))
         return efail(e, RF_ERR_ARG, "invalid options");
     e->opt = *o;
-    drop_graph(e);
     return RF_OK;
 }
 
@@ -291,7 +239,6 @@ rf_status rf_ens_set_tile(rf_ens *e, const rf_ens_tile *t)
     if ((w != 1 && w != 2 && w != 4 && w != 8) || t->blocks_per_cu < 0 || t->blocks_per_cu > 16)
         return efail(e, RF_ERR_ARG, "invalid tile");
     e->tile = *t;
-    drop_graph(e);
     return RF_OK;
 }
 
@@ -337,7 +284,6 @@ rf_status rf_ens_bind_workspace(rf_ens *e, void *dev, size_t bytes)
     const size_t need = ens_layout(e, nullptr, nullptr);
     if (bytes < need) return efail(e, RF_ERR_NOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
     EHIP(e, hipSetDevice(e->device));
-    drop_graph(e);
     ens_layout(e, (char *)dev, &e->A);
     e->ws = dev;
     e->ws_bytes = bytes;
@@ -390,14 +336,18 @@ rf_status rf_ens_get_state(const rf_ens *ce, double *h_dev)
 
 static rf_status ens_run(rf_ens *e, double t_end, rf_ens_summary *out)
 {
-    if (!e->exec) {
-        rf_status s = build_graph(e);
-        if (s) return s;
-    }
-    e->hrun->t_end = t_end;
-    e->hrun->max_steps = e->max_steps;
-    e->hrun->max_ticks = (long long)(e->max_seconds * e->tick_hz);
-    EHIP(e, hipGraphLaunch(e->exec, e->stream));
+    const bool mixed = e->opt.precision == RF_PREC_MIXED;
+    const int nblk = blocks_for(e, e->tile.waves_per_block, e->tile.blocks_per_cu);
+    EnsRunParams rp;
+    rp.t_end = t_end;
+    rp.max_steps = e->max_steps;
+    rp.max_ticks = (long long)(e->max_seconds * e->tick_hz);
+    EHIP(e, launch_ens_reset(e->A, e->stream));
+    EHIP(e, launch_ens_run(e->A, e->ncol, make_opt(e), rp, mixed, nblk, e->tile.waves_per_block,
+                           e->stream));
+    EHIP(e, launch_ens_summary(e->A, e->ncol, e->stream));
+    EHIP(e, hipMemcpyAsync(e->hsum, e->A.sum, sizeof(rf_ens_summary), hipMemcpyDeviceToHost,
+                           e->stream));
     EHIP(e, hipStreamSynchronize(e->stream));
     const rf_ens_summary sm = *e->hsum;
     if (out) *out = sm;
@@ -459,8 +409,7 @@ rf_status rf_ens_autotune(rf_ens *e, double t_span, rf_ens_tile *best)
         if (fit > 0 && fit <= 16 && (fit & (fit - 1)) != 0) per_cu.push_back(fit);
         for (int pc : per_cu) {
             e->tile = rf_ens_tile{w, pc};
-            drop_graph(e);
-            if (hipEventRecord(a, e->stream) != hipSuccess) { st = RF_ERR_HIP; break; }
+                    if (hipEventRecord(a, e->stream) != hipSuccess) { st = RF_ERR_HIP; break; }
             rf_status s = ens_run(e, t_start + t_span, nullptr);
             if (hipEventRecord(b, e->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
                 st = RF_ERR_HIP;
@@ -484,7 +433,6 @@ rf_status rf_ens_autotune(rf_ens *e, double t_span, rf_ens_tile *best)
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    drop_graph(e);
     if (st) {
         e->tile = saved;
         return efail(e, st, "autotune: HIP error");
