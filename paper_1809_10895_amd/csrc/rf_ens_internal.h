@@ -45,7 +45,6 @@ struct EnsArrays {
     rf_ens_column *col;     // [ncol] per-column state and counters
     rf_ens_summary *sum;    // totals of the last run
     unsigned int *queue;    // next queue position
-    long long *t0;          // wall clock at the start of the run
     double *h_bak;          // autotuner: copy of h
     rf_ens_column *col_bak; // autotuner: copy of the column records
 };

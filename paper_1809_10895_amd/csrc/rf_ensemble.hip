@@ -391,7 +391,9 @@ __global__ void __launch_bounds__(kEnsThreadsMax) k_ens_run(EnsArrays a, int nco
                                                             EnsRunParams rp)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const long long t0 = *a.t0;
+    // the run's wall-clock budget counts from this wavefront's start (the
+    // persistent grid is sized to be resident at once)
+    const long long t0 = wall_clock64();
     for (;;) {
         unsigned int q = 0;
         if (lane == 0) q = atomicAdd(a.queue, 1u);
@@ -454,13 +456,10 @@ __global__ void __launch_bounds__(1024) k_ens_check(EnsArrays a, long ncell)
     if (threadIdx.x == 0) a.queue[0] = cnt;
 }
 
-// Start of a run: queue position 0 and the wall clock.
+// Start of a run: queue position 0.
 __global__ void k_ens_reset(EnsArrays a)
 {
-    if (threadIdx.x == 0) {
-        a.queue[0] = 0u;
-        a.t0[0] = wall_clock64();
-    }
+    if (threadIdx.x == 0) a.queue[0] = 0u;
 }
 
 // Totals over the column records (one block of 256 threads).

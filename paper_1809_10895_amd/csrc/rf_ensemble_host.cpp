@@ -114,7 +114,6 @@ static size_t ens_layout(const rf_ens *e, char *base, EnsArrays *A)
     a.col = (rf_ens_column *)take(nc * sizeof(rf_ens_column));
     a.sum = (rf_ens_summary *)take(sizeof(rf_ens_summary));
     a.queue = (unsigned int *)take(sizeof(unsigned int));
-    a.t0 = (long long *)take(sizeof(long long));
     a.h_bak = (double *)take(ncell * sizeof(double));
     a.col_bak = (rf_ens_column *)take(nc * sizeof(rf_ens_column));
     if (A) *A = a;
