@@ -120,10 +120,20 @@ static size_t ens_layout(const rf_ens *e, char *base, EnsArrays *A)
     return off;
 }
 
+// Occupancy of the run kernel per (precision, waves per block), queried once
+// per process.
+static int occupancy(bool mixed, int waves_per_block)
+{
+    static int cache[2][9] = {};
+    int &v = cache[mixed ? 1 : 0][waves_per_block & 7 ? waves_per_block : 8];
+    if (v == 0) v = std::max(1, ens_max_blocks_per_cu(mixed, waves_per_block));
+    return v;
+}
+
 static int blocks_for(const rf_ens *e, int waves_per_block, int blocks_per_cu)
 {
     const bool mixed = e->opt.precision == RF_PREC_MIXED;
-    int fit = ens_max_blocks_per_cu(mixed, waves_per_block);
+    int fit = occupancy(mixed, waves_per_block);
     if (fit < 1) fit = 1;
     const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, fit) : fit;
     return std::max(1, per_cu * e->n_cu);
@@ -402,7 +412,7 @@ rf_status rf_ens_autotune(rf_ens *e, double t_span, rf_ens_tile *best)
     EHIP(e, hipEventCreate(&b));
     rf_status st = RF_OK;
     for (int w : kWaves) {
-        const int fit = ens_max_blocks_per_cu(e->opt.precision == RF_PREC_MIXED, w);
+        const int fit = occupancy(e->opt.precision == RF_PREC_MIXED, w);
         std::vector<int> per_cu;
         for (int pc = 1; pc <= std::min(fit, 16); pc *= 2) per_cu.push_back(pc);
         if (fit > 0 && fit <= 16 && (fit & (fit - 1)) != 0) per_cu.push_back(fit);
