@@ -4,6 +4,6 @@ the column ensemble of include/rf_ensemble.h.
 
     from paper_1809_10895_amd import Solver, Ensemble, workloads
 """
-from .binding import (Ensemble, RF_DIRICHLET, RF_FLUX, RF_FREE_DRAINAGE, RF_GARDNER, RF_NOFLOW,  # noqa: F401
+from .binding import (Ensemble, Guess, RF_DIRICHLET, RF_FLUX, RF_FREE_DRAINAGE, RF_GARDNER, RF_NOFLOW,  # noqa: F401
                       RF_PRECOND_JACOBI, RF_PRECOND_ZLINE, RF_VGM, RF_XMAX, RF_XMIN, RF_YMAX,
                       RF_YMIN, RF_ZMAX, RF_ZMIN, RfError, Solver, default_options, load_library)

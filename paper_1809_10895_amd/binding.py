@@ -39,7 +39,12 @@ EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf
            "rf_ens_create", "rf_ens_destroy", "rf_ens_last_error", "rf_ens_setup", "rf_ens_set_bc",
            "rf_ens_set_options", "rf_ens_set_tile", "rf_ens_set_limits", "rf_ens_get_tile",
            "rf_ens_cells", "rf_ens_workspace_bytes", "rf_ens_bind_workspace", "rf_ens_set_state",
-           "rf_ens_get_state", "rf_ens_run", "rf_ens_get_columns", "rf_ens_autotune"]
+           "rf_ens_get_state", "rf_ens_run", "rf_ens_get_columns", "rf_ens_autotune",
+           # include/rf_guess.h
+           "rf_guess_create", "rf_guess_destroy", "rf_guess_last_error", "rf_guess_setup",
+           "rf_guess_workspace_bytes", "rf_guess_bind_workspace", "rf_guess_param_count",
+           "rf_guess_set_params", "rf_guess_get_params", "rf_guess_predict", "rf_guess_gradient",
+           "rf_guess_train_step"]
 RF_ENS_MAX_LEN = 448
 
 
@@ -153,8 +158,23 @@ def load_library(path: str = LIB):
     L.rf_ens_run.argtypes = [vp, dp, C.POINTER(RfEnsSummary)]
     L.rf_ens_get_columns.argtypes = [vp, C.POINTER(RfEnsColumn)]
     L.rf_ens_autotune.argtypes = [vp, dp, C.POINTER(RfEnsTile)]
+    L.rf_guess_create.argtypes = [C.POINTER(vp), ip, vp]
+    L.rf_guess_destroy.argtypes = [vp]
+    L.rf_guess_last_error.argtypes = [vp]
+    L.rf_guess_last_error.restype = C.c_char_p
+    L.rf_guess_setup.argtypes = [vp, ip, ip, ip, C.c_uint]
+    L.rf_guess_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.rf_guess_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    L.rf_guess_param_count.argtypes = []
+    L.rf_guess_param_count.restype = C.c_size_t
+    L.rf_guess_set_params.argtypes = [vp, vp]
+    L.rf_guess_get_params.argtypes = [vp, vp]
+    L.rf_guess_predict.argtypes = [vp, vp, vp, vp, dp, vp]
+    L.rf_guess_gradient.argtypes = [vp, vp, vp, vp, dp, vp, C.POINTER(C.c_double), vp]
+    L.rf_guess_train_step.argtypes = [vp, vp, vp, vp, dp, vp, dp, C.POINTER(C.c_double)]
     for name in EXPORTS:
-        if name not in ("rf_default_options", "rf_destroy", "rf_last_error", "rf_ens_last_error"):
+        if name not in ("rf_default_options", "rf_destroy", "rf_last_error", "rf_ens_last_error",
+                        "rf_guess_last_error", "rf_guess_param_count"):
             getattr(L, name).restype = C.c_int      # rf_status
     _lib = L
     return L
@@ -449,3 +469,72 @@ class Ensemble:
         t = RfEnsTile()
         s = self.L.rf_ens_autotune(self.h, float(t_span), C.byref(t))
         return s, (t.waves_per_block, t.blocks_per_cu)
+
+
+class Guess:
+    """The learned Picard initial guess (include/rf_guess.h) on one grid."""
+
+    def __init__(self, nx, ny, nz, seed=0, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        s = self.L.rf_guess_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if s != RF_OK:
+            raise RfError(s, "rf_guess_create failed")
+        self.h = h
+        self.N = nx * ny * nz
+        self.shape = (nx, ny, nz)
+        self._check(self.L.rf_guess_setup(self.h, nx, ny, nz, seed))
+        n = C.c_size_t()
+        self._check(self.L.rf_guess_workspace_bytes(self.h, C.byref(n)))
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._check(self.L.rf_guess_bind_workspace(self.h, _ptr(self.ws), n.value))
+        self.nparams = self.L.rf_guess_param_count()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.rf_guess_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _check(self, s):
+        if s != RF_OK:
+            raise RfError(s, self.L.rf_guess_last_error(self.h).decode())
+        return s
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == self.nparams
+        self._check(self.L.rf_guess_set_params(self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.nparams, np.float32)
+        self._check(self.L.rf_guess_get_params(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def predict(self, hn, hprev, lnks, rain, out=None):
+        if out is None:
+            out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.rf_guess_predict(self.h, _ptr(hn), _ptr(hprev), _ptr(lnks), float(rain),
+                                            _ptr(out)))
+        return out
+
+    def gradient(self, hn, hprev, lnks, rain, target):
+        import numpy as np
+        g = np.empty(self.nparams, np.float32)
+        loss = C.c_double()
+        self._check(self.L.rf_guess_gradient(self.h, _ptr(hn), _ptr(hprev), _ptr(lnks), float(rain),
+                                             _ptr(target), C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def train_step(self, hn, hprev, lnks, rain, target, lr):
+        loss = C.c_double()
+        self._check(self.L.rf_guess_train_step(self.h, _ptr(hn), _ptr(hprev), _ptr(lnks), float(rain),
+                                               _ptr(target), float(lr), C.byref(loss)))
+        return loss.value

@@ -1,0 +1,462 @@
+// HIP kernels (gfx950 / CDNA4) of the learned Picard guess: a four-layer
+// 3x3x3 convolutional network trained and evaluated on the matrix cores.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: the
+// output tile of one wavefront is 16 output channels x 64 cells (one z-run of
+// a column, cells z-fastest as in the solver), the reduction runs over taps
+// and input channels, 32 values per instruction (one tap of 32 channels, or
+// four taps of an 8-channel input).  Activations are channels-last BF16, so a
+// cell's 32 channels are one 64-byte row and the B operand of a step is one
+// coalesced 1 KB read per 16 cells; the packed weights of a layer (<= 55 KB)
+// sit in LDS for the whole block.  The backward pass reuses the same kernel
+// with transposed, tap-mirrored weights (the gradient with respect to a
+// layer's input) and a ReLU-mask epilogue; the weight gradient is a second
+// MFMA kernel whose reduction runs over cells, with LDS transposes of the
+// two channels-last operands, and per-chunk partials summed in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "rf_guess_internal.h"
+
+namespace rf {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNetThreads = 256;   // four wavefronts
+enum { EPI_RELU = 0, EPI_LAST = 1, EPI_MASK = 2 };
+
+// Neighbour of cell (i, j, k) through tap t = 9 (di+1) + 3 (dj+1) + (dk+1);
+// false outside the grid (zero padding).
+__device__ __forceinline__ bool tap_nbr(const NetGeo &g, int i, int j, int k, int t, long &cell)
+{
+    const int di = t / 9 - 1, dj = (t / 3) % 3 - 1, dk = t % 3 - 1;
+    const int ii = i + di, jj = j + dj, kk = k + dk;
+    cell = (long)kk + (long)g.nz * ((long)ii + (long)g.nx * jj);
+    return ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+}
+
+__device__ __forceinline__ bf16x8 zero8()
+{
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; e++) z[e] = (bf16)0.0f;
+    return z;
+}
+
+// One convolution layer.  CIN: stored input channels (8 or 32); COB: output
+// blocks of 16 channels (1 or 2).  EPI_RELU: out = bf16(relu(acc + bias));
+// EPI_LAST: outf = acc + bias of channel 0 (FP32); EPI_MASK: out =
+// bf16(acc) where mask > 0, else 0 (gradient through a ReLU).
+template <int CIN, int COB, int EPI>
+__global__ void __launch_bounds__(kNetThreads) k_conv(NetGeo g, const bf16 *__restrict__ in,
+                                                      const bf16 *__restrict__ wp,
+                                                      const float *__restrict__ bias,
+                                                      bf16 *__restrict__ out, float *__restrict__ outf,
+                                                      const bf16 *__restrict__ mask)
+{
+    constexpr int STEPS = packed_steps(CIN);
+    constexpr int NPK = STEPS * COB * 64;
+    __shared__ bf16x8 sW[NPK];
+    const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
+    for (int e = threadIdx.x; e < NPK; e += kNetThreads) sW[e] = wv[e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, q = lane >> 4;
+    const int wave = threadIdx.x >> 6;
+    for (int u = blockIdx.x * 4 + wave; u < g.units; u += gridDim.x * 4) {
+        const int col = u / g.zt, k0 = (u % g.zt) * 64;
+        const int i = col % g.nx, j = col / g.nx;
+        f32x4 acc[COB][4];
+#pragma unroll
+        for (int b = 0; b < COB; b++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int s = 0; s < STEPS; s++) {
+            bf16x8 A[COB];
+#pragma unroll
+            for (int b = 0; b < COB; b++) A[b] = sW[(s * COB + b) * 64 + lane];
+            const int tap = (CIN == 32) ? s : 4 * s + q;
+            const int cofs = (CIN == 32) ? 8 * q : 0;
+            bf16x8 B[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int k = k0 + 16 * t + n;
+                long nb = 0;
+                const bool ok = k < g.nz && tap < kTaps && tap_nbr(g, i, j, k, tap, nb);
+                B[t] = ok ? *reinterpret_cast<const bf16x8 *>(in + nb * CIN + cofs) : zero8();
+            }
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+#pragma unroll
+                for (int b = 0; b < COB; b++)
+                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b], B[t], acc[b][t], 0, 0, 0);
+        }
+        // lane holds rows 4q..4q+3 (output channels) of column n (cell)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int k = k0 + 16 * t + n;
+            if (k >= g.nz) continue;
+            const long cell = (long)col * g.nz + k;
+#pragma unroll
+            for (int b = 0; b < COB; b++) {
+                if (EPI == EPI_LAST) {
+                    if (b == 0 && q == 0) outf[cell] = acc[0][t][0] + bias[0];
+                    continue;
+                }
+                const int co0 = 16 * b + 4 * q;
+                bf16x4 o;
+                if (EPI == EPI_MASK) {
+                    const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(mask + cell * kHid + co0);
+#pragma unroll
+                    for (int v = 0; v < 4; v++)
+                        o[v] = (float)mk[v] > 0.f ? (bf16)acc[b][t][v] : (bf16)0.0f;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) o[v] = (bf16)fmaxf(acc[b][t][v] + bias[co0 + v], 0.f);
+                }
+                *reinterpret_cast<bf16x4 *>(out + cell * kHid + co0) = o;
+            }
+        }
+    }
+}
+
+// Weight gradient of one layer, one tap and one chunk of columns per
+// wavefront: D[co][ci] += sum over 32 cells of dz[cell][co] x[cell + tap][ci]
+// on the matrix cores, both operands transposed through LDS ([channel][cell]
+// rows, so that each lane reads 8 consecutive cells of one channel).
+// CIN / COUT: stored channels (8 or 32).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(64) k_wgrad(NetGeo g, const bf16 *__restrict__ x,
+                                              const bf16 *__restrict__ dz, float *__restrict__ part)
+{
+    constexpr int CB = (COUT == 32) ? 2 : 1;
+    constexpr int NB = (CIN == 32) ? 2 : 1;
+    constexpr int LD = 40;                    // row stride (bf16): 80 B keeps 16-byte alignment
+    __shared__ __attribute__((aligned(16))) bf16 sA[32 * LD];
+    __shared__ __attribute__((aligned(16))) bf16 sB[32 * LD];
+    const int tap = blockIdx.x % kTaps, chunk = blockIdx.x / kTaps;
+    const int lane = threadIdx.x;
+    const int n = lane & 15, q = lane >> 4;
+    // rows never written below (channels beyond the stored ones) stay zero
+    for (int e = lane; e < 32 * LD; e += 64) {
+        sA[e] = (bf16)0.0f;
+        sB[e] = (bf16)0.0f;
+    }
+    __syncthreads();
+    f32x4 acc[CB][NB];
+#pragma unroll
+    for (int b = 0; b < CB; b++)
+#pragma unroll
+        for (int c = 0; c < NB; c++) acc[b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int c0 = chunk * g.cols_per_chunk;
+    const int c1 = min(c0 + g.cols_per_chunk, g.ncol);
+    const int zc = lane >> 1, half = lane & 1;
+    for (int col = c0; col < c1; col++) {
+        const int i = col % g.nx, j = col / g.nx;
+        for (int z0 = 0; z0 < g.nz; z0 += 32) {
+            const int z = z0 + zc;
+            const bool okc = z < g.nz;
+            const long cell = (long)col * g.nz + z;
+            long nb = 0;
+            const bool okn = okc && tap_nbr(g, i, j, z, tap, nb);
+            // dz rows: 16 channels per lane (32 stored) or 8 (lane half 0)
+            if (COUT == 32) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const bf16x8 v = okc ? *reinterpret_cast<const bf16x8 *>(dz + cell * 32 + 16 * half + 8 * h)
+                                         : zero8();
+#pragma unroll
+                    for (int e = 0; e < 8; e++) sA[(16 * half + 8 * h + e) * LD + zc] = v[e];
+                }
+            } else if (half == 0) {
+                const bf16x8 v = okc ? *reinterpret_cast<const bf16x8 *>(dz + cell * 8) : zero8();
+#pragma unroll
+                for (int e = 0; e < 8; e++) sA[e * LD + zc] = v[e];
+            }
+            if (CIN == 32) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const bf16x8 v = okn ? *reinterpret_cast<const bf16x8 *>(x + nb * 32 + 16 * half + 8 * h)
+                                         : zero8();
+#pragma unroll
+                    for (int e = 0; e < 8; e++) sB[(16 * half + 8 * h + e) * LD + zc] = v[e];
+                }
+            } else if (half == 0) {
+                const bf16x8 v = okn ? *reinterpret_cast<const bf16x8 *>(x + nb * 8) : zero8();
+#pragma unroll
+                for (int e = 0; e < 8; e++) sB[e * LD + zc] = v[e];
+            }
+            __syncthreads();
+            bf16x8 A[CB], B[NB];
+#pragma unroll
+            for (int b = 0; b < CB; b++) A[b] = *reinterpret_cast<const bf16x8 *>(&sA[(16 * b + n) * LD + 8 * q]);
+#pragma unroll
+            for (int c = 0; c < NB; c++) B[c] = *reinterpret_cast<const bf16x8 *>(&sB[(16 * c + n) * LD + 8 * q]);
+#pragma unroll
+            for (int b = 0; b < CB; b++)
+#pragma unroll
+                for (int c = 0; c < NB; c++)
+                    acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b], B[c], acc[b][c], 0, 0, 0);
+            __syncthreads();
+        }
+    }
+    float *P = part + ((long)chunk * kTaps + tap) * 1024;
+#pragma unroll
+    for (int b = 0; b < CB; b++)
+#pragma unroll
+        for (int c = 0; c < NB; c++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) P[(16 * b + 4 * q + v) * 32 + 16 * c + n] = acc[b][c][v];
+}
+
+// dW of layer l in the parameter layout, summing the chunk partials in order.
+__global__ void k_wreduce(NetGeo g, const float *__restrict__ part, float *__restrict__ grad, int woff,
+                          int cin, int cout)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = cout * kTaps * cin;
+    if (e >= n) return;
+    const int ci = e % cin, tap = (e / cin) % kTaps, co = e / (cin * kTaps);
+    float s = 0.f;
+    for (int ch = 0; ch < g.chunks; ch++) s += part[((long)ch * kTaps + tap) * 1024 + co * 32 + ci];
+    grad[woff + e] = s;
+}
+
+// Bias gradient partials: block b sums its cells for every channel.
+template <int COUT>
+__global__ void __launch_bounds__(256) k_bgrad(NetGeo g, const bf16 *__restrict__ dz,
+                                               float *__restrict__ bpart)
+{
+    __shared__ float s[256];
+    const int ch = threadIdx.x & 31, sub = threadIdx.x >> 5;   // 8 cell lanes per channel
+    float acc = 0.f;
+    if (ch < COUT)
+        for (long c = (long)blockIdx.x * 8 + sub; c < g.ncell; c += (long)gridDim.x * 8)
+            acc += (float)dz[c * COUT + ch];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.f;
+        for (int k = 0; k < 8; k++) t += s[k * 32 + threadIdx.x];
+        bpart[blockIdx.x * 32 + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_breduce(const float *__restrict__ bpart, int nblk, float *__restrict__ grad, int boff,
+                          int cout)
+{
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    float t = 0.f;
+    for (int b = 0; b < nblk; b++) t += bpart[b * 32 + co];
+    grad[boff + co] = t;
+}
+
+// Features of every cell (channels 4..7 zero).
+__global__ void k_features(NetGeo g, const double *__restrict__ hn, const double *__restrict__ hp,
+                           const double *__restrict__ lnks, double rain, bf16 *__restrict__ feat)
+{
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    bf16x8 f = zero8();
+    f[0] = (bf16)(float)(hn[c] / kHScale);
+    f[1] = (bf16)(float)((hn[c] - hp[c]) * kDhScale);
+    f[2] = (bf16)(float)(lnks ? lnks[c] : 0.0);
+    f[3] = (bf16)(float)(rain * kRainScale);
+    *reinterpret_cast<bf16x8 *>(feat + c * kFeat) = f;
+}
+
+__global__ void k_output(NetGeo g, const float *__restrict__ y, const double *__restrict__ hn,
+                         double *__restrict__ guess)
+{
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.ncell) return;
+    guess[c] = hn[c] + kOutScale * (double)y[c];
+}
+
+// r = h^n + 0.01 y - target; loss partials of 0.5 r^2 / N; dz3 = 0.01 r / N.
+__global__ void __launch_bounds__(256) k_loss(NetGeo g, const float *__restrict__ y,
+                                              const double *__restrict__ hn,
+                                              const double *__restrict__ target, bf16 *__restrict__ dz3,
+                                              double *__restrict__ lpart)
+{
+    __shared__ double s[256];
+    const double inv = 1.0 / (double)g.ncell;
+    double acc = 0.0;
+    for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < g.ncell; c += (long)gridDim.x * 256) {
+        const double r = hn[c] + kOutScale * (double)y[c] - target[c];
+        acc += 0.5 * r * r * inv;
+        bf16x8 d = zero8();
+        d[0] = (bf16)(float)(kOutScale * r * inv);
+        *reinterpret_cast<bf16x8 *>(dz3 + c * 8) = d;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = s[0];
+}
+
+// Packed BF16 operand of layer l (see packed_size).  Forward: A[m][k] =
+// W_l[oc = 16 b + m][tap][ic]; backward (gradient with respect to the layer
+// input): the transposed, tap-mirrored W_l[co = ic][26 - tap][ci = oc].
+__global__ void k_pack(const float *__restrict__ p, bf16 *__restrict__ dst, int l, int backward,
+                       int cin_stored, int cob)
+{
+    const int steps = (cin_stored == 32) ? kTaps : (kTaps + 3) / 4;
+    const int total = steps * cob * 64 * 8;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int jj = e % 8, lane = (e / 8) % 64, b = (e / 512) % cob, s = e / (512 * cob);
+    const int m = lane % 16, kq = lane / 16;
+    const int oc = 16 * b + m;
+    int tap, ic;
+    if (cin_stored == 32) {
+        tap = s;
+        ic = 8 * kq + jj;
+    } else {
+        tap = 4 * s + kq;
+        ic = jj;
+    }
+    float w = 0.f;
+    const int cin = kCin[l], cout = kCout[l];
+    if (tap < kTaps) {
+        if (!backward) {
+            if (oc < cout && ic < cin) w = p[param_w(l) + (oc * kTaps + tap) * cin + ic];
+        } else {
+            if (ic < cout && oc < cin) w = p[param_w(l) + (ic * kTaps + (kTaps - 1 - tap)) * cin + oc];
+        }
+    }
+    dst[e] = (bf16)w;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float bc1, float bc2)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gi = g[e];
+    const float mi = 0.9f * m[e] + 0.1f * gi;
+    const float vi = 0.999f * v[e] + 0.001f * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    p[e] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+int conv_grid(const NetGeo &g)
+{
+    const int need = (g.units + 3) / 4;
+    return need < 1024 ? (need < 1 ? 1 : need) : 1024;
+}
+
+}  // namespace
+
+hipError_t net_pack(const NetArrays &a, hipStream_t s)
+{
+    const int cin_f[kNetLayers] = {8, 32, 32, 32}, cob_f[kNetLayers] = {2, 2, 2, 1};
+    const int cin_b[kNetLayers] = {0, 32, 32, 8};
+    for (int l = 0; l < kNetLayers; l++) {
+        int total = packed_size(cin_f[l], cob_f[l]);
+        hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, a.p, a.wf[l], l, 0,
+                           cin_f[l], cob_f[l]);
+        if (l > 0) {
+            total = packed_size(cin_b[l], 2);
+            hipLaunchKernelGGL(k_pack, dim3((total + 255) / 256), dim3(256), 0, s, a.p, a.wb[l], l, 1,
+                               cin_b[l], 2);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t net_features(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
+                        const double *lnks, double rain, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g, hn, hprev,
+                       lnks, rain, a.feat);
+    return hipGetLastError();
+}
+
+hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s)
+{
+    const dim3 grid(conv_grid(g)), block(kNetThreads);
+    hipLaunchKernelGGL((k_conv<8, 2, EPI_RELU>), grid, block, 0, s, g, a.feat, a.wf[0], a.p + param_b(0),
+                       a.act[0], nullptr, nullptr);
+    hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[0], a.wf[1],
+                       a.p + param_b(1), a.act[1], nullptr, nullptr);
+    hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[1], a.wf[2],
+                       a.p + param_b(2), a.act[2], nullptr, nullptr);
+    hipLaunchKernelGGL((k_conv<32, 1, EPI_LAST>), grid, block, 0, s, g, a.act[2], a.wf[3],
+                       a.p + param_b(3), nullptr, a.y, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t net_output(const NetGeo &g, const NetArrays &a, const double *hn, double *guess, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_output, dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g, a.y, hn,
+                       guess);
+    return hipGetLastError();
+}
+
+hipError_t net_loss(const NetGeo &g, const NetArrays &a, const double *hn, const double *target,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss, dim3(a.lblocks), dim3(256), 0, s, g, a.y, hn, target, a.dz3, a.lpart);
+    return hipGetLastError();
+}
+
+static hipError_t grads_of_layer(const NetGeo &g, const NetArrays &a, int l, const bf16 *x,
+                                 const bf16 *dz, hipStream_t s)
+{
+    const dim3 wg(g.chunks * kTaps);
+    if (l == 0)
+        hipLaunchKernelGGL((k_wgrad<8, 32>), wg, dim3(64), 0, s, g, x, dz, a.part);
+    else if (l == 3)
+        hipLaunchKernelGGL((k_wgrad<32, 8>), wg, dim3(64), 0, s, g, x, dz, a.part);
+    else
+        hipLaunchKernelGGL((k_wgrad<32, 32>), wg, dim3(64), 0, s, g, x, dz, a.part);
+    const int nw = kCout[l] * kTaps * kCin[l];
+    hipLaunchKernelGGL(k_wreduce, dim3((nw + 255) / 256), dim3(256), 0, s, g, a.part, a.g, param_w(l),
+                       kCin[l], kCout[l]);
+    constexpr int kBBlocks = 256;
+    float *bpart = a.part;   // reused after the weight reduction
+    if (l == 3)
+        hipLaunchKernelGGL((k_bgrad<8>), dim3(kBBlocks), dim3(256), 0, s, g, dz, bpart);
+    else
+        hipLaunchKernelGGL((k_bgrad<32>), dim3(kBBlocks), dim3(256), 0, s, g, dz, bpart);
+    hipLaunchKernelGGL(k_breduce, dim3(1), dim3(32), 0, s, bpart, kBBlocks, a.g, param_b(l), kCout[l]);
+    return hipGetLastError();
+}
+
+hipError_t net_backward(const NetGeo &g, const NetArrays &a, hipStream_t s)
+{
+    const dim3 grid(conv_grid(g)), block(kNetThreads);
+    hipError_t e;
+    // layer 4 (index 3): input a3, output gradient dz3
+    if ((e = grads_of_layer(g, a, 3, a.act[2], a.dz3, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_conv<8, 2, EPI_MASK>), grid, block, 0, s, g, a.dz3, a.wb[3], nullptr, a.dz[0],
+                       nullptr, a.act[2]);
+    // layer 3 (index 2): input a2, output gradient dz[0]
+    if ((e = grads_of_layer(g, a, 2, a.act[1], a.dz[0], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_conv<32, 2, EPI_MASK>), grid, block, 0, s, g, a.dz[0], a.wb[2], nullptr,
+                       a.dz[1], nullptr, a.act[1]);
+    // layer 2 (index 1): input a1, output gradient dz[1]
+    if ((e = grads_of_layer(g, a, 1, a.act[0], a.dz[1], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_conv<32, 2, EPI_MASK>), grid, block, 0, s, g, a.dz[1], a.wb[1], nullptr,
+                       a.dz[0], nullptr, a.act[0]);
+    // layer 1 (index 0): input features, output gradient dz[0]
+    return grads_of_layer(g, a, 0, a.feat, a.dz[0], s);
+}
+
+hipError_t net_adam(const NetArrays &a, float lr, float bc1, float bc2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, a.p, a.g, a.m, a.v, kParams,
+                       lr, bc1, bc2);
+    return net_pack(a, s);
+}
+
+}  // namespace rf

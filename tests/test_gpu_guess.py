@@ -1,0 +1,93 @@
+"""GPU checks of the learned Picard guess (include/rf_guess.h): the MFMA
+forward pass and the hand-written gradients against the CPU reference
+(oracle/guess_net.py, with the same BF16 roundings), training, and what a
+trained network gains over plain Picard on held-out seeds."""
+import numpy as np
+import pytest
+
+from oracle import guess_net as R
+from paper_1809_10895_amd import learned
+from paper_1809_10895_amd.binding import Guess
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def sample(shape, seed):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(shape))
+    hn = rng.uniform(-3.0, -0.2, N)
+    hp = hn - rng.normal(0, 0.02, N)
+    lnks = rng.normal(0, 1, N)
+    target = hn + rng.normal(0, 0.01, N)
+    return hn, hp, lnks, target
+
+
+# 70 cells in z: one full 64-cell tile and a ragged one; 11 x 9 columns
+SHAPE = (11, 9, 70)
+
+
+def test_forward_matches_reference():
+    p = R.init_params(seed=5, scale_out=1.0).astype(np.float32)
+    hn, hp, lnks, _ = sample(SHAPE, 1)
+    G = Guess(*SHAPE)
+    G.set_params(p)
+    got = G.predict(dev(hn), dev(hp), dev(lnks), 3e-7).cpu().numpy()
+    want = R.predict(p.astype(np.float64), hn, hp, lnks, 3e-7, SHAPE, rnd=True)
+    y_g, y_r = (got - hn) / R.OUT_SCALE, (want - hn) / R.OUT_SCALE
+    # both sides round the same stored quantities to BF16; FP32 vs FP64 sums
+    # can move an activation across a BF16 rounding boundary (2^-8 relative)
+    assert np.abs(y_g - y_r).max() <= 2e-2 * np.abs(y_r).max()
+    assert np.corrcoef(y_g, y_r)[0, 1] >= 0.9999
+
+
+def test_gradient_matches_reference():
+    shape = (6, 5, 70)
+    p = R.init_params(seed=6, scale_out=1.0).astype(np.float32)
+    hn, hp, lnks, target = sample(shape, 2)
+    G = Guess(*shape)
+    G.set_params(p)
+    loss_g, grad_g = G.gradient(dev(hn), dev(hp), dev(lnks), 3e-7, dev(target))
+    loss_r, grad_r = R.loss_and_grad(p.astype(np.float64), hn, hp, lnks, 3e-7, target, shape, rnd=True)
+    assert loss_g == pytest.approx(loss_r, rel=1e-3)
+    for l, (wo, bo) in enumerate(R.OFFSETS):
+        for a, b in ((wo, bo), (bo, bo + R.COUT[l])):
+            g, r = grad_g[a:b].astype(np.float64), grad_r[a:b]
+            rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+            assert rel <= 3e-2, (l, a, rel)
+
+
+def test_untrained_network_returns_h_n():
+    hn, hp, lnks, _ = sample(SHAPE, 3)
+    G = Guess(*SHAPE, seed=1)
+    got = G.predict(dev(hn), dev(hp), dev(lnks), 0.0).cpu().numpy()
+    assert np.array_equal(got, hn)
+
+
+def test_training_fits_one_solver_step():
+    trajs, w = [], None
+    tr, w = learned.trajectory(100, 3, nx=32, ny=32, nz=64)
+    shape = (32, 32, 64)
+    G = Guess(*shape, seed=0)
+    hn, hp, tg = tr.states[1], tr.states[0], tr.states[2]
+    losses = [G.train_step(hn, hp, tr.lnks, tr.rain[1], tg, 2e-3) for _ in range(150)]
+    assert np.isfinite(losses).all()
+    assert np.mean(losses[-10:]) < 0.3 * losses[0], (losses[0], losses[-10:])
+
+
+def test_learned_guess_cuts_picard_iterations():
+    """Trained on four seeds of a 48 x 48 x 64 hillslope, evaluated on a
+    held-out seed: fewer Picard iterations, same converged states."""
+    nx, ny, nz, nsteps = 48, 48, 64, 24
+    trajs = [learned.trajectory(s, nsteps, nx=nx, ny=ny, nz=nz)[0] for s in (100, 101, 102, 103)]
+    params, losses = learned.train(trajs, (nx, ny, nz), 600, crop_xy=(32, 32), lr=2e-3)
+    assert np.mean(losses[-50:]) < 0.2 * np.mean(losses[:10])
+    ev = learned.evaluate(params, 200, nsteps, nx=nx, ny=ny, nz=nz)
+    assert ev["learned"]["picard_total"] < ev["plain"]["picard_total"], ev
+    # both runs converge every step to tol_picard = 1e-6 from different first
+    # iterates; their states differ by the Picard stopping error only
+    assert ev["max_abs_h_diff_m"] <= 2e-5, ev
