@@ -19,8 +19,8 @@
  * Weights are held in FP32 (the trained copy) and used as BF16; activations
  * are BF16, every product accumulates in FP32 on the matrix cores
  * (v_mfma_f32_16x16x32_bf16).  Training minimises the mean square of
- * h^{n+1,0} - h^{n+1} over the grid against solver-converged states, with
- * hand-written backward kernels and Adam.
+ * (h^{n+1,0} - h^{n+1}) / 0.01 m over the grid against solver-converged
+ * states, with hand-written backward kernels and Adam.
  *
  * Parameter vector (FP32, rf_guess_param_count values), layer by layer:
  * W_l[co][tap][ci] then b_l[co], tap = 9 (di+1) + 3 (dj+1) + (dk+1) for the
@@ -66,7 +66,7 @@ rf_status rf_guess_get_params(const rf_guess *g, float *host);
 rf_status rf_guess_predict(rf_guess *g, const double *hn, const double *hprev, const double *lnks,
                            double rain, double *guess_dev);
 
-/* Loss 0.5/N sum (h^{n+1,0} - target)^2 [m^2] and its gradient with respect
+/* Loss 0.5/N sum ((h^{n+1,0} - target) / 0.01 m)^2 and its gradient with respect
  * to the parameters (host array of rf_guess_param_count floats, may be NULL),
  * at the current parameters; no update. */
 rf_status rf_guess_gradient(rf_guess *g, const double *hn, const double *hprev, const double *lnks,

@@ -119,15 +119,16 @@ def predict(params, hn, hprev, lnks, rain, shape, rnd=False):
 
 
 def loss_and_grad(params, hn, hprev, lnks, rain, target, shape, rnd=False):
-    """Loss 0.5/N sum (h^n + 0.01 y - target)^2 and its parameter gradient."""
+    """Loss 0.5/N sum ((h^n + 0.01 y - target) / 0.01)^2 and its parameter gradient."""
     nx, ny, nz = shape
     N = nx * ny * nz
     f = features(hn, hprev, lnks, rain, shape)
     Ws, bs = unpack(params, rnd)
     y, xs = forward(params, f, rnd)
-    r = np.asarray(hn).reshape(ny, nx, nz) + OUT_SCALE * y - np.asarray(target).reshape(ny, nx, nz)
+    r = (np.asarray(hn).reshape(ny, nx, nz) + OUT_SCALE * y
+         - np.asarray(target).reshape(ny, nx, nz)) / OUT_SCALE
     loss = 0.5 * np.sum(r * r) / N
-    d = (OUT_SCALE * r / N)[..., None]
+    d = (r / N)[..., None]
     if rnd:
         d = bf16(d)
     grad = np.zeros(NPARAMS)

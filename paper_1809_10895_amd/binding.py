@@ -292,8 +292,9 @@ class Solver:
     def set_state(self, h, t=0.0):
         return self.L.rf_set_state(self.h, _ptr(h), float(t))
 
-    def get_state(self):
-        out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+    def get_state(self, out=None):
+        if out is None:
+            out = self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
         t = C.c_double()
         self._check(self.L.rf_get_state(self.h, _ptr(out), C.byref(t)))
         return out, t.value

@@ -277,7 +277,9 @@ __global__ void k_output(NetGeo g, const float *__restrict__ y, const double *__
     guess[c] = hn[c] + kOutScale * (double)y[c];
 }
 
-// r = h^n + 0.01 y - target; loss partials of 0.5 r^2 / N; dz3 = 0.01 r / N.
+// r = (h^n + 0.01 y - target) / 0.01 m (the error in units of the output
+// scale, so that gradients stay well above Adam's epsilon); loss partials of
+// 0.5 r^2 / N; dz3 = dL/dy = r / N.
 __global__ void __launch_bounds__(256) k_loss(NetGeo g, const float *__restrict__ y,
                                               const double *__restrict__ hn,
                                               const double *__restrict__ target, bf16 *__restrict__ dz3,
@@ -287,10 +289,10 @@ __global__ void __launch_bounds__(256) k_loss(NetGeo g, const float *__restrict_
     const double inv = 1.0 / (double)g.ncell;
     double acc = 0.0;
     for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < g.ncell; c += (long)gridDim.x * 256) {
-        const double r = hn[c] + kOutScale * (double)y[c] - target[c];
+        const double r = (hn[c] + kOutScale * (double)y[c] - target[c]) / kOutScale;
         acc += 0.5 * r * r * inv;
         bf16x8 d = zero8();
-        d[0] = (bf16)(float)(kOutScale * r * inv);
+        d[0] = (bf16)(float)(r * inv);
         *reinterpret_cast<bf16x8 *>(dz3 + c * 8) = d;
     }
     s[threadIdx.x] = acc;

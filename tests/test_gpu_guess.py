@@ -80,12 +80,26 @@ def test_training_fits_one_solver_step():
 
 
 def test_learned_guess_cuts_picard_iterations():
-    """Trained on four seeds of a 48 x 48 x 64 hillslope, evaluated on a
-    held-out seed: fewer Picard iterations, same converged states."""
+    """Trained on eight seeds of a 48 x 48 x 64 hillslope (24 steps each),
+    evaluated on a held-out seed: the guess is far closer to the converged
+    state than h^n or a linear extrapolation, plain Picard from it needs
+    fewer iterations, and the converged states agree."""
     nx, ny, nz, nsteps = 48, 48, 64, 24
-    trajs = [learned.trajectory(s, nsteps, nx=nx, ny=ny, nz=nz)[0] for s in (100, 101, 102, 103)]
-    params, losses = learned.train(trajs, (nx, ny, nz), 600, crop_xy=(32, 32), lr=2e-3)
-    assert np.mean(losses[-50:]) < 0.2 * np.mean(losses[:10])
+    trajs = [learned.trajectory(s, nsteps, nx=nx, ny=ny, nz=nz)[0] for s in range(100, 108)]
+    params, losses = learned.train(trajs, (nx, ny, nz), 3000, crop_xy=(32, 32), lr=3e-4)
+    val, _ = learned.trajectory(200, nsteps, nx=nx, ny=ny, nz=nz)
+    G = Guess(nx, ny, nz)
+
+    def val_loss(p):
+        G.set_params(p)
+        return np.mean([G.gradient(val.states[n], val.states[max(n - 1, 0)], val.lnks, val.rain[n],
+                                   val.states[n + 1])[0] for n in range(nsteps)])
+
+    zero = val_loss(np.zeros_like(params))
+    extrap = np.mean([0.5 * float((((2 * val.states[n] - val.states[max(n - 1, 0)])
+                                    - val.states[n + 1]) / 0.01).pow(2).mean()) for n in range(nsteps)])
+    trained = val_loss(params)
+    assert trained < 0.1 * zero and trained < 0.3 * extrap, (trained, zero, extrap)
     ev = learned.evaluate(params, 200, nsteps, nx=nx, ny=ny, nz=nz)
     assert ev["learned"]["picard_total"] < ev["plain"]["picard_total"], ev
     # both runs converge every step to tol_picard = 1e-6 from different first
