@@ -63,8 +63,13 @@ def parse():
                     help="arithmetic of the timed line (fp64 = the paper's)")
     ap.add_argument("--cg-rel-tol", type=float, default=0.0,
                     help="relative PCG exit test (0 = absolute tol_cg only)")
-    ap.add_argument("--no-variant", action="store_true",
-                    help="skip the extra run in the other precision")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the headline line only (no other precision, learned guess or "
+                         "ensemble): profiler runs")
+    ap.add_argument("--learned-steps", type=int, default=24,
+                    help="steps of the learned-guess comparison (0 = skip)")
+    ap.add_argument("--ensemble-seconds", type=float, default=120.0,
+                    help="simulated span of the 4096-column ensemble launch (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -203,6 +208,54 @@ def timed_case(args, w, precision):
             "roofline": roof, "kernels_warmup": kernels}, h
 
 
+def learned_guess(nsteps):
+    """The committed network (trained on seeds 100-119) on held-out seed 200
+    of the hillslope with its rain series: plain Picard in FP64 against the
+    learned first iterate with mixed precision, same Picard tolerance."""
+    import numpy as np
+    from paper_1809_10895_amd import learned
+    path = os.path.join(ROOT, "paper_1809_10895_amd", "data", "guess_hillslope.f32")
+    params = np.fromfile(path, dtype=np.float32)
+    fp64 = learned.evaluate(params, 200, nsteps, precision=0)
+    mixed = learned.evaluate(params, 200, nsteps, precision=1)
+    base = fp64["plain"]["wall_s_per_simulated_day"]
+    return {"workload": "hillslope 128x128x64 seed 200 with its rain series, dt 600 s, %d steps" % nsteps,
+            "wall_s_per_simulated_day": {"plain_fp64": base,
+                                         "learned_fp64": fp64["learned"]["wall_s_per_simulated_day"],
+                                         "plain_mixed": mixed["plain"]["wall_s_per_simulated_day"],
+                                         "learned_mixed": mixed["learned"]["wall_s_per_simulated_day"]},
+            "picard_total": {"plain": fp64["plain"]["picard_total"],
+                             "learned": fp64["learned"]["picard_total"]},
+            "predict_ms_per_step": mixed["learned"]["predict_s"] / nsteps * 1e3,
+            "learned_mixed_vs_plain_fp64": base / mixed["learned"]["wall_s_per_simulated_day"],
+            "max_abs_h_diff_m": max(fp64["max_abs_h_diff_m"], mixed["max_abs_h_diff_m"])}
+
+
+def ensemble(seconds):
+    """One launch of the 4096-column ensemble (lengths 50-400, sampled vG
+    parameters, EBATS from 10 s) over `seconds` of simulated time; the
+    persistent kernel is timed with HIP events."""
+    import torch
+    from paper_1809_10895_amd import workloads as W
+    from paper_1809_10895_amd.binding import Ensemble
+    w = W.ensemble(t_end=seconds)
+    E = Ensemble(w.lengths, w.dz, w.soil)
+    W.configure_ensemble(w, E)
+    E.set_options(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max, ebats=1)
+    E.bind()
+    assert E.set_state(torch.tensor(w.h0, dtype=torch.float64, device="cuda")) == 0, E.last_error()
+    s, sm = E.run(w.t_end)
+    if s != 0:
+        return {"error": E.last_error()}
+    sec = sm["kernel_ms"] * 1e-3
+    return {"workload": "4096 columns, 50-400 cells of 1 cm, n 1.3-3, alpha 0.5-5 1/m, log10 Ks -7..-4, "
+                        "h0 -10 m, top -0.75 m, free drainage, EBATS from 10 s, %.0f s simulated" % seconds,
+            "value": sm["cell_steps"] / sec, "unit": "cell-steps/s", "kernel_ms": sm["kernel_ms"],
+            "accepted_steps": sm["accepted"], "rejected_steps": sm["rejected"],
+            "picard_total": sm["picard_total"], "picard_iterations_per_s": sm["picard_total"] / sec,
+            "max_balance_error_m": sm["max_balance_error"], "dtype": "f64"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,8 +275,8 @@ def main():
     w, desc = make_workload(args.workload)
     cells = w.active_cells
     main_r, h_main = timed_case(args, w, args.precision)
-    variant = None
-    if not args.no_variant:
+    variant = learned_res = ens_res = None
+    if not args.no_extras:
         other = "mixed" if args.precision == "fp64" else "fp64"
         r, h_other = timed_case(args, w, other)
         m = w.active_mask()
@@ -232,6 +285,10 @@ def main():
                    "max_abs_h_diff_m": float(np.abs(h_other[m] - h_main[m]).max()),
                    "roofline": r["roofline"]}
 
+    if not args.no_extras and args.learned_steps > 0:
+        learned_res = learned_guess(args.learned_steps)
+    if not args.no_extras and args.ensemble_seconds > 0:
+        ens_res = ensemble(args.ensemble_seconds)
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
         "metric": "cell-steps/s at Picard tol 1e-6", "value": main_r["value"], "unit": "cell-steps/s",
@@ -249,6 +306,8 @@ def main():
         "roofline": main_r["roofline"],
         "kernels_warmup": main_r["kernels_warmup"],
         "other_precision": variant,
+        "learned_guess": learned_res,
+        "ensemble": ens_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -68,6 +68,7 @@ typedef struct {
     int failed;            /* columns whose status is not RF_OK */
     double t_min;          /* smallest time reached by a column [s] */
     double max_balance_error;  /* max over columns of |storage - storage0 - inflows| [m] */
+    double kernel_ms;      /* duration of the persistent kernel (HIP events) [ms] */
 } rf_ens_summary;
 
 rf_status rf_ens_create(rf_ens **out, int hip_device, void *hip_stream);

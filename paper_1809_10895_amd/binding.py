@@ -94,7 +94,7 @@ class RfEnsColumn(C.Structure):
 class RfEnsSummary(C.Structure):
     _fields_ = [("accepted", C.c_long), ("rejected", C.c_long), ("picard_total", C.c_long),
                 ("cell_steps", C.c_long), ("failed", C.c_int), ("t_min", C.c_double),
-                ("max_balance_error", C.c_double)]
+                ("max_balance_error", C.c_double), ("kernel_ms", C.c_double)]
 
 
 class RfError(RuntimeError):

@@ -511,6 +511,7 @@ __global__ void __launch_bounds__(256) k_ens_summary(EnsArrays a, int ncol)
         r.failed = s_fail[0];
         r.t_min = s_tmin[0];
         r.max_balance_error = s_err[0];
+        r.kernel_ms = 0.0;
         a.sum[0] = r;
     }
 }

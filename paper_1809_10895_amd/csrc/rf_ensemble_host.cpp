@@ -52,6 +52,7 @@ struct rf_ens {
     EnsArrays A{};
 
     rf_ens_summary *hsum = nullptr;  // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int n_cu = 0;
     double tick_hz = 1e8;
 };
@@ -154,7 +155,10 @@ rf_status rf_ens_create(rf_ens **out, int hip_device, void *hip_stream)
     if (hipSetDevice(hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&e->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, hip_device) != hipSuccess ||
-        hipHostMalloc((void **)&e->hsum, sizeof(rf_ens_summary), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&e->hsum, sizeof(rf_ens_summary), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&e->ev[0]) != hipSuccess || hipEventCreate(&e->ev[1]) != hipSuccess) {
+        if (e->hsum) (void)hipHostFree(e->hsum);
+        if (e->ev[0]) (void)hipEventDestroy(e->ev[0]);
         delete e;
         return RF_ERR_HIP;
     }
@@ -168,6 +172,8 @@ rf_status rf_ens_destroy(rf_ens *e)
     if (!e) return RF_ERR_ARG;
     (void)hipSetDevice(e->device);
     if (e->hsum) (void)hipHostFree(e->hsum);
+    for (hipEvent_t v : e->ev)
+        if (v) (void)hipEventDestroy(v);
     delete e;
     return RF_OK;
 }
@@ -352,13 +358,18 @@ static rf_status ens_run(rf_ens *e, double t_end, rf_ens_summary *out)
     rp.max_steps = e->max_steps;
     rp.max_ticks = (long long)(e->max_seconds * e->tick_hz);
     EHIP(e, launch_ens_reset(e->A, e->stream));
+    EHIP(e, hipEventRecord(e->ev[0], e->stream));
     EHIP(e, launch_ens_run(e->A, e->ncol, make_opt(e), rp, mixed, nblk, e->tile.waves_per_block,
                            e->stream));
+    EHIP(e, hipEventRecord(e->ev[1], e->stream));
     EHIP(e, launch_ens_summary(e->A, e->ncol, e->stream));
     EHIP(e, hipMemcpyAsync(e->hsum, e->A.sum, sizeof(rf_ens_summary), hipMemcpyDeviceToHost,
                            e->stream));
     EHIP(e, hipStreamSynchronize(e->stream));
-    const rf_ens_summary sm = *e->hsum;
+    rf_ens_summary sm = *e->hsum;
+    float ms = 0.f;
+    EHIP(e, hipEventElapsedTime(&ms, e->ev[0], e->ev[1]));
+    sm.kernel_ms = ms;
     if (out) *out = sm;
     if (sm.failed > 0)
         return efail(e, RF_ERR_NOT_CONVERGED, "%d of %d columns failed", sm.failed, e->ncol);
