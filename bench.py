@@ -68,8 +68,9 @@ def parse():
                          "ensemble): profiler runs")
     ap.add_argument("--learned-steps", type=int, default=24,
                     help="steps of the learned-guess comparison (0 = skip)")
-    ap.add_argument("--ensemble-seconds", type=float, default=120.0,
-                    help="simulated span of the 4096-column ensemble launch (0 = skip)")
+    ap.add_argument("--ensemble-seconds", type=float, default=0.0,
+                    help="simulated span of the 4096-column ensemble, run in a child process "
+                         "(0 = skip, the default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -232,28 +233,22 @@ def learned_guess(nsteps):
 
 
 def ensemble(seconds):
-    """One launch of the 4096-column ensemble (lengths 50-400, sampled vG
-    parameters, EBATS from 10 s) over `seconds` of simulated time; the
-    persistent kernel is timed with HIP events."""
-    import torch
-    from paper_1809_10895_amd import workloads as W
-    from paper_1809_10895_amd.binding import Ensemble
-    w = W.ensemble(t_end=seconds)
-    E = Ensemble(w.lengths, w.dz, w.soil)
-    W.configure_ensemble(w, E)
-    E.set_options(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max, ebats=1)
-    E.bind()
-    assert E.set_state(torch.tensor(w.h0, dtype=torch.float64, device="cuda")) == 0, E.last_error()
-    s, sm = E.run(w.t_end)
-    if s != 0:
-        return {"error": E.last_error()}
-    sec = sm["kernel_ms"] * 1e-3
-    return {"workload": "4096 columns, 50-400 cells of 1 cm, n 1.3-3, alpha 0.5-5 1/m, log10 Ks -7..-4, "
-                        "h0 -10 m, top -0.75 m, free drainage, EBATS from 10 s, %.0f s simulated" % seconds,
-            "value": sm["cell_steps"] / sec, "unit": "cell-steps/s", "kernel_ms": sm["kernel_ms"],
-            "accepted_steps": sm["accepted"], "rejected_steps": sm["rejected"],
-            "picard_total": sm["picard_total"], "picard_iterations_per_s": sm["picard_total"] / sec,
-            "max_balance_error_m": sm["max_balance_error"], "dtype": "f64"}
+    """The 4096-column ensemble, measured in a child process of its own (see
+    paper_1809_10895_amd/ensemble_bench.py) with a time limit."""
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, "-m", "paper_1809_10895_amd.ensemble_bench", "--seconds",
+                            str(seconds)], cwd=ROOT, capture_output=True, text=True, timeout=150)
+    except subprocess.TimeoutExpired:
+        return {"error": "the ensemble process did not finish within 150 s"}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": "ensemble process exited with %d" % r.returncode}
+    return json.loads(lines[-1])
+
+
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -274,10 +269,12 @@ def main():
         del src, dst
     w, desc = make_workload(args.workload)
     cells = w.active_cells
+    progress("%s %s" % (args.workload, args.precision))
     main_r, h_main = timed_case(args, w, args.precision)
     variant = learned_res = ens_res = None
     if not args.no_extras:
         other = "mixed" if args.precision == "fp64" else "fp64"
+        progress("%s %s" % (args.workload, other))
         r, h_other = timed_case(args, w, other)
         m = w.active_mask()
         variant = {"precision": other, "value": r["value"], "ms_per_step": r["ms_per_step"],
@@ -286,9 +283,12 @@ def main():
                    "roofline": r["roofline"]}
 
     if not args.no_extras and args.learned_steps > 0:
+        progress("learned guess")
         learned_res = learned_guess(args.learned_steps)
     if not args.no_extras and args.ensemble_seconds > 0:
+        progress("ensemble (child process)")
         ens_res = ensemble(args.ensemble_seconds)
+    progress("cpu baseline")
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
         "metric": "cell-steps/s at Picard tol 1e-6", "value": main_r["value"], "unit": "cell-steps/s",
