@@ -192,7 +192,7 @@ __device__ __forceinline__ double ens_inflow(const EnsOpt &o, int dir, double Kb
 
 // The whole time loop of column c (P cells per lane, solve in precision TS).
 template <int P, typename TS>
-__device__ __forceinline__ void run_column(const EnsArrays &a, const EnsOpt &o, const EnsRunParams &rp,
+__device__ void run_column(const EnsArrays &a, const EnsOpt &o, const EnsRunParams &rp,
                            long long t0, int c, int lane)
 {
     rf_ens_column st = a.col[c];
