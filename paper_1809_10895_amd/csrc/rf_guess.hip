@@ -5,10 +5,11 @@
 // output tile of one wavefront is 16 output channels x 64 cells (one z-run of
 // a column, cells z-fastest as in the solver), the reduction runs over taps
 // and input channels, 32 values per instruction (one tap of 32 channels, or
-// four taps of an 8-channel input).  Activations are channels-last BF16, so a
-// cell's 32 channels are one 64-byte row and the B operand of a step is one
-// coalesced 1 KB read per 16 cells; the packed weights of a layer (<= 55 KB)
-// sit in LDS for the whole block.  The backward pass reuses the same kernel
+// four taps of an 8-channel input).  Activations are channels-last BF16 (a
+// cell's 32 channels are one 64-byte row).  A block stages a 4 x 2 patch of
+// columns with a one-cell border (<= 99 KB) and the layer's packed weights
+// (<= 55 KB) in LDS once, so every input row crosses L2 about three times
+// instead of once per tap.  The backward pass reuses the same kernel
 // with transposed, tap-mirrored weights (the gradient with respect to a
 // layer's input) and a ReLU-mask epilogue; the weight gradient is a second
 // MFMA kernel whose reduction runs over cells, with LDS transposes of the
@@ -25,7 +26,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNetThreads = 256;   // four wavefronts
 enum { EPI_RELU = 0, EPI_LAST = 1, EPI_MASK = 2 };
 
 // Neighbour of cell (i, j, k) through tap t = 9 (di+1) + 3 (dj+1) + (dk+1);
@@ -46,79 +46,105 @@ __device__ __forceinline__ bf16x8 zero8()
     return z;
 }
 
-// One convolution layer.  CIN: stored input channels (8 or 32); COB: output
-// blocks of 16 channels (1 or 2).  EPI_RELU: out = bf16(relu(acc + bias));
-// EPI_LAST: outf = acc + bias of channel 0 (FP32); EPI_MASK: out =
-// bf16(acc) where mask > 0, else 0 (gradient through a ReLU).
+// One convolution layer over one block patch: PX x PY columns and 64 cells
+// of z.  The patch's input plus a one-cell border (6 x 4 columns x 66 cells,
+// zero outside the grid) is staged in LDS once, with the layer's packed
+// weights; each of the eight wavefronts then computes one column, 16 output
+// channels x 64 cells per MFMA group, reading every tap's operand from LDS.
+// CIN: stored input channels (8 or 32); COB: output blocks of 16 channels (1
+// or 2).  EPI_RELU: out = bf16(relu(acc + bias)); EPI_LAST: outf = acc + bias
+// of channel 0 (FP32); EPI_MASK: out = bf16(acc) where mask > 0, else 0
+// (gradient through a ReLU).
+constexpr int PX = 4, PY = 2, TX = PX + 2, TY = PY + 2, TZ = 64 + 2;
+constexpr int kTileThreads = 64 * PX * PY;
+
 template <int CIN, int COB, int EPI>
-__global__ void __launch_bounds__(kNetThreads) k_conv(NetGeo g, const bf16 *__restrict__ in,
-                                                      const bf16 *__restrict__ wp,
-                                                      const float *__restrict__ bias,
-                                                      bf16 *__restrict__ out, float *__restrict__ outf,
-                                                      const bf16 *__restrict__ mask)
+__global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__restrict__ in,
+                                                       const bf16 *__restrict__ wp,
+                                                       const float *__restrict__ bias,
+                                                       bf16 *__restrict__ out, float *__restrict__ outf,
+                                                       const bf16 *__restrict__ mask)
 {
     constexpr int STEPS = packed_steps(CIN);
     constexpr int NPK = STEPS * COB * 64;
+    constexpr int CH = CIN / 8;                    // 16-byte chunks per cell
     __shared__ bf16x8 sW[NPK];
+    __shared__ bf16x8 sT[TX * TY * TZ * CH];
+    // patch of this block
+    const int pxn = (g.nx + PX - 1) / PX, pyn = (g.ny + PY - 1) / PY;
+    const int zti = blockIdx.x % g.zt;
+    const int pxy = blockIdx.x / g.zt;
+    const int px0 = (pxy % pxn) * PX, py0 = (pxy / pxn) * PY, z0 = zti * 64;
     const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
-    for (int e = threadIdx.x; e < NPK; e += kNetThreads) sW[e] = wv[e];
+    for (int e = threadIdx.x; e < NPK; e += kTileThreads) sW[e] = wv[e];
+    for (int e = threadIdx.x; e < TX * TY * TZ * CH; e += kTileThreads) {
+        const int part = e % CH, cz = e / CH;
+        const int zl = cz % TZ, cl = cz / TZ;
+        const int i = px0 - 1 + cl % TX, j = py0 - 1 + cl / TX, k = z0 - 1 + zl;
+        const bool ok = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const long cell = (long)k + (long)g.nz * ((long)i + (long)g.nx * j);
+        sT[e] = ok ? *reinterpret_cast<const bf16x8 *>(in + cell * CIN + 8 * part) : zero8();
+    }
+    (void)pyn;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, q = lane >> 4;
     const int wave = threadIdx.x >> 6;
-    for (int u = blockIdx.x * 4 + wave; u < g.units; u += gridDim.x * 4) {
-        const int col = u / g.zt, k0 = (u % g.zt) * 64;
-        const int i = col % g.nx, j = col / g.nx;
-        f32x4 acc[COB][4];
+    const int cx = wave % PX, cy = wave / PX;
+    const int i = px0 + cx, j = py0 + cy;
+    if (i >= g.nx || j >= g.ny) return;
+    const int col = i + g.nx * j;
+    f32x4 acc[COB][4];
 #pragma unroll
-        for (int b = 0; b < COB; b++)
+    for (int b = 0; b < COB; b++)
 #pragma unroll
-            for (int t = 0; t < 4; t++) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < STEPS; s++) {
-            bf16x8 A[COB];
+        for (int t = 0; t < 4; t++) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < STEPS; s++) {
+        bf16x8 A[COB];
 #pragma unroll
-            for (int b = 0; b < COB; b++) A[b] = sW[(s * COB + b) * 64 + lane];
-            const int tap = (CIN == 32) ? s : 4 * s + q;
-            const int cofs = (CIN == 32) ? 8 * q : 0;
-            bf16x8 B[4];
-#pragma unroll
-            for (int t = 0; t < 4; t++) {
-                const int k = k0 + 16 * t + n;
-                long nb = 0;
-                const bool ok = k < g.nz && tap < kTaps && tap_nbr(g, i, j, k, tap, nb);
-                B[t] = ok ? *reinterpret_cast<const bf16x8 *>(in + nb * CIN + cofs) : zero8();
-            }
-#pragma unroll
-            for (int t = 0; t < 4; t++)
-#pragma unroll
-                for (int b = 0; b < COB; b++)
-                    acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b], B[t], acc[b][t], 0, 0, 0);
-        }
-        // lane holds rows 4q..4q+3 (output channels) of column n (cell)
+        for (int b = 0; b < COB; b++) A[b] = sW[(s * COB + b) * 64 + lane];
+        const int tap = (CIN == 32) ? s : 4 * s + q;
+        const bool tok = tap < kTaps;
+        const int tt = tok ? tap : 0;
+        const int di = tt / 9 - 1, dj = (tt / 3) % 3 - 1, dk = tt % 3 - 1;
+        const int cl = (cx + 1 + di) + TX * (cy + 1 + dj);
+        const int part = (CIN == 32) ? q : 0;
+        bf16x8 B[4];
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-            const int k = k0 + 16 * t + n;
-            if (k >= g.nz) continue;
-            const long cell = (long)col * g.nz + k;
+            const int zl = 16 * t + n + 1 + dk;
+            B[t] = tok ? sT[(cl * TZ + zl) * CH + part] : zero8();
+        }
 #pragma unroll
-            for (int b = 0; b < COB; b++) {
-                if (EPI == EPI_LAST) {
-                    if (b == 0 && q == 0) outf[cell] = acc[0][t][0] + bias[0];
-                    continue;
-                }
-                const int co0 = 16 * b + 4 * q;
-                bf16x4 o;
-                if (EPI == EPI_MASK) {
-                    const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(mask + cell * kHid + co0);
+        for (int t = 0; t < 4; t++)
 #pragma unroll
-                    for (int v = 0; v < 4; v++)
-                        o[v] = (float)mk[v] > 0.f ? (bf16)acc[b][t][v] : (bf16)0.0f;
-                } else {
+            for (int b = 0; b < COB; b++)
+                acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b], B[t], acc[b][t], 0, 0, 0);
+    }
+    // lane holds rows 4q..4q+3 (output channels) of column n (cell)
 #pragma unroll
-                    for (int v = 0; v < 4; v++) o[v] = (bf16)fmaxf(acc[b][t][v] + bias[co0 + v], 0.f);
-                }
-                *reinterpret_cast<bf16x4 *>(out + cell * kHid + co0) = o;
+    for (int t = 0; t < 4; t++) {
+        const int k = z0 + 16 * t + n;
+        if (k >= g.nz) continue;
+        const long cell = (long)col * g.nz + k;
+#pragma unroll
+        for (int b = 0; b < COB; b++) {
+            if (EPI == EPI_LAST) {
+                if (b == 0 && q == 0) outf[cell] = acc[0][t][0] + bias[0];
+                continue;
             }
+            const int co0 = 16 * b + 4 * q;
+            bf16x4 o;
+            if (EPI == EPI_MASK) {
+                const bf16x4 mk = *reinterpret_cast<const bf16x4 *>(mask + cell * kHid + co0);
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    o[v] = (float)mk[v] > 0.f ? (bf16)acc[b][t][v] : (bf16)0.0f;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; v++) o[v] = (bf16)fmaxf(acc[b][t][v] + bias[co0 + v], 0.f);
+            }
+            *reinterpret_cast<bf16x4 *>(out + cell * kHid + co0) = o;
         }
     }
 }
@@ -350,10 +376,10 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[e] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
 }
 
+// One block per patch of PX x PY columns and 64 cells of z.
 int conv_grid(const NetGeo &g)
 {
-    const int need = (g.units + 3) / 4;
-    return need < 1024 ? (need < 1 ? 1 : need) : 1024;
+    return ((g.nx + PX - 1) / PX) * ((g.ny + PY - 1) / PY) * g.zt;
 }
 
 }  // namespace
@@ -385,7 +411,7 @@ hipError_t net_features(const NetGeo &g, const NetArrays &a, const double *hn, c
 
 hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s)
 {
-    const dim3 grid(conv_grid(g)), block(kNetThreads);
+    const dim3 grid(conv_grid(g)), block(kTileThreads);
     hipLaunchKernelGGL((k_conv<8, 2, EPI_RELU>), grid, block, 0, s, g, a.feat, a.wf[0], a.p + param_b(0),
                        a.act[0], nullptr, nullptr);
     hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[0], a.wf[1],
@@ -436,7 +462,7 @@ static hipError_t grads_of_layer(const NetGeo &g, const NetArrays &a, int l, con
 
 hipError_t net_backward(const NetGeo &g, const NetArrays &a, hipStream_t s)
 {
-    const dim3 grid(conv_grid(g)), block(kNetThreads);
+    const dim3 grid(conv_grid(g)), block(kTileThreads);
     hipError_t e;
     // layer 4 (index 3): input a3, output gradient dz3
     if ((e = grads_of_layer(g, a, 3, a.act[2], a.dz3, s)) != hipSuccess) return e;
