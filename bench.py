@@ -217,19 +217,25 @@ def learned_guess(nsteps):
     from paper_1809_10895_amd import learned
     path = os.path.join(ROOT, "paper_1809_10895_amd", "data", "guess_hillslope.f32")
     params = np.fromfile(path, dtype=np.float32)
-    fp64 = learned.evaluate(params, 200, nsteps, precision=0)
-    mixed = learned.evaluate(params, 200, nsteps, precision=1)
+    modes = ("plain", "learned", "extrapolate")
+    fp64 = learned.evaluate(params, 200, nsteps, precision=0, modes=modes)
+    mixed = learned.evaluate(params, 200, nsteps, precision=1, modes=modes)
     base = fp64["plain"]["wall_s_per_simulated_day"]
     return {"workload": "hillslope 128x128x64 seed 200 with its rain series, dt 600 s, %d steps" % nsteps,
-            "wall_s_per_simulated_day": {"plain_fp64": base,
-                                         "learned_fp64": fp64["learned"]["wall_s_per_simulated_day"],
-                                         "plain_mixed": mixed["plain"]["wall_s_per_simulated_day"],
-                                         "learned_mixed": mixed["learned"]["wall_s_per_simulated_day"]},
-            "picard_total": {"plain": fp64["plain"]["picard_total"],
-                             "learned": fp64["learned"]["picard_total"]},
+            "wall_s_per_simulated_day": {
+                "plain_fp64": base,
+                "learned_fp64": fp64["learned"]["wall_s_per_simulated_day"],
+                "extrapolate_fp64": fp64["extrapolate"]["wall_s_per_simulated_day"],
+                "plain_mixed": mixed["plain"]["wall_s_per_simulated_day"],
+                "learned_mixed": mixed["learned"]["wall_s_per_simulated_day"],
+                "extrapolate_mixed": mixed["extrapolate"]["wall_s_per_simulated_day"]},
+            "picard_total": {m: fp64[m]["picard_total"] for m in modes},
             "predict_ms_per_step": mixed["learned"]["predict_s"] / nsteps * 1e3,
             "learned_mixed_vs_plain_fp64": base / mixed["learned"]["wall_s_per_simulated_day"],
-            "max_abs_h_diff_m": max(fp64["max_abs_h_diff_m"], mixed["max_abs_h_diff_m"])}
+            "extrapolate_mixed_vs_plain_fp64": base / mixed["extrapolate"]["wall_s_per_simulated_day"],
+            "max_abs_h_diff_m": max(fp64["max_abs_h_diff_m"], mixed["max_abs_h_diff_m"],
+                                    fp64["max_abs_h_diff_m_extrapolate"],
+                                    mixed["max_abs_h_diff_m_extrapolate"])}
 
 
 def ensemble(seconds):

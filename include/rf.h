@@ -75,6 +75,13 @@ enum { RF_PREC_FP64 = 0, RF_PREC_MIXED = 1 };
  * analytic capacity of Eq. 3.  Both converge to the same backward-Euler
  * solution; the iterations differ. */
 enum { RF_PICARD_CHORD = 0, RF_PICARD_MODIFIED = 1 };
+/* First Picard iterate of a step when rf_step gets no h_guess_dev.
+ * RF_FIRST_PREVIOUS: h^{n+1,0} = h^n (the paper's Picard loop, Sec. 2.2).
+ * RF_FIRST_EXTRAPOLATE: h^{n+1,0} = h^n + (dt / dt_prev) (h^n - h^{n-1}), the
+ * linear extrapolation of the last accepted increment (h^n after rf_set_state
+ * or a change of options); the loop still runs to tol_picard, so only the
+ * number of iterations changes. */
+enum { RF_FIRST_PREVIOUS = 0, RF_FIRST_EXTRAPOLATE = 1 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -106,6 +113,7 @@ typedef struct {
                            cg_rel_tol times its value at the start of the solve
                            (0 = the absolute test alone, the default) */
     int picard_variant; /* RF_PICARD_CHORD (default) or RF_PICARD_MODIFIED */
+    int first_iterate;  /* RF_FIRST_PREVIOUS (default) or RF_FIRST_EXTRAPOLATE */
 } rf_options;
 
 typedef struct {

@@ -67,6 +67,7 @@ struct rf_ctx {
 
     double t = 0.0, dt_cur = 1.0;
     int easy = 0;
+    double dt_prev = 0.0;                  // last accepted dt with dh tracked (0: none)
     double storage0 = 0.0, storage = 0.0, inflow[6] = {0, 0, 0, 0, 0, 0};
     int pred_picard = 3;                   // Picard iterations enqueued up front
     int pred_cg[RF_MAX_PICARD_LOG];        // PCG iterations enqueued per Picard iteration
@@ -215,7 +216,7 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
     };
     Arrays a{};
     double **dbl[] = {&a.hn, &a.thn, &a.hb0, &a.hb1, &a.K, &a.Dd, &a.bst, &a.diag, &a.r,
-                      &a.p0, &a.p1, &a.q, &a.e, &a.z, &a.Ks, &a.tz, &a.rdp};
+                      &a.p0, &a.p1, &a.q, &a.e, &a.z, &a.Ks, &a.tz, &a.rdp, &a.dh};
     // Per-cell arrays are often a power of two in size; a kernel streams several
     // of them at the same index, so successive arrays are skewed by a few KiB
     // plus a fraction of a DRAM page to keep those streams on different
@@ -347,6 +348,7 @@ void rf_default_options(rf_options *o)
     o->precision = RF_PREC_FP64;
     o->cg_rel_tol = 0.0;
     o->picard_variant = RF_PICARD_CHORD;
+    o->first_iterate = RF_FIRST_PREVIOUS;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -529,7 +531,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         o->inc_after < 1 || o->few_iters < 1 || o->max_iters < 1 || !(o->factor > 1.0) ||
         o->cols_per_wave < 0 || (o->precision != RF_PREC_FP64 && o->precision != RF_PREC_MIXED) ||
         !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0) ||
-        (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED))
+        (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED) ||
+        (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {
         // the FP32 arrays exist only in a workspace laid out for them
@@ -540,6 +543,7 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
     c->opt = *o;
     c->dt_cur = o->dt0;
     c->easy = 0;
+    c->dt_prev = 0.0;
     if (c->have_grid) set_shapes(c);
     return RF_OK;
 }
@@ -600,6 +604,7 @@ rf_status rf_set_state(rf_ctx *c, const double *h_dev, double t)
     c->t = t;
     c->dt_cur = c->opt.dt0;
     c->easy = 0;
+    c->dt_prev = 0.0;
     c->have_state = true;
     return RF_OK;
 }
@@ -663,10 +668,13 @@ static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
     return enqueue_apply(c, m);
 }
 
+static bool extrapolating(const rf_ctx *c) { return c->opt.first_iterate == RF_FIRST_EXTRAPOLATE; }
+
 static rf_status enqueue_accept(rf_ctx *c, const Bc &bc, int M, int &naccept)
 {
     TIMED(c, K_DECIDE, M, -1, launch_decide(c->G, c->A, M, c->opt.tol_picard, c->stream));
-    TIMED(c, K_ACCEPT, M, naccept, launch_accept(c->G, c->S, c->A, c->stream));
+    TIMED(c, K_ACCEPT, M, naccept,
+          launch_accept(c->G, c->S, c->A, extrapolating(c), c->stream));
     naccept++;
     return RF_OK;
 }
@@ -687,7 +695,10 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     const Bc bc = bc_at(c, c->t);
     for (int m = 0; m < RF_MAX_PICARD_LOG; m++) c->pairs_enq[m] = c->apply_enq[m] = 0;
     int naccept = 0;
-    TIMED(c, K_BEGIN, -1, -1, launch_step_begin(G, c->S, bc, A, guess ? guess : A.hn, c->stream));
+    // first iterate: the caller's guess, h^n, or h^n + (dt / dt_prev) (h^n - h^{n-1})
+    const double ratio = (!guess && extrapolating(c) && c->dt_prev > 0.0) ? dt / c->dt_prev : 0.0;
+    TIMED(c, K_BEGIN, -1, -1,
+          launch_step_begin(G, c->S, bc, A, guess ? guess : A.hn, ratio, c->stream));
     int M = std::max(1, std::min(max_picard, c->pred_picard));
     for (int m = 0; m < M; m++) {
         rf_status s = enqueue_iteration(c, bc, dt, m);
@@ -767,6 +778,7 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     c->storage = sums[0];
     for (int f = 0; f < 6; f++) c->inflow[f] += dt * sums[1 + f];
     c->t += dt;
+    c->dt_prev = extrapolating(c) ? dt : 0.0;
     st->converged = 1;
     st->t = c->t;
     return RF_OK;
@@ -867,7 +879,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     const Bc bc = bc_at(c, c->t);
     (void)N;
-    HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, c->stream));
+    HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
                            c->stream));
     HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, c->stream));

@@ -92,6 +92,7 @@ struct CgVec {
 // hb[m & 1]; iteration m writes h^{m+1} into hb[(m + 1) & 1].
 struct Arrays {
     double *hn, *thn, *hb0, *hb1, *K, *Dd, *bst, *diag, *r, *p0, *p1, *q, *e, *z, *Ks;
+    double *dh;               // last accepted increment h^n - h^{n-1} (extrapolated first iterate)
     double *tz;               // z-line: coupling of cell k with k+1 (A_z K_f / dz)
     double *rdp;              // z-line: reciprocal pivots
     uint8_t *layer;           // may be null
@@ -116,8 +117,9 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s);
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             hipStream_t s);
+// hb0 = h0 + ratio * dh (ratio 0: a copy of h0).
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                             const double *h0, hipStream_t s);
+                             const double *h0, double ratio, hipStream_t s);
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s);
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, int variant, hipStream_t s);
@@ -136,7 +138,8 @@ hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed,
                          hipStream_t s);
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s);
-hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s);
+// track: also dh = h^{n+1} - h^n.
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, hipStream_t s);
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             double *theta, double *C, double *K, hipStream_t s);
 hipError_t launch_operator(const Geo &g, const Arrays &a, const double *x, double *y,

@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(kThreads) k_set_state(Geo g, Soil so, Arrays a
 // every Dirichlet face for every layer (the face conductivity of a cell is
 // its own Ks times that entry).
 __global__ void __launch_bounds__(kThreads) k_step_begin(Geo g, Soil so, Bc bc, Arrays a,
-                                                         const double *h0)
+                                                         const double *h0, double ratio)
 {
     if (blockIdx.x == 0 && threadIdx.x < 6 * RF_MAX_LAYERS) {
         const int f = threadIdx.x / RF_MAX_LAYERS, l = threadIdx.x % RF_MAX_LAYERS;
@@ -351,7 +351,9 @@ __global__ void __launch_bounds__(kThreads) k_step_begin(Geo g, Soil so, Bc bc, 
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
             const int k = k0 + lane;
-            if (k < kt) a.hb0[(size_t)col * g.nz + k] = h0[(size_t)col * g.nz + k];
+            if (k >= kt) continue;
+            const size_t i = (size_t)col * g.nz + k;
+            a.hb0[i] = (ratio != 0.0) ? h0[i] + ratio * a.dh[i] : h0[i];
         }
     }
     if (lead_thread()) {
@@ -1111,8 +1113,10 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
 // ---------------------------------------------------------------------------
 
 // Runs when the Picard exit test has passed (the flag comes from k_decide).
+// TRACK: also dh = h^{n+1} - h^n for the extrapolated first iterate.
 // Block partials (ps): [0] storage sum V theta~(h); [1+f] inflow rate through
 // face f with h = h^{m+1} and K = K(h^m) (the converged system).
+template <bool TRACK>
 __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
 {
     Scalars *s = a.sc;
@@ -1132,7 +1136,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
         constexpr int G2 = 2;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
             ColSlot cs[G2];
-            double hu[G2], Ku[G2], ksu[G2];
+            double hu[G2], Ku[G2], ksu[G2], ho[G2];
             int lu[G2];
 #pragma unroll
             for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
@@ -1143,6 +1147,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
                 Ku[u] = a.K[i];
                 ksu[u] = a.Ks[i];
                 lu[u] = a.layer ? a.layer[i] : 0;
+                if (TRACK) ho[u] = a.hn[i];
             }
 #pragma unroll
             for (int u = 0; u < G2; u++) {
@@ -1151,6 +1156,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
                 const int ci = cs[u].col % g.nx, cj = cs[u].col / g.nx;
                 const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, lane == 0,
                                      lane == cs[u].kt - 1};
+                if (TRACK) a.dh[i] = hu[u] - ho[u];
                 a.hn[i] = hu[u];
                 const double th = soil_theta(so.model, hu[u], sL[lu[u]]);
                 a.thn[i] = th;
@@ -1174,6 +1180,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
             const size_t idx = c.idx;
             const int lay = a.layer ? a.layer[idx] : 0;
             const double h = hf[idx];
+            if (TRACK) a.dh[idx] = h - a.hn[idx];
             a.hn[idx] = h;
             const double th = soil_theta(so.model, h, sL[lay]);
             a.thn[idx] = th;
@@ -1336,9 +1343,9 @@ hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const
 }
 
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                             const double *h0, hipStream_t s)
+                             const double *h0, double ratio, hipStream_t s)
 {
-    RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0);
+    RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0, ratio);
 }
 
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s)
@@ -1405,9 +1412,10 @@ hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, cons
                    t.max_cg);
 }
 
-hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s)
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, hipStream_t s)
 {
-    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept, g, so, a);
+    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<true>, g, so, a);
+    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<false>, g, so, a);
 }
 
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,

@@ -118,3 +118,33 @@ def test_appendix_b_steep_front_modified_picard(orc):
     w = steep_block(1.0)
     w.t_end = 60.0
     run_both(orc, w, tol_picard=1e-4, picard_variant=1)
+
+
+@pytest.mark.parametrize("case", ["column100", "small_3d"])
+def test_extrapolated_first_iterate(orc, case):
+    """first_iterate = RF_FIRST_EXTRAPOLATE: the GPU starts each Picard loop
+    from h^n + (h^n - h^{n-1}); the oracle is handed the same first iterate
+    (computed here from its own states).  Same Picard counts and heads; on
+    the smoothly advancing column also fewer iterations than from h^n."""
+    w = W.column100() if case == "column100" else small_3d()
+    nsteps = 30 if case == "column100" else 5
+    P = make_oracle(orc, w)
+    S = make_solver(w, precond=1, first_iterate=1)
+    P0 = make_oracle(orc, w)                       # plain start, for the iteration count
+    m = w.active_mask()
+    h_prev = None
+    it_ex = it_plain = 0
+    for n in range(nsteps):
+        h_now, _ = P.get_state()
+        guess = None if h_prev is None else h_now + (h_now - h_prev)
+        s_o, st_o = P.step(w.dt, guess)
+        s_g, st_g = S.step(w.dt)
+        s_p, st_p = P0.step(w.dt)
+        assert s_o == 0 and s_g == 0 and s_p == 0, S.last_error()
+        assert st_g["picard_iters"] == st_o["picard_iters"], (n, st_g, st_o)
+        assert rel_err(host(S.get_state()[0]), P.get_state()[0], m) <= 1e-8, n
+        it_ex += st_g["picard_iters"]
+        it_plain += st_p["picard_iters"]
+        h_prev = h_now
+    if case == "column100":
+        assert it_ex < it_plain, (it_ex, it_plain)
