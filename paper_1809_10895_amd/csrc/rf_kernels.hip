@@ -4,12 +4,12 @@
 // the wave holds cell k of the column (columns longer than 64 cells are
 // walked in chunks of 64).  With z the fastest index every column is one
 // contiguous run of doubles, so each chunk is a single coalesced 512-byte
-// access per array, the vertical coupling stays inside the wave (shuffles),
-// and the lateral neighbours are the adjacent columns.  Blocks of 8 waves
-// take contiguous runs of columns (optionally remapped per XCD, see
-// block_columns).  The PCG kernels are templated on the precision of their
-// vectors: FP64, or FP32 under FP64 Picard refinement (mixed precision); their
-// reductions are FP64 in both.
+// access per array, the vertical coupling stays inside the wave (DPP lane
+// shifts and scans, rf_wave.h), and the lateral neighbours are the adjacent
+// columns.  Blocks of 8 waves take contiguous runs of columns (optionally
+// remapped per XCD, see block_columns).  The PCG kernels are templated on
+// the precision of their vectors: FP64, or FP32 under FP64 Picard refinement
+// (mixed precision); their reductions are FP64 in both.
 //
 // Global reductions are two-stage, deterministic and fence-free: every block
 // writes one partial per value, and the consumer -- every block of the next
@@ -26,6 +26,7 @@
 
 #include "rf_internal.h"
 #include "rf_soil.h"
+#include "rf_wave.h"
 
 namespace rf {
 
@@ -53,18 +54,26 @@ __device__ __forceinline__ void block_columns(const Geo &g, int cpb, int &cb, in
     ce = min(cb + cpb, g.ncol);
 }
 
+// Sum / max over the wave, the same value in every lane: an in-row scan
+// with DPP shifts leaves each 16-lane row's total in its last lane; the four
+// row totals are combined in a fixed order.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+    x += dpp<kDppRowShr + 1>(x, 0.0);
+    x += dpp<kDppRowShr + 2>(x, 0.0);
+    x += dpp<kDppRowShr + 4>(x, 0.0);
+    x += dpp<kDppRowShr + 8>(x, 0.0);
+    return (lane_value<15>(x) + lane_value<31>(x)) + (lane_value<47>(x) + lane_value<63>(x));
 }
 
+// (A lane without a partner compares with itself.)
 __device__ __forceinline__ double wave_max(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, kWave));
-    return x;
+    x = fmax(x, dpp<kDppRowShr + 1>(x, x));
+    x = fmax(x, dpp<kDppRowShr + 2>(x, x));
+    x = fmax(x, dpp<kDppRowShr + 4>(x, x));
+    x = fmax(x, dpp<kDppRowShr + 8>(x, x));
+    return fmax(fmax(lane_value<15>(x), lane_value<31>(x)), fmax(lane_value<47>(x), lane_value<63>(x)));
 }
 
 // Block-level reduction of NV values (bit i of MAXMASK set = max, else sum)
@@ -402,6 +411,38 @@ __global__ void __launch_bounds__(kThreads) k_decide(Geo g, Arrays a, int m, dou
 // boundary right-hand-side terms (see FaceTab).  Modified Picard: C = Eq. 3
 // at h^m and bst = V (C h^m - (theta~(h^m) - theta~^n)) / dt + boundary
 // terms.  Interior-face terms are added in k_resid.
+//
+// Diagonal and right-hand side of one active cell from theta~, C, K at h^m;
+// bnd: its faces on the domain boundary.
+__device__ __forceinline__ void coeff_terms(const FaceTab *sBT, const double *sKR,
+                                            int lay, const bool (&bnd)[6], double hm, double hn,
+                                            double thn, double ks, double th, double C, double K,
+                                            double vdt, double chord_eps, int variant, double &D,
+                                            double &b)
+{
+    if (variant == RF_PICARD_MODIFIED) {
+        D = vdt * C;
+        b = vdt * (C * hm - (th - thn));
+    } else {
+        const double dh = hm - hn;
+        const double Cc = (fabs(dh) >= chord_eps) ? (th - thn) / dh : C;
+        D = vdt * Cc;
+        b = D * hn;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        if (!bnd[d]) continue;
+        const double Kb = ks * sKR[d * RF_MAX_LAYERS + lay];
+        D += sBT[d].cD * Kb;
+        b += sBT[d].cKb * Kb + sBT[d].cK * K + sBT[d].c0;
+    }
+}
+
+// The soil model is a template parameter.  Short columns: two columns per
+// wave at a time, all loads of the pair issued first, then two independent
+// soil evaluations per lane (branch-free for van Genuchten-Mualem), which
+// the compiler interleaves.
+template <int MODEL>
 __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
                                                     double chord_eps, int variant)
 {
@@ -415,8 +456,52 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
     const double *hmv = (m & 1) ? a.hb1 : a.hb0;
     const double vdt = g.V / dt;
     int cb, ce;
-    block_columns(g, g.cpb_w, cb, ce);
+    block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
+    if (g.nz <= kWave) {
+        // G columns at a time: every load of the group first, then G
+        // independent soil evaluations per lane
+        constexpr int G = 2;
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G) {
+            ColSlot cs[G];
+            int lay[G];
+            double ks[G], hm[G], hn[G], thn[G], th[G], C[G], K[G];
+#pragma unroll
+            for (int u = 0; u < G; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                const size_t i = cs[u].i;
+                lay[u] = a.layer ? a.layer[i] : 0;
+                ks[u] = a.Ks[i];
+                hm[u] = hmv[i];
+                hn[u] = a.hn[i];
+                thn[u] = a.thn[i];
+            }
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                if (MODEL == RF_VGM) {
+                    soil_eval_vgm_flat(hm[u], sL[lay[u]], ks[u], th[u], C[u], K[u]);
+                } else {
+                    soil_eval(MODEL, hm[u], sL[lay[u]], ks[u], th[u], C[u], K[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; u++) {
+                if (!cs[u].act) continue;
+                const int ci = cs[u].col % g.nx, cj = cs[u].col / g.nx;
+                const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, lane == 0,
+                                     lane == cs[u].kt - 1};
+                double D, b;
+                coeff_terms(sBT, sKR, lay[u], bnd, hm[u], hn[u], thn[u], ks[u], th[u],
+                            C[u], K[u], vdt, chord_eps, variant, D, b);
+                const size_t i = cs[u].i;
+                a.K[i] = K[u];
+                a.Dd[i] = D;
+                a.bst[i] = b;
+            }
+        }
+        return;
+    }
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -429,25 +514,10 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
             const double ks = a.Ks[idx];
             const double hm = hmv[idx], hn = a.hn[idx];
             double th, C, K;
-            soil_eval(so.model, hm, sL[lay], ks, th, C, K);
-            const double thn = a.thn[idx];
+            soil_eval(MODEL, hm, sL[lay], ks, th, C, K);
             double D, b;
-            if (variant == RF_PICARD_MODIFIED) {
-                D = vdt * C;
-                b = vdt * (C * hm - (th - thn));
-            } else {
-                const double dh = hm - hn;
-                const double Cc = (fabs(dh) >= chord_eps) ? (th - thn) / dh : C;
-                D = vdt * Cc;
-                b = D * hn;
-            }
-#pragma unroll
-            for (int d = 0; d < 6; d++) {
-                if (!c.bnd[d]) continue;
-                const double Kb = ks * sKR[d * RF_MAX_LAYERS + lay];
-                D += sBT[d].cD * Kb;
-                b += sBT[d].cKb * Kb + sBT[d].cK * K + sBT[d].c0;
-            }
+            coeff_terms(sBT, sKR, lay, c.bnd, hm, hn, a.thn[idx], ks, th, C, K, vdt,
+                        chord_eps, variant, D, b);
             a.K[idx] = K;
             a.Dd[idx] = D;
             a.bst[idx] = b;
@@ -458,69 +528,6 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
 // ---------------------------------------------------------------------------
 // z-line preconditioner pieces (exact LDL^T of each column's vertical part)
 // ---------------------------------------------------------------------------
-
-// Inclusive upward scan of affine maps x_k = a_k x_{k-1} + c_k over the
-// wave; returns x_k for the given carry x_{k0-1}.
-template <typename T>
-__device__ __forceinline__ T scan_affine_up(T a, T c, T carry, int lane)
-{
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const T ao = __shfl_up(a, off, kWave);
-        const T co = __shfl_up(c, off, kWave);
-        if (lane >= off) {
-            c = a * co + c;
-            a = a * ao;
-        }
-    }
-    return a * carry + c;
-}
-
-// Inclusive downward scan of x_k = b_k x_{k+1} + c_k.
-template <typename T>
-__device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
-{
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const T bo = __shfl_down(b, off, kWave);
-        const T co = __shfl_down(c, off, kWave);
-        if (lane + off < kWave) {
-            c = b * co + c;
-            b = b * bo;
-        }
-    }
-    return b * carry + c;
-}
-
-// Pivots of the column tridiagonal T: d_k = diag_k - t_{k-1}^2 / d_{k-1}.
-// With P_k = diag_k P_{k-1} - t_{k-1}^2 P_{k-2} (leading minors), d_k =
-// P_k / P_{k-1}; (P_k, P_{k-1}) is a prefix product of 2x2 matrices, scanned
-// across the wave with a per-step rescaling (only ratios matter).  carry =
-// d_{k0-1} (0 for the first chunk).  Returns d_k.
-__device__ __forceinline__ double scan_pivots(double diag, double tprev2, double carry, int lane)
-{
-    double m00 = diag, m01 = -tprev2, m10 = 1.0, m11 = 0.0;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double o00 = __shfl_up(m00, off, kWave);
-        const double o01 = __shfl_up(m01, off, kWave);
-        const double o10 = __shfl_up(m10, off, kWave);
-        const double o11 = __shfl_up(m11, off, kWave);
-        if (lane >= off) {
-            const double n00 = m00 * o00 + m01 * o10;
-            const double n01 = m00 * o01 + m01 * o11;
-            const double n10 = m10 * o00 + m11 * o10;
-            const double n11 = m10 * o01 + m11 * o11;
-            // rescale by a power of two (exact) to keep the product in range
-            const double sc = fmax(fmax(fabs(n00), fabs(n01)), fmax(fabs(n10), fabs(n11)));
-            const int ex = (sc > 0.0) ? ilogb(sc) : 0;
-            m00 = ldexp(n00, -ex); m01 = ldexp(n01, -ex); m10 = ldexp(n10, -ex); m11 = ldexp(n11, -ex);
-        }
-    }
-    const double v0 = (carry != 0.0) ? carry : 1.0;
-    const double v1 = (carry != 0.0) ? 1.0 : 0.0;
-    return (m00 * v0 + m01 * v1) / (m10 * v0 + m11 * v1);
-}
 
 // z = M^-1 r for a column longer than one wave, from memory: forward sweep
 // w_k = (r_k + t_{k-1} w_{k-1}) rdp_k into zout, backward sweep
@@ -537,7 +544,7 @@ __device__ __forceinline__ void zline_solve_long(const T *r, const T *rdp, const
         const T rd = act ? rdp[base + k] : T(0);
         const T tp = (act && k > 0) ? tz[base + k - 1] : T(0);
         const T wk = scan_affine_up<T>(tp * rd, rk * rd, carry, lane);
-        carry = __shfl(wk, kWave - 1, kWave);
+        carry = lane_value<kWave - 1>(wk);
         if (act) zout[base + k] = wk;
     }
     carry = 0;
@@ -547,7 +554,7 @@ __device__ __forceinline__ void zline_solve_long(const T *r, const T *rdp, const
         const T wk = act ? zout[base + k] : T(0);
         const T bk = act ? tz[base + k] * rdp[base + k] : T(0);
         const T zk = scan_affine_down<T>(bk, wk, carry, lane);
-        carry = __shfl(zk, 0, kWave);
+        carry = lane_value<0>(zk);
         if (act) zout[base + k] = zk;
     }
 }
@@ -557,8 +564,7 @@ __device__ __forceinline__ void zline_solve_long(const T *r, const T *rdp, const
 template <typename T>
 __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 {
-    T tp = __shfl_up(t, 1, kWave);
-    if (lane == 0) tp = 0;
+    const T tp = from_below<T>(t, T(0));
     const T wk = scan_affine_up<T>(tp * rd, r * rd, T(0), lane);
     return scan_affine_down<T>(t * rd, wk, T(0), lane);
 }
@@ -618,8 +624,8 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                 const bool act = cs[u].act;
                 const int kt = cs[u].kt;
                 const size_t i = cs[u].i;
-                const double Kd = __shfl_up(Kp[u], 1, kWave), hd = __shfl_up(hp[u], 1, kWave);
-                const double Ku = __shfl_down(Kp[u], 1, kWave), hu = __shfl_down(hp[u], 1, kWave);
+                const double Kd = from_below(Kp[u], 0.0), hd = from_below(hp[u], 0.0);
+                const double Ku = from_above(Kp[u], 0.0), hu = from_above(hp[u], 0.0);
                 double diag = act ? Dp[u] : 1.0, Ap = Dp[u] * hp[u], b = bp[u], tup = 0.0;
 #pragma unroll
                 for (int d = 0; d < 4; d++) {
@@ -659,8 +665,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                     if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
                 }
                 if (PRECOND == RF_PRECOND_ZLINE) {
-                    double tprev = __shfl_up(tup, 1, kWave);
-                    if (lane == 0) tprev = 0.0;
+                    const double tprev = from_below(tup, 0.0);
                     const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
                     const double rdp = act ? 1.0 / dpiv : 0.0;
                     const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
@@ -718,15 +723,14 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
             }
             if (PRECOND == RF_PRECOND_ZLINE) {
                 // couplings and pivots of the column tridiagonal, in registers
-                double tprev = __shfl_up(tup, 1, kWave);
-                if (lane == 0) tprev = t_carry;
+                const double tprev = from_below(tup, t_carry);
                 const double dpiv = scan_pivots(act ? diag : 1.0, act ? tprev * tprev : 0.0,
                                                 d_carry, lane);
                 rdp = act ? 1.0 / dpiv : 0.0;
                 wk = scan_affine_up<double>(tprev * rdp, r * rdp, w_carry, lane);
-                t_carry = __shfl(tup, kWave - 1, kWave);
-                d_carry = __shfl(dpiv, kWave - 1, kWave);
-                w_carry = __shfl(wk, kWave - 1, kWave);
+                t_carry = lane_value<kWave - 1>(tup);
+                d_carry = lane_value<kWave - 1>(dpiv);
+                w_carry = lane_value<kWave - 1>(wk);
                 if (act) {
                     cv.tz[base + k] = (T)tup;
                     cv.rdp[base + k] = (T)rdp;
@@ -754,7 +758,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                     const T wv = act ? cv.z[base + k] : T(0);
                     const T bk = act ? cv.tz[base + k] * cv.rdp[base + k] : T(0);
                     const T zk = scan_affine_down<T>(bk, wv, carry, lane);
-                    carry = __shfl(zk, 0, kWave);
+                    carry = lane_value<0>(zk);
                     if (act) {
                         cv.z[base + k] = zk;
                         v[0] += (double)cv.r[base + k] * (double)zk;
@@ -789,24 +793,17 @@ __device__ __forceinline__ T pnew_at(const CgVec<T> &cv, size_t i, T beta, bool 
     return first ? z : z + beta * p_in[i];
 }
 
-// Starts PCG iteration j = (updates done so far).  Every block combines the
-// (r.z, max|r/diag|) partials of the last update and takes the same exit
-// decision (max|r/diag| <= tol, with tol = max(tol_cg, rel * the value at
-// j = 0) fixed at j = 0); otherwise p = z + beta p_old (z = M^-1 r) at the
-// cell and its neighbours, q = A p with A = Dd + sum_f T_f (I - shift_f)
-// rebuilt from (K, Dd); writes p, q and the block partials of p.q.  Vector
-// arithmetic in T, reductions and the scalars rho, beta in FP64.  The
-// direction buffers alternate: parity 0 reads p0 and writes p1.
-template <int PRECOND, typename T>
-__global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv, int parity,
-                                                   double tol_cg, double rel, int max_cg)
+// Combines the (r.z, max|r/diag|) partials of the last update and takes
+// the exit decision of PCG iteration j (max|r/diag| <= tol, with tol =
+// max(tol_cg, rel * the value at j = 0) fixed at j = 0).  Called by every
+// thread; returns true when the solve goes on, with rho = r.z.
+__device__ __forceinline__ bool spmv_continue(const Geo &g, const Arrays &a, Scalars *s, int j,
+                                              double tol_cg, double rel, int max_cg, double &rho)
 {
-    Scalars *s = a.sc;
-    if (s->done || s->fail || s->stall || s->picard_done) return;
-    const int j = s->iters;
     double tot[2];
     reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
-    const double rho = tot[0], resmax = tot[1];
+    rho = tot[0];
+    const double resmax = tot[1];
     const double tol = (j == 0) ? fmax(tol_cg, rel * resmax) : s->tol_eff;
     const bool bad = !isfinite(rho) || !isfinite(resmax);
     const bool done = bad || resmax <= tol || j >= max_cg;
@@ -822,76 +819,109 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
             else if (resmax > tol) s->fail = 2;
         }
     }
-    if (done) return;
+    return !done;
+}
+
+// Values of G columns of one wave (and of their lateral neighbours) read by
+// the spmv kernel.  Every load is unconditional (first iteration: the old
+// direction is read but not used), so all are in flight at once.
+template <int PRECOND, typename T, int G>
+struct SpmvGroup {
+    ColSlot cs[G];
+    bool nb[G][4];
+    T K[G], D[G], z[G], p[G], Kn[G][4], zn[G][4], pn[G][4];
+
+    __device__ __forceinline__ void load(const Geo &g, const Arrays &a, const CgVec<T> &cv,
+                                         const T *__restrict__ p_in, int c0, int ce, int lane)
+    {
+        size_t in[G][4];
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+            lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            const size_t i = cs[u].i;
+            K[u] = cv.K[i];
+            D[u] = cv.Dd[i];
+            z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
+            p[u] = p_in[i];
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                const size_t jn = in[u][d];
+                Kn[u][d] = cv.K[jn];
+                zn[u][d] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[jn] / cv.diag[jn] : cv.z[jn];
+                pn[u][d] = p_in[jn];
+            }
+        }
+    }
+};
+
+// Starts PCG iteration j = (updates done so far).  Every block combines the
+// (r.z, max|r/diag|) partials of the last update and takes the same exit
+// decision (spmv_continue); otherwise p = z + beta p_old (z = M^-1 r) at the
+// cell and its neighbours, q = A p with A = Dd + sum_f T_f (I - shift_f)
+// rebuilt from (K, Dd); writes p, q and the block partials of p.q.  Vector
+// arithmetic in T, reductions and the scalars rho, beta in FP64.  The
+// direction buffers alternate: parity 0 reads p0 and writes p1.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv, int parity,
+                                                   double tol_cg, double rel, int max_cg)
+{
+    Scalars *s = a.sc;
+    if (s->done || s->fail || s->stall || s->picard_done) return;
+    const int j = s->iters;
     const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
     const bool first = (j == 0);
-    const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
     const T tz2 = (T)(0.5 * g.Tk[2]);
     const T tx2[2] = {(T)(0.5 * g.Tk[0]), (T)(0.5 * g.Tk[1])};
     double v[1] = {0.0};
+    double rho;
     if (g.nz <= kWave) {
-        // gather p_new = z + beta p_old and K at the cell and its lateral
-        // neighbours for G2 columns, then apply the stencil; the vertical
+        // p_new = z + beta p_old and K at the cell and its lateral
+        // neighbours for G2 columns, then the stencil; the vertical
         // neighbours come from the adjacent lanes
         constexpr int G2 = 2;
+        if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
+        const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
+        SpmvGroup<PRECOND, T, G2> gr;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            ColSlot cs[G2];
-            bool nb[G2][4];
-            size_t in[G2][4];
-            T Kp[G2], Dp[G2], pp[G2], Kn[G2][4], pn[G2][4];
+            gr.load(g, a, cv, p_in, c0, ce, lane);
+            T pp[G2], pn[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
-                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-                lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
-            }
-            // every load of the group is unconditional (first iteration: the
-            // old direction is read but not used), so all are in flight at once
-            T zc[G2], pc[G2], zn[G2][4], po[G2][4];
+                pp[u] = first ? gr.z[u] : gr.z[u] + beta * gr.p[u];
 #pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const size_t i = cs[u].i;
-                Kp[u] = cv.K[i];
-                Dp[u] = cv.Dd[i];
-                zc[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
-                pc[u] = p_in[i];
-#pragma unroll
-                for (int d = 0; d < 4; d++) {
-                    const size_t jn = in[u][d];
-                    Kn[u][d] = cv.K[jn];
-                    zn[u][d] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[jn] / cv.diag[jn] : cv.z[jn];
-                    po[u][d] = p_in[jn];
-                }
+                for (int d = 0; d < 4; d++) pn[u][d] = first ? gr.zn[u][d] : gr.zn[u][d] + beta * gr.pn[u][d];
             }
 #pragma unroll
             for (int u = 0; u < G2; u++) {
-                pp[u] = first ? zc[u] : zc[u] + beta * pc[u];
-#pragma unroll
-                for (int d = 0; d < 4; d++) pn[u][d] = first ? zn[u][d] : zn[u][d] + beta * po[u][d];
-            }
-#pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const int kt = cs[u].kt;
-                const T Kd = __shfl_up(Kp[u], 1, kWave), pdn = __shfl_up(pp[u], 1, kWave);
-                const T Ku = __shfl_down(Kp[u], 1, kWave), pup = __shfl_down(pp[u], 1, kWave);
-                if (!cs[u].act) continue;
-                T q = Dp[u] * pp[u];
+                const int kt = gr.cs[u].kt;
+                const T Kp = gr.K[u];
+                const T Kd = from_below(Kp, T(0)), pdn = from_below(pp[u], T(0));
+                const T Ku = from_above(Kp, T(0)), pup = from_above(pp[u], T(0));
+                if (!gr.cs[u].act) continue;
+                T q = gr.D[u] * pp[u];
 #pragma unroll
                 for (int d = 0; d < 4; d++)
-                    if (nb[u][d]) q += tx2[d >> 1] * (Kp[u] + Kn[u][d]) * (pp[u] - pn[u][d]);
-                if (lane > 0) q += tz2 * (Kp[u] + Kd) * (pp[u] - pdn);
-                if (lane + 1 < kt) q += tz2 * (Kp[u] + Ku) * (pp[u] - pup);
-                p_out[cs[u].i] = pp[u];
-                cv.q[cs[u].i] = q;
+                    if (gr.nb[u][d]) q += tx2[d >> 1] * (Kp + gr.Kn[u][d]) * (pp[u] - pn[u][d]);
+                if (lane > 0) q += tz2 * (Kp + Kd) * (pp[u] - pdn);
+                if (lane + 1 < kt) q += tz2 * (Kp + Ku) * (pp[u] - pup);
+                p_out[gr.cs[u].i] = pp[u];
+                cv.q[gr.cs[u].i] = q;
                 v[0] += (double)pp[u] * (double)q;
             }
         }
         block_partial<1, 0u>(v, a.pq);
         return;
     }
+    if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
+    const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -920,15 +950,12 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
 // PCG iteration, kernel B: e += alpha p, r -= alpha q, z = M^-1 r, r.z
 // ---------------------------------------------------------------------------
 
-// alpha = rho_j / p.q (every block combines the p.q partials); block
-// partials of (r.z, max|r/diag|).  p is the direction the spmv kernel of the
-// same parity wrote.
-template <int PRECOND, typename T>
-__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
+// Combines the p.q partials of the spmv kernel: alpha = rho_j / p.q, or a
+// breakdown (p.q not positive or not finite) that ends the solve.  Called
+// by every thread; returns false on breakdown.
+__device__ __forceinline__ bool update_alpha(const Geo &g, const Arrays &a, Scalars *s, int j,
+                                             double &alpha)
 {
-    Scalars *s = a.sc;
-    if (s->done || s->fail || s->stall || s->picard_done) return;
-    const int j = s->jcur;
     double tot[1];
     reduce_partials<1, 0u>(a.pq + g.foff, g.np, tot);
     const double pq = tot[0];
@@ -939,55 +966,85 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
             s->done = 1;
             s->final_iters = j;
         }
-        return;
+        return false;
     }
-    const T alpha = (T)(s->rho[j & 1] / pq);
+    alpha = s->rho[j & 1] / pq;
     if (lead_thread()) {
         s->pq = pq;
         s->iters = j + 1;
     }
+    return true;
+}
+
+// Values of G columns of one wave read by the update kernel.
+template <int PRECOND, typename T, int G>
+struct UpdGroup {
+    ColSlot cs[G];
+    T p[G], r[G], q[G], d[G], e[G], rd[G], t[G];
+
+    __device__ __forceinline__ void load(const Geo &g, const Arrays &a, const CgVec<T> &cv,
+                                         const T *__restrict__ pv, int c0, int ce, int lane)
+    {
+#pragma unroll
+        for (int u = 0; u < G; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+        for (int u = 0; u < G; u++) {
+            const size_t i = cs[u].i;
+            p[u] = pv[i];
+            r[u] = cv.r[i];
+            q[u] = cv.q[i];
+            d[u] = cv.diag[i];
+            e[u] = cv.e[i];
+            if (PRECOND == RF_PRECOND_ZLINE) {
+                rd[u] = cv.rdp[i];
+                t[u] = cv.tz[i];
+            }
+        }
+    }
+};
+
+// alpha = rho_j / p.q (every block combines the p.q partials); block
+// partials of (r.z, max|r/diag|).  p is the direction the spmv kernel of the
+// same parity wrote.  Short columns: the loads of a wave's first group of
+// columns are issued before the partials are combined, so the two are in
+// flight together.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
+{
+    Scalars *s = a.sc;
+    if (s->done || s->fail || s->stall || s->picard_done) return;
+    const int j = s->jcur;
     const T *__restrict__ p = parity ? cv.p0 : cv.p1;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
+    double alpha_d;
     if (g.nz <= kWave) {
-        constexpr int G2 = 2;
+        constexpr int G = 2;
+        UpdGroup<PRECOND, T, G> gr;
+        gr.load(g, a, cv, p, cb + w, ce, lane);
+        if (!update_alpha(g, a, s, j, alpha_d)) return;
+        const T alpha = (T)alpha_d;
         T *__restrict__ ev = cv.e;
         T *__restrict__ rv = cv.r;
         T *__restrict__ zv = cv.z;
-        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            ColSlot cs[G2];
-            T pu[G2], ru[G2], qu[G2], du[G2], eu[G2], rdu[G2], tu[G2];
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G) {
+            if (c0 != cb + w) gr.load(g, a, cv, p, c0, ce, lane);
 #pragma unroll
-            for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-#pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const size_t i = cs[u].i;
-                pu[u] = p[i];
-                ru[u] = rv[i];
-                qu[u] = cv.q[i];
-                du[u] = cv.diag[i];
-                eu[u] = ev[i];
-                if (PRECOND == RF_PRECOND_ZLINE) {
-                    rdu[u] = cv.rdp[i];
-                    tu[u] = cv.tz[i];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const bool act = cs[u].act;
-                const size_t i = cs[u].i;
-                const T r = act ? ru[u] - alpha * qu[u] : T(0);
+            for (int u = 0; u < G; u++) {
+                const bool act = gr.cs[u].act;
+                const size_t i = gr.cs[u].i;
+                const T r = act ? gr.r[u] - alpha * gr.q[u] : T(0);
                 if (act) {
-                    ev[i] = eu[u] + alpha * pu[u];
+                    ev[i] = gr.e[u] + alpha * gr.p[u];
                     rv[i] = r;
-                    v[1] = fmax(v[1], (double)fabs(r / du[u]));
+                    v[1] = fmax(v[1], (double)fabs(r / gr.d[u]));
                 }
                 if (PRECOND == RF_PRECOND_JACOBI) {
-                    if (act) v[0] += (double)r * (double)(r / du[u]);
+                    if (act) v[0] += (double)r * (double)(r / gr.d[u]);
                 } else {
-                    const T zk = zline_solve_short<T>(r, act ? rdu[u] : T(0), act ? tu[u] : T(0), lane);
+                    const T zk = zline_solve_short<T>(r, act ? gr.rd[u] : T(0), act ? gr.t[u] : T(0), lane);
                     if (act) {
                         zv[i] = zk;
                         v[0] += (double)r * (double)zk;
@@ -998,6 +1055,8 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
         block_partial<2, 2u>(v, a.pr);
         return;
     }
+    if (!update_alpha(g, a, s, j, alpha_d)) return;
+    const T alpha = (T)alpha_d;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         const size_t base = (size_t)col * g.nz;
@@ -1040,6 +1099,27 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
+    const double *__restrict__ hmv = (m & 1) ? a.hb1 : a.hb0;
+    double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
+    const T *__restrict__ ev = e_in;
+    int cb, ce;
+    block_columns(g, g.cpb, cb, ce);
+    RF_WAVE_IDS;
+    // short columns: the first group of e and h^m is in flight while the
+    // partials are combined
+    ColSlot cs[kColGroup];
+    double e[kColGroup], hv[kColGroup];   // e widened to FP64
+    auto load = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < kColGroup; u++)
+            cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+#pragma unroll
+        for (int u = 0; u < kColGroup; u++) {
+            e[u] = (double)ev[cs[u].i];
+            hv[u] = hmv[cs[u].i];
+        }
+    };
+    if (g.nz <= kWave) load(cb + w);
     double tot[2];
     reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
     // the exit tolerance of this solve (fixed by its first direction update)
@@ -1061,25 +1141,10 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
         }
         return;
     }
-    const double *__restrict__ hmv = (m & 1) ? a.hb1 : a.hb0;
-    double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
-    const T *__restrict__ ev = e_in;
-    int cb, ce;
-    block_columns(g, g.cpb, cb, ce);
-    RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
     if (g.nz <= kWave) {
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * kColGroup) {
-            ColSlot cs[kColGroup];
-            double e[kColGroup], hv[kColGroup];   // e widened to FP64
-#pragma unroll
-            for (int u = 0; u < kColGroup; u++)
-                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-#pragma unroll
-            for (int u = 0; u < kColGroup; u++) {
-                e[u] = (double)ev[cs[u].i];
-                hv[u] = hmv[cs[u].i];
-            }
+            if (c0 != cb + w) load(c0);
 #pragma unroll
             for (int u = 0; u < kColGroup; u++) {
                 if (!cs[u].act) continue;
@@ -1356,7 +1421,8 @@ hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, int variant, hipStream_t s)
 {
-    RF_LAUNCH_W(k_coeff, g, so, a, m, dt, chord_eps, variant);
+    if (so.model == RF_GARDNER) RF_LAUNCH((k_coeff<RF_GARDNER>), g, so, a, m, dt, chord_eps, variant);
+    RF_LAUNCH((k_coeff<RF_VGM>), g, so, a, m, dt, chord_eps, variant);
 }
 
 // The PCG arrays of the FP64 solve: the workspace arrays themselves.

@@ -48,6 +48,32 @@ __device__ __forceinline__ void soil_eval(int model, double h, const Layer &L, d
     K = ks * sqSe * w * w;
 }
 
+// van Genuchten-Mualem without a branch on the sign of h: a saturated cell
+// evaluates the unsaturated forms at h = -1 m and takes the saturated values
+// (theta~ = theta_s + S h, C = S, K = Ks).  Unsaturated cells get exactly the
+// arithmetic of soil_eval; the straight-line code lets the evaluations of
+// several cells interleave.
+__device__ __forceinline__ void soil_eval_vgm_flat(double h, const Layer &L, double ks, double &th,
+                                                   double &C, double &K)
+{
+    const bool sat = h >= 0.0;
+    const double hu = sat ? -1.0 : h;
+    const double lu = L.n * log(-L.a * hu);    // log u
+    const double u = exp(lu);
+    const bool small = u <= 1.0;
+    const double t = small ? u : 1.0 / u;      // min(u, 1/u)
+    const double lp = log1p(t);
+    const double l1 = small ? lp : lu + lp;    // log(1 + u)
+    const double lq = small ? lp - lu : lp;    // log(1 + 1/u)
+    const double sqSe = exp(-0.5 * L.m * l1);  // Se^(1/2)
+    const double Se = sqSe * sqSe;
+    const double frac = 1.0 / (1.0 + (small ? 1.0 / u : t));   // u / (1 + u)
+    const double w = -expm1(-L.m * lq);
+    th = sat ? L.ts + L.S * h : L.tr + (L.ts - L.tr) * Se;
+    C = sat ? L.S : (L.ts - L.tr) * L.n * L.m * Se * frac / (-hu);
+    K = sat ? ks : ks * sqSe * w * w;
+}
+
 __device__ __forceinline__ double soil_theta(int model, double h, const Layer &L)
 {
     if (h >= 0.0) return L.ts + L.S * h;

@@ -1,0 +1,179 @@
+// Cross-lane primitives of a 64-lane wavefront on gfx950 (GFX9 DPP).
+//
+// The column recurrences of the solver (vertical neighbours, the z-line
+// forward/backward sweeps and the tridiagonal pivots) need shifts and
+// prefix scans across the lanes of one wave.  Written with __shfl_* they
+// compile to ds_bpermute, a round trip through the LDS crossbar per 32-bit
+// value and scan step.  Here the shifts use DPP modifiers (executed by the
+// VALU): row_shr/row_shl move data inside each 16-lane row, wave_shr/wave_shl
+// move the whole wave by one lane, and the four rows of a scan are chained
+// through v_readlane (the row ends become wave-uniform values).
+//
+// Every function must be called with all 64 lanes active (wave-uniform
+// control flow): a DPP source lane that is switched off is not read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <type_traits>
+
+namespace rf {
+
+// DPP control codes (GFX9 encoding).
+enum : int {
+    kDppRowShl = 0x100,   // + k: lane i of a row reads lane i + k of the same row
+    kDppRowShr = 0x110,   // + k: lane i of a row reads lane i - k of the same row
+    kDppWaveShl1 = 0x130, // lane i reads lane i + 1 (lane 63: no source)
+    kDppWaveShr1 = 0x138, // lane i reads lane i - 1 (lane 0: no source)
+};
+
+// x moved by the DPP pattern CTRL; lanes without a source lane get `old`.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x, float old)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL,
+                                                      0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x, double old)
+{
+    const long long xi = __double_as_longlong(x), oi = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)xi, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(xi >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Value of lane L (wave-uniform result).
+template <int L>
+__device__ __forceinline__ float lane_value(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), L));
+}
+
+template <int L>
+__device__ __forceinline__ double lane_value(double x)
+{
+    const long long xi = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)xi, L);
+    const int hi = __builtin_amdgcn_readlane((int)(xi >> 32), L);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// x of lane i - 1 (lane 0 gets `edge`) and of lane i + 1 (lane 63 gets `edge`).
+template <typename T>
+__device__ __forceinline__ T from_below(T x, T edge) { return dpp<kDppWaveShr1>(x, edge); }
+template <typename T>
+__device__ __forceinline__ T from_above(T x, T edge) { return dpp<kDppWaveShl1>(x, edge); }
+
+// Inclusive upward scan of affine maps x_k = a_k x_{k-1} + c_k over the
+// wave (k = lane); returns x_k for x_{-1} = carry.  Inside each 16-lane row
+// the maps are composed in four doubling steps (a lane whose partner lies
+// below its row composes with the identity); the rows are then chained from
+// the values at lanes 15, 31 and 47.
+template <typename T>
+__device__ __forceinline__ T scan_affine_up(T a, T c, T carry, int lane)
+{
+#define RF_UP_STEP(K)                                          \
+    {                                                          \
+        const T ao = dpp<kDppRowShr + (K)>(a, T(1));           \
+        const T co = dpp<kDppRowShr + (K)>(c, T(0));           \
+        c = a * co + c;                                        \
+        a = a * ao;                                            \
+    }
+    RF_UP_STEP(1) RF_UP_STEP(2) RF_UP_STEP(4) RF_UP_STEP(8)
+#undef RF_UP_STEP
+    const T y0 = lane_value<15>(a) * carry + lane_value<15>(c);
+    const T y1 = lane_value<31>(a) * y0 + lane_value<31>(c);
+    const T y2 = lane_value<47>(a) * y1 + lane_value<47>(c);
+    const int row = lane >> 4;
+    const T cin = (row == 0) ? carry : (row == 1) ? y0 : (row == 2) ? y1 : y2;
+    return a * cin + c;
+}
+
+// Inclusive downward scan of x_k = b_k x_{k+1} + c_k; x_64 = carry.  Rows
+// are chained from the values at lanes 48, 32 and 16.
+template <typename T>
+__device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
+{
+#define RF_DOWN_STEP(K)                                        \
+    {                                                          \
+        const T bo = dpp<kDppRowShl + (K)>(b, T(1));           \
+        const T co = dpp<kDppRowShl + (K)>(c, T(0));           \
+        c = b * co + c;                                        \
+        b = b * bo;                                            \
+    }
+    RF_DOWN_STEP(1) RF_DOWN_STEP(2) RF_DOWN_STEP(4) RF_DOWN_STEP(8)
+#undef RF_DOWN_STEP
+    const T y3 = lane_value<48>(b) * carry + lane_value<48>(c);
+    const T y2 = lane_value<32>(b) * y3 + lane_value<32>(c);
+    const T y1 = lane_value<16>(b) * y2 + lane_value<16>(c);
+    const int row = lane >> 4;
+    const T cin = (row == 3) ? carry : (row == 2) ? y3 : (row == 1) ? y2 : y1;
+    return b * cin + c;
+}
+
+// Scales (m00, m01, m10, m11) by the power of two that brings the largest
+// magnitude into [1, 2) (exact; zero stays zero).
+__device__ __forceinline__ void rescale4(double &m00, double &m01, double &m10, double &m11)
+{
+    const double sc = fmax(fmax(fabs(m00), fabs(m01)), fmax(fabs(m10), fabs(m11)));
+    const int ex = (sc > 0.0) ? ilogb(sc) : 0;
+    m00 = ldexp(m00, -ex); m01 = ldexp(m01, -ex); m10 = ldexp(m10, -ex); m11 = ldexp(m11, -ex);
+}
+
+__device__ __forceinline__ void rescale2(double &v0, double &v1)
+{
+    const double sc = fmax(fabs(v0), fabs(v1));
+    const int ex = (sc > 0.0) ? ilogb(sc) : 0;
+    v0 = ldexp(v0, -ex);
+    v1 = ldexp(v1, -ex);
+}
+
+// Pivots of a column tridiagonal T (diagonal diag_k, off-diagonal t_{k-1}
+// below and above): d_k = diag_k - t_{k-1}^2 / d_{k-1}.  The leading minors
+// obey P_k = diag_k P_{k-1} - t_{k-1}^2 P_{k-2}, so (P_k, P_{k-1}) is the
+// prefix product of the 2x2 matrices [[diag_k, -t_{k-1}^2], [1, 0]] applied
+// to (P_{k0-1}, P_{k0-2}); d_k = P_k / P_{k-1}.  Products are rescaled by
+// powers of two after every step (only ratios matter).  carry = d_{k0-1}
+// (0 for the first cells of the column, where (P_{-1}, P_{-2}) = (1, 0)).
+__device__ __forceinline__ double scan_pivots(double diag, double tprev2, double carry, int lane)
+{
+    double m00 = diag, m01 = -tprev2, m10 = 1.0, m11 = 0.0;
+#define RF_PIV_STEP(K)                                                      \
+    {                                                                       \
+        const double o00 = dpp<kDppRowShr + (K)>(m00, 1.0);                 \
+        const double o01 = dpp<kDppRowShr + (K)>(m01, 0.0);                 \
+        const double o10 = dpp<kDppRowShr + (K)>(m10, 0.0);                 \
+        const double o11 = dpp<kDppRowShr + (K)>(m11, 1.0);                 \
+        const double n00 = m00 * o00 + m01 * o10;                           \
+        const double n01 = m00 * o01 + m01 * o11;                           \
+        const double n10 = m10 * o00 + m11 * o10;                           \
+        const double n11 = m10 * o01 + m11 * o11;                           \
+        m00 = n00; m01 = n01; m10 = n10; m11 = n11;                         \
+        rescale4(m00, m01, m10, m11);                                       \
+    }
+    RF_PIV_STEP(1) RF_PIV_STEP(2) RF_PIV_STEP(4) RF_PIV_STEP(8)
+#undef RF_PIV_STEP
+    // (P, P_prev) entering each row: carry vector, then through the row ends
+    double u0 = (carry != 0.0) ? carry : 1.0, u1 = (carry != 0.0) ? 1.0 : 0.0;
+    double r0[4] = {u0, 0, 0, 0}, r1[4] = {u1, 0, 0, 0};
+#define RF_PIV_ROW(L, R)                                                        \
+    {                                                                           \
+        const double a00 = lane_value<L>(m00), a01 = lane_value<L>(m01);        \
+        const double a10 = lane_value<L>(m10), a11 = lane_value<L>(m11);        \
+        double w0 = a00 * u0 + a01 * u1, w1 = a10 * u0 + a11 * u1;              \
+        rescale2(w0, w1);                                                       \
+        u0 = w0; u1 = w1;                                                       \
+        r0[R] = u0; r1[R] = u1;                                                 \
+    }
+    RF_PIV_ROW(15, 1) RF_PIV_ROW(31, 2) RF_PIV_ROW(47, 3)
+#undef RF_PIV_ROW
+    const int row = lane >> 4;
+    const double v0 = (row == 0) ? r0[0] : (row == 1) ? r0[1] : (row == 2) ? r0[2] : r0[3];
+    const double v1 = (row == 0) ? r1[0] : (row == 1) ? r1[1] : (row == 2) ? r1[2] : r1[3];
+    return (m00 * v0 + m01 * v1) / (m10 * v0 + m11 * v1);
+}
+
+}  // namespace rf

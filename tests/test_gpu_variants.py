@@ -106,8 +106,65 @@ def run_both(orc, w, **opts):
 
 
 def test_loam_column_sec3_1_ebats_run(orc):
-    rs = run_both(orc, loam_sec3_1())
-    assert rs["rejected"] > 0            # the ponded top exercises the EBATS rerun path
+    """The library's own EBATS driver against the oracle's over the first
+    300 s: dt falls from 5 min to below 1 s through many reruns."""
+    w = loam_sec3_1()
+    w.t_end = 300.0
+    rs = run_both(orc, w)
+    assert rs["rejected"] > 10           # the ponded top exercises the EBATS rerun path
+
+
+def lockstep_ebats(orc, w, tol_picard=1e-6, max_flips=3, **opts):
+    """Both solvers stepped with the same dt, chosen by the EBATS rules
+    (Sec. 2.3) from the oracle's Picard counts.  Every step must give the
+    same Picard count (or the same rejection) and heads within 1e-8.  A
+    step whose count differs is accepted only at a borderline stopping
+    decision: at the first iteration where the two sides part, one delta is
+    below tol_picard and the other above, both within 5 % of it (a Picard
+    iterate sitting on a kink of the coefficients, such as h = 0, turns
+    rounding-level differences into a few per cent of delta).  The GPU is then
+    re-started from the oracle's state; at most max_flips such steps."""
+    import torch
+    assert not w.forcing
+    o = dict(ebats=0, max_picard=8, tol_picard=tol_picard, **opts)
+    P = make_oracle(orc, w, **o)
+    S = make_solver(w, precond=1, **o)
+    m = w.active_mask()
+    t, dt, easy, flips, steps, rejected = 0.0, w.dt, 0, 0, 0, 0
+    while t < w.t_end * (1 - 1e-15) - 1e-12:
+        d = min(dt, w.t_end - t)
+        s_o, st_o = P.step(d)
+        s_g, st_g = S.step(d)
+        steps += 1
+        if (s_o == 0) != (s_g == 0) or st_o["picard_iters"] != st_g["picard_iters"]:
+            do, dg = st_o["delta"], st_g["delta"]
+            k = next((i for i in range(min(len(do), len(dg)))
+                      if (do[i] < tol_picard) != (dg[i] < tol_picard)), None)
+            assert k is not None, (steps, do, dg)
+            assert all(abs(do[i] - dg[i]) <= 1e-8 * do[i] for i in range(k)), (steps, do, dg)
+            assert abs(do[k] - tol_picard) <= 0.05 * tol_picard, (steps, k, do, dg)
+            assert abs(dg[k] - tol_picard) <= 0.05 * tol_picard, (steps, k, do, dg)
+            flips += 1
+            assert flips <= max_flips, steps
+            h_o, t_o = P.get_state()
+            assert S.set_state(torch.tensor(h_o, dtype=torch.float64, device="cuda"), t_o) == 0
+        else:
+            assert rel_err(host(S.get_state()[0]), P.get_state()[0], m) <= 1e-8, steps
+        if s_o != 0:
+            rejected += 1
+            dt, easy = d / 1.3, 0
+            continue
+        t += d
+        easy = easy + 1 if st_o["picard_iters"] <= 3 else 0
+        if easy >= 10:
+            dt, easy = min(dt * 1.3, w.dt_max), 0
+    return steps, rejected, flips
+
+
+def test_loam_column_sec3_1_lockstep(orc):
+    """The whole hour of the ponded loam column, step by step."""
+    steps, rejected, flips = lockstep_ebats(orc, loam_sec3_1())
+    assert steps > 2000 and rejected > 50, (steps, rejected)
 
 
 def test_appendix_b_saturated_infiltration(orc):
