@@ -112,9 +112,12 @@ static void timed_begin(rf_ctx *c, int kernel, int m, int j, EvPair &p)
     p.kernel = -1;
     if (!((c->timing >> kernel) & 1)) return;
     if (c->freelist.empty()) {
+        // timing-only events: no system-scope fence (no L2 writeback and
+        // invalidate) at each record, so they do not slow the kernels they
+        // bracket and time those rather than the fences
         EvPair q;
-        (void)hipEventCreate(&q.a);
-        (void)hipEventCreate(&q.b);
+        (void)hipEventCreateWithFlags(&q.a, hipEventDisableSystemFence);
+        (void)hipEventCreateWithFlags(&q.b, hipEventDisableSystemFence);
         c->freelist.push_back(q);
     }
     p = c->freelist.back();
