@@ -6,7 +6,8 @@ coefficients, assembly, PCG solve, Picard exit test, step acceptance) on the
 3-D hillslope workload (128 x 128 x 64 cells, lognormal Ks, rain on top),
 inputs resident in HBM.  Prints ONE JSON line with the throughput in
 cell-steps/s, the roofline of the dominant kernel (HIP events on the library
-stream, inside the timed region) and the CPU oracle timed on a bounded sample.
+stream, inside the timed region; also against device copies measured on the
+same box, outside it) and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 144] [--warmup 5] [--workload hillslope]
                     [--precision fp64|mixed]
@@ -209,6 +210,39 @@ def timed_case(args, w, precision):
             "roofline": roof, "kernels_warmup": kernels}, h
 
 
+def copy_reference(nbytes, reps=20):
+    """Same-box reference rate: a device-to-device copy (the runtime's copy
+    kernel) of nbytes, read + write counted, GB/s."""
+    import torch
+    n = max(int(nbytes) // 16, 1)                     # nbytes moved = read n*8 + write n*8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 16.0 * n * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
+def add_copy_reference(roof):
+    """The roofline against copies measured on the same box: one moving the
+    dominant kernel's algorithmic bytes per launch (MALL-resident when the
+    working set is) and one of 1 GiB (from HBM)."""
+    if roof is None:
+        return
+    same = copy_reference(roof["algorithmic_bytes_per_launch"])
+    big = copy_reference(1 << 30)
+    roof["copy_reference_GBps"] = {"same_bytes": same, "1GiB": big}
+    roof["frac_of_copy"] = {"same_bytes": round(roof["achieved"] / same, 4),
+                            "1GiB": round(roof["achieved"] / big, 4)}
+
+
 def learned_guess(nsteps):
     """The committed network (trained on seeds 100-119) on held-out seed 200
     of the hillslope with its rain series: plain Picard in FP64 against the
@@ -260,7 +294,7 @@ def progress(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -294,6 +328,7 @@ def main():
     if not args.no_extras and args.ensemble_seconds > 0:
         progress("ensemble (child process)")
         ens_res = ensemble(args.ensemble_seconds)
+    add_copy_reference(main_r["roofline"])
     progress("cpu baseline")
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
     out = {
