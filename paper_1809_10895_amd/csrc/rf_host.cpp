@@ -299,27 +299,51 @@ static double next_forcing_change(const rf_ctx *c, double t)
     return tn;
 }
 
-static rf_status sync_scalars(rf_ctx *c)
+// Enqueues the copy of the nv-valued block partials of the last kernel into
+// the pinned host buffer (combine_partials reads them after a sync).
+static rf_status copy_partials(rf_ctx *c, const double *dev, int nv)
 {
-    HIPCHK(c, hipMemcpyAsync(c->hsc, c->A.sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hpart, dev + (size_t)c->G.foff * nv,
+                             (size_t)c->G.np * nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     return RF_OK;
 }
 
-// Copies the nv-valued block partials of the last kernel and combines them on
-// the host in block order (sum, or max where bit i of maxmask is set).
-static rf_status host_reduce(rf_ctx *c, const double *dev, int nv, unsigned maxmask, double *tot)
+// Combines copied partials on the host in block order (sum, or max where
+// bit i of maxmask is set).
+static void combine_partials(const rf_ctx *c, int nv, unsigned maxmask, double *tot)
 {
-    const int nb = c->G.np;
-    HIPCHK(c, hipMemcpyAsync(c->hpart, dev + (size_t)c->G.foff * nv, (size_t)nb * nv * sizeof(double),
-                             hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < nv; i++) tot[i] = 0.0;
-    for (int b = 0; b < nb; b++)
+    for (int b = 0; b < c->G.np; b++)
         for (int i = 0; i < nv; i++) {
             const double x = c->hpart[(size_t)b * nv + i];
             tot[i] = ((maxmask >> i) & 1u) ? std::max(tot[i], x) : tot[i] + x;
         }
+}
+
+// Reads the step's scalars back and waits.  With kAcceptSlots, also the
+// acceptance kernel's partials (storage, face inflows), in the same wait:
+// they are only used when the scalars say the step was accepted, and then
+// the acceptance kernel was the last one to write them.
+constexpr int kAcceptSlots = 7;
+static rf_status sync_scalars(rf_ctx *c, int partial_slots = 0)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hsc, c->A.sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    if (partial_slots) {
+        rf_status s = copy_partials(c, c->A.ps, partial_slots);
+        if (s) return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RF_OK;
+}
+
+// Copies the nv-valued block partials of the last kernel, waits, and
+// combines them.
+static rf_status host_reduce(rf_ctx *c, const double *dev, int nv, unsigned maxmask, double *tot)
+{
+    rf_status s = copy_partials(c, dev, nv);
+    if (s) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    combine_partials(c, nv, maxmask, tot);
     return RF_OK;
 }
 
@@ -711,7 +735,7 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     if (s) return s;
     rf_status status = RF_OK;
     for (;;) {
-        s = sync_scalars(c);
+        s = sync_scalars(c, kAcceptSlots);
         if (s) return s;
         const Scalars &h = *c->hsc;
         if (h.accepted) break;
@@ -775,9 +799,8 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     // prediction for the next step
     c->pred_picard = last_m + 1;
     for (int m = 0; m <= last_m && m < RF_MAX_PICARD_LOG; m++) c->pred_cg[m] = std::max(1, st->cg_iters[m]);
-    double sums[7];
-    s = host_reduce(c, A.ps, 7, 0u, sums);
-    if (s) return s;
+    double sums[kAcceptSlots];
+    combine_partials(c, kAcceptSlots, 0u, sums);   // copied with the last scalars
     c->storage = sums[0];
     for (int f = 0; f < 6; f++) c->inflow[f] += dt * sums[1 + f];
     c->t += dt;
