@@ -26,7 +26,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-enum { EPI_RELU = 0, EPI_LAST = 1, EPI_MASK = 2 };
+enum { EPI_RELU = 0, EPI_MASK = 2 };
 
 // Neighbour of cell (i, j, k) through tap t = 9 (di+1) + 3 (dj+1) + (dk+1);
 // false outside the grid (zero padding).
@@ -46,15 +46,26 @@ __device__ __forceinline__ bf16x8 zero8()
     return z;
 }
 
+// x of the lane whose index differs in bit 0 / bit 1 (DPP quad_perm, all
+// lanes of the quad active).
+__device__ __forceinline__ float dpp_quad_xor1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float dpp_quad_xor2(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
+
 // One convolution layer over one block patch: PX x PY columns and 64 cells
 // of z.  The patch's input plus a one-cell border (6 x 4 columns x 66 cells,
 // zero outside the grid) is staged in LDS once, with the layer's packed
 // weights; each of the eight wavefronts then computes one column, 16 output
 // channels x 64 cells per MFMA group, reading every tap's operand from LDS.
 // CIN: stored input channels (8 or 32); COB: output blocks of 16 channels (1
-// or 2).  EPI_RELU: out = bf16(relu(acc + bias)); EPI_LAST: outf = acc + bias
-// of channel 0 (FP32); EPI_MASK: out = bf16(acc) where mask > 0, else 0
-// (gradient through a ReLU).
+// or 2).  EPI_RELU: out = bf16(relu(acc + bias)); EPI_MASK: out = bf16(acc)
+// where mask > 0, else 0 (gradient through a ReLU).
 constexpr int PX = 4, PY = 2, TX = PX + 2, TY = PY + 2, TZ = 64 + 2;
 constexpr int kTileThreads = 64 * PX * PY;
 
@@ -62,8 +73,7 @@ template <int CIN, int COB, int EPI>
 __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__restrict__ in,
                                                        const bf16 *__restrict__ wp,
                                                        const float *__restrict__ bias,
-                                                       bf16 *__restrict__ out, float *__restrict__ outf,
-                                                       const bf16 *__restrict__ mask)
+                                                       bf16 *__restrict__ out, const bf16 *__restrict__ mask)
 {
     constexpr int STEPS = packed_steps(CIN);
     constexpr int NPK = STEPS * COB * 64;
@@ -129,10 +139,6 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
         const long cell = (long)col * g.nz + k;
 #pragma unroll
         for (int b = 0; b < COB; b++) {
-            if (EPI == EPI_LAST) {
-                if (b == 0 && q == 0) outf[cell] = acc[0][t][0] + bias[0];
-                continue;
-            }
             const int co0 = 16 * b + 4 * q;
             bf16x4 o;
             if (EPI == EPI_MASK) {
@@ -146,6 +152,73 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
             }
             *reinterpret_cast<bf16x4 *>(out + cell * kHid + co0) = o;
         }
+    }
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// The output layer (32 channels -> 1) is a matrix-vector product per cell: on
+// the 16 x 16 MFMA tile it would fill one output row of sixteen.  Here it
+// runs on the VALU with packed BF16 dot products (v_dot2_f32_bf16, FP32
+// accumulation), from the same LDS patch as k_conv: four adjacent lanes share
+// a cell, lane q taking channels 8q..8q+7, so that a wavefront's LDS reads
+// are consecutive 16-byte chunks (no bank conflicts) and its weight reads are
+// four-way broadcasts; the four partial sums of a cell are added with two
+// quad DPP exchanges.  A wavefront covers its column's 64 cells in four
+// passes of 16.  outf = sum + bias (FP32).
+__global__ void __launch_bounds__(kTileThreads) k_conv_out(NetGeo g, const bf16 *__restrict__ in,
+                                                           const bf16 *__restrict__ wp,
+                                                           const float *__restrict__ bias,
+                                                           float *__restrict__ outf)
+{
+    constexpr int CIN = kHid, CH = CIN / 8;
+    static_assert(CH == 4, "one lane per 16-byte chunk of a cell, four per cell");
+    __shared__ bf16x8 sW[kTaps * CH];
+    __shared__ bf16x8 sT[TX * TY * TZ * CH];
+    const int pxn = (g.nx + PX - 1) / PX;
+    const int zti = blockIdx.x % g.zt;
+    const int pxy = blockIdx.x / g.zt;
+    const int px0 = (pxy % pxn) * PX, py0 = (pxy / pxn) * PY, z0 = zti * 64;
+    // packed forward weights, one output block: step s, lane 16 q holds
+    // channels 8q..8q+7 of output channel 0 at tap s
+    const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
+    for (int e = threadIdx.x; e < kTaps * CH; e += kTileThreads) sW[e] = wv[(e / CH) * 64 + 16 * (e % CH)];
+    for (int e = threadIdx.x; e < TX * TY * TZ * CH; e += kTileThreads) {
+        const int part = e % CH, cz = e / CH;
+        const int zl = cz % TZ, cl = cz / TZ;
+        const int i = px0 - 1 + cl % TX, j = py0 - 1 + cl / TX, k = z0 - 1 + zl;
+        const bool ok = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const long cell = (long)k + (long)g.nz * ((long)i + (long)g.nx * j);
+        sT[e] = ok ? *reinterpret_cast<const bf16x8 *>(in + cell * CIN + 8 * part) : zero8();
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int cx = wave % PX, cy = wave / PX;
+    const int i = px0 + cx, j = py0 + cy;
+    if (i >= g.nx || j >= g.ny) return;            // whole wavefront
+    const int q = lane & 3, cc = lane >> 2;
+    const float b0 = bias[0];
+#pragma unroll
+    for (int pass = 0; pass < 4; pass++) {
+        const int kl = 16 * pass + cc;              // cell of the column's z-run
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < kTaps; tap++) {
+            const int di = tap / 9 - 1, dj = (tap / 3) % 3 - 1, dk = tap % 3 - 1;
+            const int cl = (cx + 1 + di) + TX * (cy + 1 + dj);
+            const bf16x8 x = sT[(cl * TZ + kl + 1 + dk) * CH + q];
+            const bf16x8 w = sW[tap * CH + q];
+#pragma unroll
+            for (int e = 0; e < 8; e += 2)
+                acc[e / 2] = __builtin_amdgcn_fdot2_f32_bf16(bf16x2{x[e], x[e + 1]}, bf16x2{w[e], w[e + 1]},
+                                                            acc[e / 2], false);
+        }
+        float sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        sum += dpp_quad_xor1(sum);
+        sum += dpp_quad_xor2(sum);
+        const int k = z0 + kl;
+        if (q == 0 && k < g.nz) outf[(long)(i + g.nx * j) * g.nz + k] = sum + b0;
     }
 }
 
@@ -413,13 +486,12 @@ hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s)
 {
     const dim3 grid(conv_grid(g)), block(kTileThreads);
     hipLaunchKernelGGL((k_conv<8, 2, EPI_RELU>), grid, block, 0, s, g, a.feat, a.wf[0], a.p + param_b(0),
-                       a.act[0], nullptr, nullptr);
+                       a.act[0], nullptr);
     hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[0], a.wf[1],
-                       a.p + param_b(1), a.act[1], nullptr, nullptr);
+                       a.p + param_b(1), a.act[1], nullptr);
     hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[1], a.wf[2],
-                       a.p + param_b(2), a.act[2], nullptr, nullptr);
-    hipLaunchKernelGGL((k_conv<32, 1, EPI_LAST>), grid, block, 0, s, g, a.act[2], a.wf[3],
-                       a.p + param_b(3), nullptr, a.y, nullptr);
+                       a.p + param_b(2), a.act[2], nullptr);
+    hipLaunchKernelGGL(k_conv_out, grid, block, 0, s, g, a.act[2], a.wf[3], a.p + param_b(3), a.y);
     return hipGetLastError();
 }
 
@@ -467,15 +539,15 @@ hipError_t net_backward(const NetGeo &g, const NetArrays &a, hipStream_t s)
     // layer 4 (index 3): input a3, output gradient dz3
     if ((e = grads_of_layer(g, a, 3, a.act[2], a.dz3, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_conv<8, 2, EPI_MASK>), grid, block, 0, s, g, a.dz3, a.wb[3], nullptr, a.dz[0],
-                       nullptr, a.act[2]);
+                       a.act[2]);
     // layer 3 (index 2): input a2, output gradient dz[0]
     if ((e = grads_of_layer(g, a, 2, a.act[1], a.dz[0], s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_conv<32, 2, EPI_MASK>), grid, block, 0, s, g, a.dz[0], a.wb[2], nullptr,
-                       a.dz[1], nullptr, a.act[1]);
+                       a.dz[1], a.act[1]);
     // layer 2 (index 1): input a1, output gradient dz[1]
     if ((e = grads_of_layer(g, a, 1, a.act[0], a.dz[1], s)) != hipSuccess) return e;
     hipLaunchKernelGGL((k_conv<32, 2, EPI_MASK>), grid, block, 0, s, g, a.dz[1], a.wb[1], nullptr,
-                       a.dz[0], nullptr, a.act[0]);
+                       a.dz[0], a.act[0]);
     // layer 1 (index 0): input features, output gradient dz[0]
     return grads_of_layer(g, a, 0, a.feat, a.dz[0], s);
 }
