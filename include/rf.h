@@ -82,6 +82,16 @@ enum { RF_PICARD_CHORD = 0, RF_PICARD_MODIFIED = 1 };
  * or a change of options); the loop still runs to tol_picard, so only the
  * number of iterations changes. */
 enum { RF_FIRST_PREVIOUS = 0, RF_FIRST_EXTRAPOLATE = 1 };
+/* When the z-line preconditioner (the exact LDL^T factorisation of each
+ * column's vertical tridiagonal, standing in for the DIC of Sec. 2.2) is
+ * factorised.
+ * RF_REFACTOR_EVERY: every Picard iteration, from that iteration's matrix.
+ * RF_REFACTOR_STEP: at the first Picard iteration of each step; the later
+ * iterations of the step precondition with those factors.  A preconditioner
+ * does not change the solution of the linear system (only how many PCG
+ * iterations reach the tolerance), so the Picard iterates are those of
+ * RF_REFACTOR_EVERY to within the PCG tolerance. */
+enum { RF_REFACTOR_EVERY = 0, RF_REFACTOR_STEP = 1 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -114,6 +124,7 @@ typedef struct {
                            (0 = the absolute test alone, the default) */
     int picard_variant; /* RF_PICARD_CHORD (default) or RF_PICARD_MODIFIED */
     int first_iterate;  /* RF_FIRST_PREVIOUS (default) or RF_FIRST_EXTRAPOLATE */
+    int zline_refactor; /* RF_REFACTOR_EVERY (default) or RF_REFACTOR_STEP */
 } rf_options;
 
 typedef struct {

@@ -384,6 +384,7 @@ void rf_default_options(rf_options *o)
     o->cg_rel_tol = 0.0;
     o->picard_variant = RF_PICARD_CHORD;
     o->first_iterate = RF_FIRST_PREVIOUS;
+    o->zline_refactor = RF_REFACTOR_EVERY;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -568,7 +569,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         o->cols_per_wave < 0 || (o->precision != RF_PREC_FP64 && o->precision != RF_PREC_MIXED) ||
         !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0) ||
         (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED) ||
-        (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE))
+        (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE) ||
+        (o->zline_refactor != RF_REFACTOR_EVERY && o->zline_refactor != RF_REFACTOR_STEP))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {
         // the FP32 arrays exist only in a workspace laid out for them
@@ -698,7 +700,9 @@ static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
     if (m > 0) TIMED(c, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
     TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps,
                                           c->opt.picard_variant, c->stream));
-    TIMED(c, K_RESID, m, -1, launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), c->stream));
+    const bool refactor = (m == 0) || c->opt.zline_refactor == RF_REFACTOR_EVERY;
+    TIMED(c, K_RESID, m, -1,
+          launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), refactor, c->stream));
     rf_status s = enqueue_pairs(c, m, std::max(1, c->pred_cg[mi]));
     if (s) return s;
     return enqueue_apply(c, m);
@@ -917,7 +921,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
                            c->stream));
-    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, c->stream));
+    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, true, c->stream));
     if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->assembled = true;

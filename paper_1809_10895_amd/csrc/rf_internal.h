@@ -130,8 +130,10 @@ struct CgTol {
     int max_cg;
 };
 
+// refactor: compute (and store) the z-line factors of this iteration's matrix;
+// otherwise the stored ones are used.
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        bool mixed, hipStream_t s);
+                        bool mixed, bool refactor, hipStream_t s);
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
                        const CgTol &t, hipStream_t s);
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,

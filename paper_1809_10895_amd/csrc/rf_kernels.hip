@@ -577,11 +577,13 @@ __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 // with K_f = (K_P + K_N)/2 and T_f = A_f K_f / d_f; r = b - A h^m (the
 // right-hand side of the increment system A e = r, e0 = 0); e = 0.
 // Jacobi: z = r / diag.  z-line: t_k (vertical couplings) and reciprocal
-// pivots of each column, z = M^-1 r.  Block partials of (r.z, max|r/diag|).
+// pivots of each column (refactor = 1), or those stored by the step's first
+// Picard iteration (refactor = 0), and z = M^-1 r with them.  Block partials of (r.z, max|r/diag|).
 // Everything is computed in FP64; the PCG arrays v receive it in the
 // precision T of the solve (FP32 copies of K and Dd as well when T is float).
 template <int PRECOND, typename T>
-__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv, int m, double *bout)
+__global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv, int m, double *bout,
+                                                    int refactor)
 {
     constexpr bool kCopyKD = !std::is_same<T, double>::value;
     Scalars *s = a.sc;
@@ -601,6 +603,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
             bool nb[G2][4];
             size_t in[G2][4];
             double Kp[G2], hp[G2], Dp[G2], bp[G2], Kn[G2][4], hn[G2][4];
+            double tzs[G2], rds[G2];   // stored z-line factors (reused when not refactoring)
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
@@ -613,6 +616,10 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                 hp[u] = hmv[i];
                 Dp[u] = a.Dd[i];
                 bp[u] = a.bst[i];
+                if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
+                    tzs[u] = (double)cv.tz[i];
+                    rds[u] = (double)cv.rdp[i];
+                }
 #pragma unroll
                 for (int d = 0; d < 4; d++) {
                     Kn[u][d] = a.K[in[u][d]];
@@ -665,15 +672,27 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                     if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
                 }
                 if (PRECOND == RF_PRECOND_ZLINE) {
-                    const double tprev = from_below(tup, 0.0);
-                    const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
-                    const double rdp = act ? 1.0 / dpiv : 0.0;
+                    // factors of this iteration's column tridiagonal, or the
+                    // stored ones of the step's first iteration
+                    double tzv, rdp;
+                    if (refactor) {
+                        const double tprev = from_below(tup, 0.0);
+                        const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
+                        tzv = tup;
+                        rdp = act ? 1.0 / dpiv : 0.0;
+                    } else {
+                        tzv = act ? tzs[u] : 0.0;
+                        rdp = act ? rds[u] : 0.0;
+                    }
+                    const double tprev = from_below(tzv, 0.0);
                     const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
-                    const double zk = scan_affine_down<double>(tup * rdp, wk, 0.0, lane);
+                    const double zk = scan_affine_down<double>(tzv * rdp, wk, 0.0, lane);
                     if (act) {
                         const T zs = (T)zk;
-                        cv.tz[i] = (T)tup;
-                        cv.rdp[i] = (T)rdp;
+                        if (refactor) {
+                            cv.tz[i] = (T)tup;
+                            cv.rdp[i] = (T)rdp;
+                        }
                         cv.z[i] = zs;
                         v[0] += (double)rs * (double)zs;
                     }
@@ -686,7 +705,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
         const size_t base = (size_t)col * g.nz;
         // carries between chunks of a long column (z-line only)
         double t_carry = 0.0, d_carry = 0.0, w_carry = 0.0;
-        double r = 0.0, tup = 0.0, rdp = 0.0, wk = 0.0;
+        double r = 0.0, tup = 0.0, tzv = 0.0, rdp = 0.0, wk = 0.0;
         for (int k0 = 0; k0 < kt; k0 += kWave) {
             const int k = k0 + lane;
             const bool act = k < kt;
@@ -722,18 +741,28 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                 if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)(T)r * (double)((T)r / (T)diag);
             }
             if (PRECOND == RF_PRECOND_ZLINE) {
-                // couplings and pivots of the column tridiagonal, in registers
-                const double tprev = from_below(tup, t_carry);
-                const double dpiv = scan_pivots(act ? diag : 1.0, act ? tprev * tprev : 0.0,
-                                                d_carry, lane);
-                rdp = act ? 1.0 / dpiv : 0.0;
+                // couplings and pivots of the column tridiagonal, in registers,
+                // or the stored ones of the step's first iteration
+                if (refactor) {
+                    const double tprev = from_below(tup, t_carry);
+                    const double dpiv = scan_pivots(act ? diag : 1.0, act ? tprev * tprev : 0.0,
+                                                    d_carry, lane);
+                    rdp = act ? 1.0 / dpiv : 0.0;
+                    d_carry = lane_value<kWave - 1>(dpiv);
+                    tzv = tup;
+                } else {
+                    tzv = act ? (double)cv.tz[base + k] : 0.0;
+                    rdp = act ? (double)cv.rdp[base + k] : 0.0;
+                }
+                const double tprev = from_below(tzv, t_carry);
                 wk = scan_affine_up<double>(tprev * rdp, r * rdp, w_carry, lane);
-                t_carry = lane_value<kWave - 1>(tup);
-                d_carry = lane_value<kWave - 1>(dpiv);
+                t_carry = lane_value<kWave - 1>(tzv);
                 w_carry = lane_value<kWave - 1>(wk);
                 if (act) {
-                    cv.tz[base + k] = (T)tup;
-                    cv.rdp[base + k] = (T)rdp;
+                    if (refactor) {
+                        cv.tz[base + k] = (T)tup;
+                        cv.rdp[base + k] = (T)rdp;
+                    }
                     if (kt > kWave) cv.z[base + k] = (T)wk;   // forward sweep, re-read by this lane
                 }
             }
@@ -742,7 +771,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
             // backward sweep z_k = w_k + t_k rdp_k z_{k+1}
             if (kt <= kWave) {
                 const bool act = lane < kt;
-                const double zk = scan_affine_down<double>(act ? tup * rdp : 0.0, act ? wk : 0.0,
+                const double zk = scan_affine_down<double>(act ? tzv * rdp : 0.0, act ? wk : 0.0,
                                                            0.0, lane);
                 if (act) {
                     const T zs = (T)zk;
@@ -1432,13 +1461,15 @@ static CgVec<double> dvec(const Arrays &a)
 }
 
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        bool mixed, hipStream_t s)
+                        bool mixed, bool refactor, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
-    if (mixed && zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout);
-    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout);
-    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m, bout);
-    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m, bout);
+    const int rf = refactor ? 1 : 0;
+    if (mixed && zl)
+        RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
+    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout, rf);
+    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m, bout, rf);
+    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m, bout, rf);
 }
 
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,

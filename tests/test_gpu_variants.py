@@ -205,3 +205,26 @@ def test_extrapolated_first_iterate(orc, case):
         h_prev = h_now
     if case == "column100":
         assert it_ex < it_plain, (it_ex, it_plain)
+
+
+@pytest.mark.parametrize("case", ["column100", "small_3d", "hillslope_slice"])
+def test_zline_factored_once_per_step(orc, case):
+    """zline_refactor = RF_REFACTOR_STEP: Picard iterations after the first
+    precondition with the first iteration's column factors.  The oracle (DIC,
+    refactored every time) gives the same Picard counts and heads: the
+    preconditioner changes how PCG reaches tol_cg, not where."""
+    if case == "column100":
+        w, n = W.column100(), 30
+    elif case == "small_3d":
+        w, n = small_3d(), 5
+    else:
+        w, n = W.hillslope(nx=24, ny=20, nz=64), 4
+    P = make_oracle(orc, w)
+    S = make_solver(w, precond=1, zline_refactor=1)
+    m = w.active_mask()
+    for k in range(n):
+        s_o, st_o = P.step(w.dt)
+        s_g, st_g = S.step(w.dt)
+        assert s_o == 0 and s_g == 0, S.last_error()
+        assert st_g["picard_iters"] == st_o["picard_iters"], (k, st_g, st_o)
+        assert rel_err(host(S.get_state()[0]), P.get_state()[0], m) <= 1e-8, k
