@@ -15,10 +15,13 @@
  *   z2 = conv(a1; 32 -> 32) + b2, a2 = relu(z2)
  *   z3 = conv(a2; 32 -> 32) + b3, a3 = relu(z3)
  *   y  = conv(a3; 32 -> 1) + b4
- *   h^{n+1,0} = h^n + 0.01 m * y
+ *   h^{n+1,0} = h^n + (h^n - h^{n-1}) + 0.01 m * y
+ * i.e. the network corrects the linear extrapolation in time of the last
+ * accepted increment (an untrained network, y = 0, returns that
+ * extrapolation; h^{n-1} = h^n gives h^n plus the correction).
  * Weights are held in FP32 (the trained copy) and used as BF16; activations
- * are BF16, every product accumulates in FP32 on the matrix cores
- * (v_mfma_f32_16x16x32_bf16).  Training minimises the mean square of
+ * are BF16, every product accumulates in FP32 (v_mfma_f32_16x16x32_bf16 on
+ * the matrix cores; the 32 -> 1 layer with v_dot2_f32_bf16).  Training minimises the mean square of
  * (h^{n+1,0} - h^{n+1}) / 0.01 m over the grid against solver-converged
  * states, with hand-written backward kernels and Adam.
  *

@@ -113,19 +113,26 @@ def forward(params, f, rnd=False):
     return y, xs
 
 
+def first_iterate(hn, hprev, y):
+    """h^{n+1,0} = h^n + (h^n - h^{n-1}) + 0.01 m y: the network's output y
+    corrects the linear extrapolation in time."""
+    hn, hprev = np.asarray(hn, dtype=np.float64), np.asarray(hprev, dtype=np.float64)
+    return hn + (hn - hprev) + OUT_SCALE * np.asarray(y, dtype=np.float64).reshape(hn.shape)
+
+
 def predict(params, hn, hprev, lnks, rain, shape, rnd=False):
     y, _ = forward(params, features(hn, hprev, lnks, rain, shape), rnd)
-    return np.asarray(hn) + OUT_SCALE * y.reshape(-1)
+    return first_iterate(hn, hprev, y.reshape(-1))
 
 
 def loss_and_grad(params, hn, hprev, lnks, rain, target, shape, rnd=False):
-    """Loss 0.5/N sum ((h^n + 0.01 y - target) / 0.01)^2 and its parameter gradient."""
+    """Loss 0.5/N sum ((h^{n+1,0} - target) / 0.01 m)^2 and its parameter gradient."""
     nx, ny, nz = shape
     N = nx * ny * nz
     f = features(hn, hprev, lnks, rain, shape)
     Ws, bs = unpack(params, rnd)
     y, xs = forward(params, f, rnd)
-    r = (np.asarray(hn).reshape(ny, nx, nz) + OUT_SCALE * y
+    r = (first_iterate(hn, hprev, y.reshape(-1)).reshape(ny, nx, nz)
          - np.asarray(target).reshape(ny, nx, nz)) / OUT_SCALE
     loss = 0.5 * np.sum(r * r) / N
     d = (r / N)[..., None]

@@ -368,19 +368,27 @@ __global__ void k_features(NetGeo g, const double *__restrict__ hn, const double
     *reinterpret_cast<bf16x8 *>(feat + c * kFeat) = f;
 }
 
+// The network predicts a correction to the linear extrapolation in time:
+// h^{n+1,0} = h^n + (h^n - h^{n-1}) + 0.01 m y.
+__device__ __forceinline__ double guess_of(double hn, double hp, float y)
+{
+    return hn + (hn - hp) + kOutScale * (double)y;
+}
+
 __global__ void k_output(NetGeo g, const float *__restrict__ y, const double *__restrict__ hn,
-                         double *__restrict__ guess)
+                         const double *__restrict__ hp, double *__restrict__ guess)
 {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.ncell) return;
-    guess[c] = hn[c] + kOutScale * (double)y[c];
+    guess[c] = guess_of(hn[c], hp[c], y[c]);
 }
 
-// r = (h^n + 0.01 y - target) / 0.01 m (the error in units of the output
+// r = (h^{n+1,0} - target) / 0.01 m (the error in units of the output
 // scale, so that gradients stay well above Adam's epsilon); loss partials of
 // 0.5 r^2 / N; dz3 = dL/dy = r / N.
 __global__ void __launch_bounds__(256) k_loss(NetGeo g, const float *__restrict__ y,
                                               const double *__restrict__ hn,
+                                              const double *__restrict__ hp,
                                               const double *__restrict__ target, bf16 *__restrict__ dz3,
                                               double *__restrict__ lpart)
 {
@@ -388,7 +396,7 @@ __global__ void __launch_bounds__(256) k_loss(NetGeo g, const float *__restrict_
     const double inv = 1.0 / (double)g.ncell;
     double acc = 0.0;
     for (long c = (long)blockIdx.x * 256 + threadIdx.x; c < g.ncell; c += (long)gridDim.x * 256) {
-        const double r = (hn[c] + kOutScale * (double)y[c] - target[c]) / kOutScale;
+        const double r = (guess_of(hn[c], hp[c], y[c]) - target[c]) / kOutScale;
         acc += 0.5 * r * r * inv;
         bf16x8 d = zero8();
         d[0] = (bf16)(float)(r * inv);
@@ -495,17 +503,19 @@ hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t net_output(const NetGeo &g, const NetArrays &a, const double *hn, double *guess, hipStream_t s)
+hipError_t net_output(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
+                      double *guess, hipStream_t s)
 {
     hipLaunchKernelGGL(k_output, dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g, a.y, hn,
-                       guess);
+                       hprev, guess);
     return hipGetLastError();
 }
 
-hipError_t net_loss(const NetGeo &g, const NetArrays &a, const double *hn, const double *target,
-                    hipStream_t s)
+hipError_t net_loss(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
+                    const double *target, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_loss, dim3(a.lblocks), dim3(256), 0, s, g, a.y, hn, target, a.dz3, a.lpart);
+    hipLaunchKernelGGL(k_loss, dim3(a.lblocks), dim3(256), 0, s, g, a.y, hn, hprev, target, a.dz3,
+                       a.lpart);
     return hipGetLastError();
 }
 

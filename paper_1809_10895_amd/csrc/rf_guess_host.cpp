@@ -107,7 +107,7 @@ static rf_status forward_loss(rf_guess *g, const double *hn, const double *hprev
 {
     GHIP(g, net_features(g->G, g->A, hn, hprev, lnks, rain, g->stream));
     GHIP(g, net_forward(g->G, g->A, g->stream));
-    GHIP(g, net_loss(g->G, g->A, hn, target, g->stream));
+    GHIP(g, net_loss(g->G, g->A, hn, hprev, target, g->stream));
     GHIP(g, net_backward(g->G, g->A, g->stream));
     GHIP(g, hipMemcpyAsync(g->hloss, g->A.lpart, kLossBlocks * sizeof(double), hipMemcpyDeviceToHost,
                            g->stream));
@@ -223,7 +223,7 @@ rf_status rf_guess_predict(rf_guess *g, const double *hn, const double *hprev, c
     if (!std::isfinite(rain)) return gfail(g, RF_ERR_ARG, "non-finite rain");
     GHIP(g, net_features(g->G, g->A, hn, hprev, lnks, rain, g->stream));
     GHIP(g, net_forward(g->G, g->A, g->stream));
-    GHIP(g, net_output(g->G, g->A, hn, guess_dev, g->stream));
+    GHIP(g, net_output(g->G, g->A, hn, hprev, guess_dev, g->stream));
     GHIP(g, hipStreamSynchronize(g->stream));
     return RF_OK;
 }

@@ -21,7 +21,7 @@ constexpr int kCout[kNetLayers] = {32, 32, 32, 1};
 constexpr double kHScale = 10.0;       // h^n feature: h / 10 m
 constexpr double kDhScale = 100.0;     // (h^n - h^{n-1}) * 100 / m
 constexpr double kRainScale = 1e7;     // rain * 1e7 s/m
-constexpr double kOutScale = 0.01;     // h^{n+1,0} = h^n + 0.01 m * y
+constexpr double kOutScale = 0.01;     // h^{n+1,0} = h^n + (h^n - h^{n-1}) + 0.01 m * y
 
 // Offsets of W_l and b_l in the FP32 parameter vector.
 constexpr int param_w(int l)
@@ -72,10 +72,10 @@ hipError_t net_pack(const NetArrays &a, hipStream_t s);
 hipError_t net_features(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
                         const double *lnks, double rain, hipStream_t s);
 hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s);
-hipError_t net_output(const NetGeo &g, const NetArrays &a, const double *hn, double *guess,
-                      hipStream_t s);
-hipError_t net_loss(const NetGeo &g, const NetArrays &a, const double *hn, const double *target,
-                    hipStream_t s);
+hipError_t net_output(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
+                      double *guess, hipStream_t s);
+hipError_t net_loss(const NetGeo &g, const NetArrays &a, const double *hn, const double *hprev,
+                    const double *target, hipStream_t s);
 hipError_t net_backward(const NetGeo &g, const NetArrays &a, hipStream_t s);
 hipError_t net_adam(const NetArrays &a, float lr, float bc1, float bc2, hipStream_t s);
 

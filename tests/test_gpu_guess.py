@@ -38,7 +38,8 @@ def test_forward_matches_reference():
     G.set_params(p)
     got = G.predict(dev(hn), dev(hp), dev(lnks), 3e-7).cpu().numpy()
     want = R.predict(p.astype(np.float64), hn, hp, lnks, 3e-7, SHAPE, rnd=True)
-    y_g, y_r = (got - hn) / R.OUT_SCALE, (want - hn) / R.OUT_SCALE
+    base = hn + (hn - hp)                     # the extrapolation the network corrects
+    y_g, y_r = (got - base) / R.OUT_SCALE, (want - base) / R.OUT_SCALE
     # both sides round the same stored quantities to BF16; FP32 vs FP64 sums
     # can move an activation across a BF16 rounding boundary (2^-8 relative)
     assert np.abs(y_g - y_r).max() <= 2e-2 * np.abs(y_r).max()
@@ -61,11 +62,11 @@ def test_gradient_matches_reference():
             assert rel <= 3e-2, (l, a, rel)
 
 
-def test_untrained_network_returns_h_n():
+def test_untrained_network_returns_the_extrapolation():
     hn, hp, lnks, _ = sample(SHAPE, 3)
     G = Guess(*SHAPE, seed=1)
     got = G.predict(dev(hn), dev(hp), dev(lnks), 0.0).cpu().numpy()
-    assert np.array_equal(got, hn)
+    assert np.array_equal(got, hn + (hn - hp))
 
 
 def test_training_fits_one_solver_step():
@@ -80,10 +81,12 @@ def test_training_fits_one_solver_step():
 
 
 def test_learned_guess_cuts_picard_iterations():
-    """Trained on eight seeds of a 48 x 48 x 64 hillslope (24 steps each, 6000 Adam steps),
-    evaluated on a held-out seed: the guess is far closer to the converged
-    state than h^n or a linear extrapolation, plain Picard from it needs
-    fewer iterations, and the converged states agree."""
+    """Trained on eight seeds of a 48 x 48 x 64 hillslope (24 steps each, 6000
+    Adam steps), evaluated on a held-out seed.  The network corrects the
+    linear extrapolation in time (its zero-parameter form), and its first
+    iterate is far closer to the converged state than that extrapolation;
+    plain Picard from it needs fewer iterations than from h^n and no more
+    than from the extrapolation, and the converged states agree."""
     nx, ny, nz, nsteps = 48, 48, 64, 24
     trajs = [learned.trajectory(s, nsteps, nx=nx, ny=ny, nz=nz)[0] for s in range(100, 108)]
     params, losses = learned.train(trajs, (nx, ny, nz), 6000, crop_xy=(32, 32), lr=3e-4)
@@ -95,13 +98,13 @@ def test_learned_guess_cuts_picard_iterations():
         return np.mean([G.gradient(val.states[n], val.states[max(n - 1, 0)], val.lnks, val.rain[n],
                                    val.states[n + 1])[0] for n in range(nsteps)])
 
-    zero = val_loss(np.zeros_like(params))
-    extrap = np.mean([0.5 * float((((2 * val.states[n] - val.states[max(n - 1, 0)])
-                                    - val.states[n + 1]) / 0.01).pow(2).mean()) for n in range(nsteps)])
+    extrap = val_loss(np.zeros_like(params))      # y = 0: the extrapolated first iterate
     trained = val_loss(params)
-    assert trained < 0.1 * zero and trained < 0.3 * extrap, (trained, zero, extrap)
-    ev = learned.evaluate(params, 200, nsteps, nx=nx, ny=ny, nz=nz)
+    assert trained < 0.2 * extrap, (trained, extrap)
+    ev = learned.evaluate(params, 200, nsteps, nx=nx, ny=ny, nz=nz,
+                          modes=("plain", "learned", "extrapolate"))
     assert ev["learned"]["picard_total"] < ev["plain"]["picard_total"], ev
-    # both runs converge every step to tol_picard = 1e-6 from different first
+    assert ev["learned"]["picard_total"] <= ev["extrapolate"]["picard_total"], ev
+    # the runs converge every step to tol_picard = 1e-6 from different first
     # iterates; their states differ by the Picard stopping error only
     assert ev["max_abs_h_diff_m"] <= 2e-5, ev

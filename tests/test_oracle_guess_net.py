@@ -85,14 +85,17 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - g[e]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (e, fd, g[e])
 
 
-def test_untrained_output_layer_gives_h_n():
+def test_untrained_output_layer_gives_the_extrapolation():
+    """y = 0: h^n + (h^n - h^{n-1}), which is h^n when the two states agree."""
     rng = np.random.default_rng(4)
     shape = (2, 2, 3)
     p = G.init_params(seed=1, scale_out=0.0)
     wo, bo = G.OFFSETS[3]
     p[bo] = 0.0
     hn = rng.uniform(-2, -1, 12)
+    hp = hn - rng.normal(0, 0.01, 12)
     assert np.array_equal(G.predict(p, hn, hn, None, 0.0, shape), hn)
+    assert np.array_equal(G.predict(p, hn, hp, None, 0.0, shape), hn + (hn - hp))
 
 
 @pytest.mark.parametrize("x,want", [(1.0, 1.0), (1.00390625, 1.0), (1.01171875, 1.015625),
