@@ -1243,6 +1243,16 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
                 lu[u] = a.layer ? a.layer[i] : 0;
                 if (TRACK) ho[u] = a.hn[i];
             }
+            // both columns' theta~ before the per-column branches, so that the
+            // two evaluations interleave (branch-free for van Genuchten-Mualem)
+            double thu[G2];
+            if (so.model == RF_VGM) {
+#pragma unroll
+                for (int u = 0; u < G2; u++) thu[u] = soil_theta_vgm_flat(hu[u], sL[lu[u]]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < G2; u++) thu[u] = soil_theta(so.model, hu[u], sL[lu[u]]);
+            }
 #pragma unroll
             for (int u = 0; u < G2; u++) {
                 if (!cs[u].act) continue;
@@ -1252,7 +1262,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
                                      lane == cs[u].kt - 1};
                 if (TRACK) a.dh[i] = hu[u] - ho[u];
                 a.hn[i] = hu[u];
-                const double th = soil_theta(so.model, hu[u], sL[lu[u]]);
+                const double th = thu[u];
                 a.thn[i] = th;
                 v[0] += g.V * th;
 #pragma unroll

@@ -74,6 +74,16 @@ __device__ __forceinline__ void soil_eval_vgm_flat(double h, const Layer &L, dou
     K = sat ? ks : ks * sqSe * w * w;
 }
 
+// theta~ of van Genuchten-Mualem without a branch on the sign of h (the
+// arithmetic of soil_theta for unsaturated cells).
+__device__ __forceinline__ double soil_theta_vgm_flat(double h, const Layer &L)
+{
+    const bool sat = h >= 0.0;
+    const double lu = L.n * log(-L.a * (sat ? -1.0 : h));
+    const double th = L.tr + (L.ts - L.tr) * exp(-L.m * log1p(exp(lu)));
+    return sat ? L.ts + L.S * h : th;
+}
+
 __device__ __forceinline__ double soil_theta(int model, double h, const Layer &L)
 {
     if (h >= 0.0) return L.ts + L.S * h;
