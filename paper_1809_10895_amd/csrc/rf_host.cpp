@@ -126,13 +126,18 @@ static void timed_begin(rf_ctx *c, int kernel, int m, int j, EvPair &p)
     p.kernel = kernel;
     p.m = m;
     p.j = j;
-    (void)hipEventRecord(p.a, c->stream);
+    arm_launch_events(p.a, p.b);
 }
 
+// The launcher's kernel took the events; should none have (no launch), both
+// are recorded here, an empty interval.
 static void timed_end(rf_ctx *c, EvPair &p)
 {
     if (p.kernel < 0) return;
-    (void)hipEventRecord(p.b, c->stream);
+    if (disarm_launch_events()) {
+        (void)hipEventRecord(p.a, c->stream);
+        (void)hipEventRecord(p.b, c->stream);
+    }
     c->pending.push_back(p);
 }
 
@@ -190,9 +195,12 @@ static void timed_drop(rf_ctx *c)
         EvPair ev_;                                                     \
         timed_begin(ctx, kid, m, j, ev_);                               \
         hipError_t e_ = (call);                                         \
-        if (e_ != hipSuccess)                                           \
+        if (e_ != hipSuccess) {                                         \
+            disarm_launch_events();                                     \
+            if (ev_.kernel >= 0) ctx->freelist.push_back(ev_);          \
             return fail(ctx, RF_ERR_HIP, "launch %s: %s", kKernelNames[kid], \
                         hipGetErrorString(e_));                         \
+        }                                                               \
         timed_end(ctx, ev_);                                            \
     } while (0)
 

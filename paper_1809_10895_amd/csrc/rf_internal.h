@@ -113,6 +113,14 @@ struct Arrays {
 enum KernelId { K_COEFF = 0, K_RESID, K_SPMV, K_UPDATE, K_APPLYH, K_ACCEPT, K_DECIDE, K_BEGIN };
 
 // Launchers (rf_kernels.hip).  All enqueue on `s` and return the launch status.
+//
+// Timing: after arm_launch_events(a, b) the next kernel that a launcher
+// enqueues on this thread carries the two events in its own dispatch, so a
+// records when that kernel starts and b when it ends (the fold kernel a
+// launcher may add after it is not included).  disarm_launch_events()
+// clears them and says whether they were still unused.
+void arm_launch_events(hipEvent_t start, hipEvent_t stop);
+bool disarm_launch_events();
 hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStream_t s);
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s);
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,

@@ -20,6 +20,7 @@
 // single ticket counter would serialise every block of the grid.  Scalars
 // such as alpha and beta never leave the device during the PCG loop.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include <type_traits>
@@ -1412,9 +1413,35 @@ __global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk)
 // launchers
 // ---------------------------------------------------------------------------
 
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+}
+
+void arm_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool disarm_launch_events()
+{
+    const bool unused = t_ev_start != nullptr;
+    t_ev_start = t_ev_stop = nullptr;
+    return unused;
+}
+
+// A launch that takes armed events passes them to the extension launch, which
+// stamps them with the kernel's own start and end.
 #define RF_LAUNCH_N(nb, kern, ...)                                                      \
     do {                                                                                \
-        hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, __VA_ARGS__);          \
+        if (t_ev_start) {                                                               \
+            hipEvent_t a_ = t_ev_start, b_ = t_ev_stop;                                 \
+            t_ev_start = t_ev_stop = nullptr;                                           \
+            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, a_, b_, 0u,     \
+                                  __VA_ARGS__);                                         \
+        } else {                                                                        \
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, __VA_ARGS__);      \
+        }                                                                               \
         return hipGetLastError();                                                       \
     } while (0)
 // reducing kernels (partials combined later) and wide kernels
@@ -1429,8 +1456,7 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
 
 #define RF_LAUNCH_FOLD(P, nv, mask, kern, ...)                                          \
     do {                                                                                \
-        hipLaunchKernelGGL(kern, dim3(g.nblk), dim3(kThreads), 0, s, __VA_ARGS__);      \
-        const hipError_t e_ = hipGetLastError();                                        \
+        const hipError_t e_ = [&]() { RF_LAUNCH_N(g.nblk, kern, __VA_ARGS__); }();        \
         if (e_ != hipSuccess) return e_;                                                \
         return launch_fold(g, P, nv, mask, s);                                          \
     } while (0)
