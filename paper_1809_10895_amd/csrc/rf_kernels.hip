@@ -439,12 +439,14 @@ __device__ __forceinline__ void coeff_terms(const FaceTab *sBT, const double *sK
     }
 }
 
-// The soil model is a template parameter.  Short columns: two columns per
-// wave at a time, all loads of the pair issued first, then two independent
-// soil evaluations per lane (branch-free for van Genuchten-Mualem), which
-// the compiler interleaves.
+// The soil model is a template parameter.  Short columns: one column per
+// wave at a time, its loads issued together, a branch-free soil evaluation
+// for van Genuchten-Mualem.  At most 128 VGPRs (four waves per SIMD): two
+// 512-thread blocks per CU, so a grid of two blocks per CU runs in one
+// round.  Two interleaved columns per wave took 150 VGPRs, one block per CU
+// and two rounds.
 template <int MODEL>
-__global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
+__global__ void __launch_bounds__(kThreads, 4) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
                                                     double chord_eps, int variant)
 {
     Scalars *s = a.sc;
@@ -462,7 +464,7 @@ __global__ void __launch_bounds__(kThreads) k_coeff(Geo g, Soil so, Arrays a, in
     if (g.nz <= kWave) {
         // G columns at a time: every load of the group first, then G
         // independent soil evaluations per lane
-        constexpr int G = 2;
+        constexpr int G = 1;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G) {
             ColSlot cs[G];
             int lay[G];
@@ -1037,7 +1039,8 @@ struct UpdGroup {
 // partials of (r.z, max|r/diag|).  p is the direction the spmv kernel of the
 // same parity wrote.  Short columns: the loads of a wave's first group of
 // columns are issued before the partials are combined, so the two are in
-// flight together.
+// flight together, and each further group is loaded while the one before
+// it is computed.
 template <int PRECOND, typename T>
 __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
 {
@@ -1052,15 +1055,15 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
     double alpha_d;
     if (g.nz <= kWave) {
         constexpr int G = 2;
-        UpdGroup<PRECOND, T, G> gr;
-        gr.load(g, a, cv, p, cb + w, ce, lane);
+        constexpr int step = kWavesPerBlock * G;
+        UpdGroup<PRECOND, T, G> ga, gb;
+        ga.load(g, a, cv, p, cb + w, ce, lane);
         if (!update_alpha(g, a, s, j, alpha_d)) return;
         const T alpha = (T)alpha_d;
         T *__restrict__ ev = cv.e;
         T *__restrict__ rv = cv.r;
         T *__restrict__ zv = cv.z;
-        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G) {
-            if (c0 != cb + w) gr.load(g, a, cv, p, c0, ce, lane);
+        auto work = [&](const UpdGroup<PRECOND, T, G> &gr) {
 #pragma unroll
             for (int u = 0; u < G; u++) {
                 const bool act = gr.cs[u].act;
@@ -1081,6 +1084,16 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                     }
                 }
             }
+        };
+        // two groups in turn: the next group's loads are in flight while
+        // the current one is computed
+        for (int c0 = cb + w; c0 < ce; c0 += 2 * step) {
+            const bool more = c0 + step < ce;
+            if (more) gb.load(g, a, cv, p, c0 + step, ce, lane);
+            work(ga);
+            if (!more) break;
+            if (c0 + 2 * step < ce) ga.load(g, a, cv, p, c0 + 2 * step, ce, lane);
+            work(gb);
         }
         block_partial<2, 2u>(v, a.pr);
         return;
@@ -1212,7 +1225,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
 // Block partials (ps): [0] storage sum V theta~(h); [1+f] inflow rate through
 // face f with h = h^{m+1} and K = K(h^m) (the converged system).
 template <bool TRACK>
-__global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
+__global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a)
 {
     Scalars *s = a.sc;
     if (s->fail || s->stall || !s->picard_done) return;
@@ -1228,7 +1241,7 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
     RF_WAVE_IDS;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (g.nz <= kWave) {
-        constexpr int G2 = 2;
+        constexpr int G2 = 1;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
             ColSlot cs[G2];
             double hu[G2], Ku[G2], ksu[G2], ho[G2];
@@ -1244,8 +1257,9 @@ __global__ void __launch_bounds__(kThreads) k_accept(Geo g, Soil so, Arrays a)
                 lu[u] = a.layer ? a.layer[i] : 0;
                 if (TRACK) ho[u] = a.hn[i];
             }
-            // both columns' theta~ before the per-column branches, so that the
-            // two evaluations interleave (branch-free for van Genuchten-Mualem)
+            // theta~ of the group before the per-column branches (branch-free
+            // for van Genuchten-Mualem); one column at a time, as in k_coeff,
+            // keeps the kernel within 128 VGPRs
             double thu[G2];
             if (so.model == RF_VGM) {
 #pragma unroll
