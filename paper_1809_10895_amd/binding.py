@@ -24,6 +24,7 @@ RF_PREC_FP64, RF_PREC_MIXED = 0, 1
 RF_PICARD_CHORD, RF_PICARD_MODIFIED = 0, 1
 RF_FIRST_PREVIOUS, RF_FIRST_EXTRAPOLATE = 0, 1
 RF_REFACTOR_EVERY, RF_REFACTOR_STEP = 0, 1
+RF_WAIT_SPIN, RF_WAIT_BLOCK = 0, 1
 RF_MAX_PICARD_LOG = 128
 RF_NKERNELS = 8
 
@@ -57,7 +58,8 @@ class RfOptions(C.Structure):
                 ("dt_min", C.c_double), ("ebats", C.c_int), ("inc_after", C.c_int),
                 ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double),
                 ("cols_per_wave", C.c_int), ("precision", C.c_int), ("cg_rel_tol", C.c_double),
-                ("picard_variant", C.c_int), ("first_iterate", C.c_int), ("zline_refactor", C.c_int)]
+                ("picard_variant", C.c_int), ("first_iterate", C.c_int), ("zline_refactor", C.c_int),
+                ("host_wait", C.c_int)]
 
 
 class RfStepStats(C.Structure):

@@ -348,8 +348,16 @@ static rf_status sync_scalars(rf_ctx *c, int partial_slots = 0)
         rf_status s = copy_partials(c, c->A.ps, partial_slots);
         if (s) return s;
     }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return RF_OK;
+    if (c->opt.host_wait == RF_WAIT_BLOCK) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return RF_OK;
+    }
+    // the stream is polled until its work has completed or failed
+    for (;;) {
+        const hipError_t q = hipStreamQuery(c->stream);
+        if (q == hipSuccess) return RF_OK;
+        if (q != hipErrorNotReady) HIPCHK(c, q);
+    }
 }
 
 // Copies the nv-valued block partials of the last kernel, waits, and
@@ -393,6 +401,7 @@ void rf_default_options(rf_options *o)
     o->picard_variant = RF_PICARD_CHORD;
     o->first_iterate = RF_FIRST_PREVIOUS;
     o->zline_refactor = RF_REFACTOR_EVERY;
+    o->host_wait = RF_WAIT_SPIN;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -578,7 +587,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         !(o->cg_rel_tol >= 0.0 && o->cg_rel_tol < 1.0) ||
         (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED) ||
         (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE) ||
-        (o->zline_refactor != RF_REFACTOR_EVERY && o->zline_refactor != RF_REFACTOR_STEP))
+        (o->zline_refactor != RF_REFACTOR_EVERY && o->zline_refactor != RF_REFACTOR_STEP) ||
+        (o->host_wait != RF_WAIT_SPIN && o->host_wait != RF_WAIT_BLOCK))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {
         // the FP32 arrays exist only in a workspace laid out for them

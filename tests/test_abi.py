@@ -41,6 +41,7 @@ def test_default_options_host_only():
     assert (o["inc_after"], o["few_iters"], o["max_iters"], o["factor"]) == (10, 3, 8, 1.3)
     assert o["precision"] == 0 and o["cg_rel_tol"] == 0.0
     assert (o["picard_variant"], o["first_iterate"], o["zline_refactor"]) == (0, 0, 0)
+    assert o["host_wait"] == 0
 
 
 def test_null_arguments_rejected_without_gpu():

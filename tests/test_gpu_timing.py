@@ -1,7 +1,9 @@
-"""Per-kernel timing (rf_set_timing / rf_get_timing): each launch that did
-work is counted once under its kernel, launches enqueued ahead of need that
-returned at once are counted apart, durations are positive and add up to no
-more than the wall time of the steps, and timing changes no result."""
+"""Host-side step machinery.  Per-kernel timing (rf_set_timing /
+rf_get_timing): each launch that did work is counted once under its kernel,
+launches enqueued ahead of need that returned at once are counted apart,
+durations are positive and add up to no more than the wall time of the
+steps, and timing changes no result.  The host's two ways of waiting for a
+step (polling, blocking) give the same results."""
 import time
 
 import numpy as np
@@ -75,3 +77,17 @@ def test_timing_reset_and_off():
     tm = S.get_timing()
     assert all(v["launches"] == 0 and v["idle_launches"] == 0
                for v in tm.values() if isinstance(v, dict))
+
+
+def test_host_wait_modes_agree():
+    from paper_1809_10895_amd.binding import RF_WAIT_BLOCK, RF_WAIT_SPIN
+    w = small_hillslope()
+    out = []
+    for mode in (RF_WAIT_SPIN, RF_WAIT_BLOCK):
+        S = make_solver(w, precond=1, tol_cg=1e-8, host_wait=mode)
+        for _ in range(3):
+            assert S.step(w.dt)[0] == 0, S.last_error()
+        s, rs = S.run(S.get_state()[1] + 2 * w.dt)
+        assert s == 0, S.last_error()
+        out.append(S.get_state()[0].cpu().numpy())
+    assert np.array_equal(out[0], out[1])
