@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--timing-every", type=int, default=4,
+                    help="time the dominant kernel in every N-th step of the timed region")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy this many MiB with torch before the steps (reference kernel of "
                          "known traffic for hardware-counter runs)")
@@ -172,11 +174,15 @@ def timed_case(args, w, precision):
     tot_all = sum(v["ms"] for v in tm_all.values() if isinstance(v, dict))
     kern = max((k for k in algo_bytes if k in tm_all and tm_all[k]["launches"]),
                key=lambda k: tm_all[k]["ms"], default=None)
-    # timed region: HIP events bracket only the dominant kernel's launches
-    S.set_timing([kern] if (kern and not args.no_timing) else False)
+    # timed region: HIP events time the dominant kernel's launches in every
+    # timing_every-th step (a timed launch costs some overhead of its own)
+    timed = [kern] if (kern and not args.no_timing) else False
+    S.set_timing(timed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        if timed and args.timing_every > 1 and i % args.timing_every in (0, 1):
+            S.select_timing(timed if i % args.timing_every == 0 else False)
         s, st = S.step(w.dt)
         if s != 0:
             raise SystemExit("step failed: " + S.last_error())
@@ -196,6 +202,10 @@ def timed_case(args, w, precision):
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kern, "avg_us": round(avg_s * 1e6, 2),
+                "timed_launches": tm[kern]["launches"],
+                "timed_steps": "every %d%s step of the timed region" % (
+                    args.timing_every, {1: "st", 2: "nd", 3: "rd"}.get(args.timing_every, "th"))
+                if args.timing_every > 1 else "every step of the timed region",
                 "algorithmic_bytes_per_launch": algo}
     # per-kernel breakdown from the warm-up steps (all kernels timed there),
     # with each kernel's algorithmic rate against the same peak

@@ -37,7 +37,7 @@ EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf
            "rf_set_soil", "rf_set_bc", "rf_set_forcing", "rf_set_options", "rf_workspace_bytes",
            "rf_bind_workspace", "rf_set_state", "rf_get_state", "rf_step", "rf_run",
            "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
-           "rf_apply_precond", "rf_set_timing", "rf_get_timing",
+           "rf_apply_precond", "rf_set_timing", "rf_select_timing", "rf_get_timing",
            # include/rf_ensemble.h
            "rf_ens_create", "rf_ens_destroy", "rf_ens_last_error", "rf_ens_setup", "rf_ens_set_bc",
            "rf_ens_set_options", "rf_ens_set_tile", "rf_ens_set_limits", "rf_ens_get_tile",
@@ -143,6 +143,7 @@ def load_library(path: str = LIB):
     L.rf_apply_operator.argtypes = [vp, vp, vp]
     L.rf_apply_precond.argtypes = [vp, vp, vp]
     L.rf_set_timing.argtypes = [vp, ip]
+    L.rf_select_timing.argtypes = [vp, ip]
     L.rf_get_timing.argtypes = [vp, C.POINTER(RfTiming)]
     L.rf_ens_create.argtypes = [C.POINTER(vp), ip, vp]
     L.rf_ens_destroy.argtypes = [vp]
@@ -349,17 +350,21 @@ class Solver:
     # --- measurement --------------------------------------------------------
     KERNELS = ("coeff", "resid", "spmv", "update", "apply_h", "accept", "decide", "begin")
 
+    def _timing_mask(self, kernels):
+        if kernels is True:
+            return 0xff
+        mask = 0
+        for k in (kernels or ()):
+            mask |= 1 << self.KERNELS.index(k)
+        return mask
+
     def set_timing(self, kernels=True):
         """kernels: True (all), False/None (off) or an iterable of kernel names."""
-        if kernels is True:
-            mask = 0xff
-        elif not kernels:
-            mask = 0
-        else:
-            mask = 0
-            for k in kernels:
-                mask |= 1 << self.KERNELS.index(k)
-        self._check(self.L.rf_set_timing(self.h, mask))
+        self._check(self.L.rf_set_timing(self.h, self._timing_mask(kernels)))
+
+    def select_timing(self, kernels=True):
+        """Like set_timing, from the next launch on, keeping the counters."""
+        self._check(self.L.rf_select_timing(self.h, self._timing_mask(kernels)))
 
     def get_timing(self) -> dict:
         tm = RfTiming()

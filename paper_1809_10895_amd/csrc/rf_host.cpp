@@ -147,7 +147,7 @@ static void timed_end(rf_ctx *c, EvPair &p)
 // iterations of iteration m; napply[m] / naccept: launches of the kind.
 static void timed_collect(rf_ctx *c, int last_m, const int *cg, const int *napply, int naccept)
 {
-    if (!c->timing) return;
+    if (c->pending.empty()) return;
     std::vector<int> seen_apply(RF_MAX_PICARD_LOG, 0);
     int seen_accept = 0;
     for (auto &p : c->pending) {
@@ -748,6 +748,7 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     memset(st, 0, sizeof(*st));
     st->dt = dt;
     st->t = c->t;
+    timed_drop(c);   // events of a step that ended in an error
     const Geo &G = c->G;
     Arrays &A = c->A;
     const Bc bc = bc_at(c, c->t);
@@ -974,6 +975,13 @@ rf_status rf_set_timing(rf_ctx *c, int mask)
     memset(&c->tm, 0, sizeof(c->tm));
     for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
     c->tm.cells = cells;
+    return RF_OK;
+}
+
+rf_status rf_select_timing(rf_ctx *c, int mask)
+{
+    if (!c) return RF_ERR_ARG;
+    c->timing = mask & 0xff;
     return RF_OK;
 }
 

@@ -91,3 +91,20 @@ def test_host_wait_modes_agree():
         assert s == 0, S.last_error()
         out.append(S.get_state()[0].cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+def test_select_timing_keeps_counters_and_times_a_sample():
+    w = small_hillslope()
+    S = make_solver(w, precond=1, tol_cg=1e-8)
+    assert S.step(w.dt)[0] == 0
+    S.set_timing(["update"])
+    cg_timed = 0
+    for i in range(6):
+        S.select_timing(["update"] if i % 3 == 0 else False)
+        s, st = S.step(w.dt)
+        assert s == 0, S.last_error()
+        if i % 3 == 0:
+            cg_timed += st["cg_iters_total"]
+    tm = S.get_timing()
+    assert tm["update"]["launches"] == cg_timed and tm["update"]["ms"] > 0.0
+    assert tm["spmv"]["launches"] == 0
