@@ -9,7 +9,7 @@ cell-steps/s, the roofline of the dominant kernel (HIP events on the library
 stream, inside the timed region; also against device copies measured on the
 same box, outside it) and the CPU oracle timed on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps 144] [--warmup 5] [--workload hillslope]
+    python bench.py [--gpus 1] [--steps 144] [--warmup 64] [--workload hillslope]
                     [--precision fp64|mixed]
 
 The headline line is FP64 (the paper's arithmetic); the same steps are then
@@ -57,7 +57,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=144)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--workload", default="hillslope", choices=["hillslope", "watershed", "column100"])
     ap.add_argument("--precond", default="zline", choices=["zline", "jacobi"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the dominant kernel in every N-th step of the timed region")
+    ap.add_argument("--driver", choices=("run", "step"), default="run",
+                    help="timed steps through rf_run (default) or one rf_step call per step")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy this many MiB with torch before the steps (reference kernel of "
                          "known traffic for hardware-counter runs)")
@@ -153,41 +155,70 @@ def timed_case(args, w, precision):
     import torch
     from paper_1809_10895_amd import Solver, workloads as W
     pc = 1 if args.precond == "zline" else 0
-    S = Solver(0)
-    S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
-    W.configure(w, S)
-    S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt, ebats=0,
-                  cols_per_wave=args.cols_per_wave, precision=PRECISION[precision],
-                  cg_rel_tol=args.cg_rel_tol)
-    S.bind()
     h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
-    assert S.set_state(h0) == 0, S.last_error()
-    algo_bytes = ALGO_BYTES[precision]
 
+    def solver():
+        S = Solver(0)
+        S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
+        W.configure(w, S)
+        S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt,
+                      ebats=0, cols_per_wave=args.cols_per_wave,
+                      precision=PRECISION[precision], cg_rel_tol=args.cg_rel_tol)
+        S.bind()
+        assert S.set_state(h0) == 0, S.last_error()
+        return S
+
+    algo_bytes = ALGO_BYTES[precision]
     picard = cg = 0
-    # warm-up steps, timing every kernel to find the dominant one
+    # warm-up on a context of its own, so that the timed steps are the
+    # workload's first ones: the first steps (at most five) time every kernel
+    # to find the dominant one; the rest go through the timed driver untimed
+    # (the HIP runtime sets up, once per process, what a long queue of work
+    # needs: the first few dozen steps run ahead cost about 6 ms more)
+    S = solver()
+    n_all = min(5, args.warmup)
     S.set_timing(True)
-    for _ in range(args.warmup):
+    for _ in range(n_all):
         s, st = S.step(w.dt)
         assert s == 0, S.last_error()
     tm_all = S.get_timing()
+    S.set_timing(False)
+    rest = args.warmup - n_all
+    if rest and args.driver == "run":
+        s, rs = S.run(S.get_state()[1] + rest * w.dt)
+        assert s == 0 and rs["accepted"] == rest, S.last_error()
+    else:
+        for _ in range(rest):
+            s, st = S.step(w.dt)
+            assert s == 0, S.last_error()
     tot_all = sum(v["ms"] for v in tm_all.values() if isinstance(v, dict))
     kern = max((k for k in algo_bytes if k in tm_all and tm_all[k]["launches"]),
                key=lambda k: tm_all[k]["ms"], default=None)
+    S.close() if hasattr(S, "close") else None
+    del S
+    S = solver()
     # timed region: HIP events time the dominant kernel's launches in every
     # timing_every-th step (a timed launch costs some overhead of its own)
     timed = [kern] if (kern and not args.no_timing) else False
     S.set_timing(timed)
+    S.select_timing(timed, every=max(1, args.timing_every))
+    t_start = S.get_state()[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        if timed and args.timing_every > 1 and i % args.timing_every in (0, 1):
-            S.select_timing(timed if i % args.timing_every == 0 else False)
-        s, st = S.step(w.dt)
-        if s != 0:
-            raise SystemExit("step failed: " + S.last_error())
-        picard += st["picard_iters"]
-        cg += st["cg_iters_total"]
+    if args.driver == "run":
+        # the library's time loop: fixed steps, each enqueued before the one
+        # ahead of it is waited for
+        s, rs = S.run(t_start + args.steps * w.dt)
+        if s != 0 or rs["accepted"] != args.steps:
+            raise SystemExit("run failed: %s %s" % (rs, S.last_error()))
+        picard, cg = rs["picard_total"], rs["cg_total"]
+    else:
+        for i in range(args.steps):
+            s, st = S.step(w.dt)
+            if s != 0:
+                raise SystemExit("step failed: " + S.last_error())
+            picard += st["picard_iters"]
+            cg += st["cg_iters_total"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     tm = S.get_timing()
@@ -360,6 +391,7 @@ def main():
                    "dt_s": w.dt, "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
                    "cg_rel_tol": args.cg_rel_tol, "precision": args.precision,
                    "precond": args.precond, "cols_per_wave": args.cols_per_wave,
+                   "driver": "rf_run" if args.driver == "run" else "rf_step per step",
                    "picard_per_step": main_r["picard_per_step"],
                    "cg_per_picard": main_r["cg_per_picard"],
                    "wall_s_per_simulated_day": main_r["wall_s_per_simulated_day"]},

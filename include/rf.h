@@ -279,10 +279,12 @@ typedef struct {
  * step when one kernel of the 1 M-cell hillslope is timed).  Waits for the
  * stream and resets the counters. */
 rf_status rf_set_timing(rf_ctx *ctx, int mask);
-/* Changes which kernels are timed from the next launch on (mask as in
- * rf_set_timing), keeping the counters gathered so far; does not wait.  Lets
- * a caller time a sample of the steps (say every fourth) of a longer run. */
-rf_status rf_select_timing(rf_ctx *ctx, int mask);
+/* Changes which kernels are timed (mask as in rf_set_timing) and in which
+ * steps: the first step planned from now on and every `every`-th one after
+ * it (every >= 1; 1 = every step), keeping the counters gathered so far;
+ * does not wait.  Lets a caller time a sample of the steps of a long run.
+ * RF_ERR_ARG when every < 1. */
+rf_status rf_select_timing(rf_ctx *ctx, int mask, int every);
 rf_status rf_get_timing(rf_ctx *ctx, rf_timing *out);
 
 #ifdef __cplusplus

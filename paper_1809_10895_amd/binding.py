@@ -143,7 +143,7 @@ def load_library(path: str = LIB):
     L.rf_apply_operator.argtypes = [vp, vp, vp]
     L.rf_apply_precond.argtypes = [vp, vp, vp]
     L.rf_set_timing.argtypes = [vp, ip]
-    L.rf_select_timing.argtypes = [vp, ip]
+    L.rf_select_timing.argtypes = [vp, ip, ip]
     L.rf_get_timing.argtypes = [vp, C.POINTER(RfTiming)]
     L.rf_ens_create.argtypes = [C.POINTER(vp), ip, vp]
     L.rf_ens_destroy.argtypes = [vp]
@@ -362,9 +362,10 @@ class Solver:
         """kernels: True (all), False/None (off) or an iterable of kernel names."""
         self._check(self.L.rf_set_timing(self.h, self._timing_mask(kernels)))
 
-    def select_timing(self, kernels=True):
-        """Like set_timing, from the next launch on, keeping the counters."""
-        self._check(self.L.rf_select_timing(self.h, self._timing_mask(kernels)))
+    def select_timing(self, kernels=True, every=1):
+        """Like set_timing, in the next step planned and every `every`-th one
+        after it, keeping the counters."""
+        self._check(self.L.rf_select_timing(self.h, self._timing_mask(kernels), int(every)))
 
     def get_timing(self) -> dict:
         tm = RfTiming()

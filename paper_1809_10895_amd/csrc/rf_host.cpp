@@ -29,8 +29,27 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct EvPair {
     hipEvent_t a, b;
     int kernel;
+    int serial; // step of the launch
     int m;      // Picard iteration of the launch (-1: none)
     int j;      // PCG iteration of an spmv/update launch, launch count of apply_h/accept
+};
+
+// One step as the host enqueued it: where it starts, what its first kernel
+// needs, how much Picard and PCG work went in, and where its scalars and
+// acceptance partials are read back.
+struct StepRec {
+    int serial = 0;             // tag the acceptance kernel leaves on the device
+    int slot = 0;               // readback slot (pinned host mirrors and event)
+    int timing = 0;             // kernels timed in this step
+    double t = 0.0, dt = 0.0;   // start time and time step
+    double ratio = 0.0;         // first iterate h^n + ratio (h^n - h^{n-1})
+    const double *guess = nullptr;
+    int max_picard = 1;
+    int M = 0;                  // Picard iterations enqueued
+    int naccept = 0;            // acceptance launches enqueued
+    rf::Bc bc{};
+    int pairs_enq[RF_MAX_PICARD_LOG];   // PCG iterations enqueued per Picard iteration
+    int apply_enq[RF_MAX_PICARD_LOG];   // Picard-update launches per Picard iteration
 };
 
 }  // namespace
@@ -72,14 +91,17 @@ struct rf_ctx {
     double storage0 = 0.0, storage = 0.0, inflow[6] = {0, 0, 0, 0, 0, 0};
     int pred_picard = 3;                   // Picard iterations enqueued up front
     int pred_cg[RF_MAX_PICARD_LOG];        // PCG iterations enqueued per Picard iteration
-    int pairs_enq[RF_MAX_PICARD_LOG];      // PCG iterations enqueued in this step
-    int apply_enq[RF_MAX_PICARD_LOG];      // Picard-update launches in this step
+    int serial = 0;                        // last step serial handed out
+    StepRec rec[2];                        // steps in flight (two when rf_run runs ahead)
 
-    Scalars *hsc = nullptr;   // pinned host mirror of the device scalars
-    double *hpart = nullptr;  // pinned host copy of block partials
+    Scalars *hsc = nullptr;   // pinned host mirrors of the device scalars, one per slot
+    double *hpart = nullptr;  // pinned host copies of block partials, one area per slot
+    hipEvent_t done_ev[2] = {nullptr, nullptr};   // recorded after each slot's readback
     bool assembled = false;
 
-    int timing = 0;           // bit k: bracket kernel k with events
+    int timing = 0;           // bit k: time kernel k
+    int timing_every = 1;     // in every timing_every-th step
+    long timing_count = 0;    // steps planned since the selection
     std::vector<EvPair> pending;
     std::vector<EvPair> freelist;
     rf_timing tm{};
@@ -108,10 +130,10 @@ static rf_status fail(rf_ctx *c, rf_status s, const char *fmt, ...)
 // timing helpers
 // ---------------------------------------------------------------------------
 
-static void timed_begin(rf_ctx *c, int kernel, int m, int j, EvPair &p)
+static void timed_begin(rf_ctx *c, const StepRec &r, int kernel, int m, int j, EvPair &p)
 {
     p.kernel = -1;
-    if (!((c->timing >> kernel) & 1)) return;
+    if (!((r.timing >> kernel) & 1)) return;
     if (c->freelist.empty()) {
         // timing-only events: no system-scope fence (no L2 writeback and
         // invalidate) at each record, so they do not slow the kernels they
@@ -124,6 +146,7 @@ static void timed_begin(rf_ctx *c, int kernel, int m, int j, EvPair &p)
     p = c->freelist.back();
     c->freelist.pop_back();
     p.kernel = kernel;
+    p.serial = r.serial;
     p.m = m;
     p.j = j;
     arm_launch_events(p.a, p.b);
@@ -141,16 +164,23 @@ static void timed_end(rf_ctx *c, EvPair &p)
     c->pending.push_back(p);
 }
 
-// After a step: a launch did work iff the device logs say so (kernels
+// After step `serial`: a launch did work iff the device logs say so (kernels
 // enqueued speculatively past the end of a PCG solve or of the Picard loop
 // return at once).  last_m: last Picard iteration that ran; cg[m]: PCG
 // iterations of iteration m; napply[m] / naccept: launches of the kind.
-static void timed_collect(rf_ctx *c, int last_m, const int *cg, const int *napply, int naccept)
+// Events of other steps stay pending.
+static void timed_collect(rf_ctx *c, int serial, int last_m, const int *cg, const int *napply,
+                          int naccept)
 {
     if (c->pending.empty()) return;
     std::vector<int> seen_apply(RF_MAX_PICARD_LOG, 0);
     int seen_accept = 0;
+    std::vector<EvPair> other;
     for (auto &p : c->pending) {
+        if (p.serial != serial) {
+            other.push_back(p);
+            continue;
+        }
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, p.a, p.b);
         bool work = true;
@@ -181,19 +211,24 @@ static void timed_collect(rf_ctx *c, int last_m, const int *cg, const int *nappl
         }
         c->freelist.push_back(p);
     }
-    c->pending.clear();
+    c->pending.swap(other);
 }
 
-static void timed_drop(rf_ctx *c)
+// Returns the events of one step (serial >= 0) or of every step to the pool.
+static void timed_drop(rf_ctx *c, int serial = -1)
 {
-    for (auto &p : c->pending) c->freelist.push_back(p);
-    c->pending.clear();
+    std::vector<EvPair> other;
+    for (auto &p : c->pending) {
+        if (serial < 0 || p.serial == serial) c->freelist.push_back(p);
+        else other.push_back(p);
+    }
+    c->pending.swap(other);
 }
 
-#define TIMED(ctx, kid, m, j, call)                                     \
+#define TIMED(ctx, rec, kid, m, j, call)                                \
     do {                                                                \
         EvPair ev_;                                                     \
-        timed_begin(ctx, kid, m, j, ev_);                               \
+        timed_begin(ctx, rec, kid, m, j, ev_);                          \
         hipError_t e_ = (call);                                         \
         if (e_ != hipSuccess) {                                         \
             disarm_launch_events();                                     \
@@ -315,46 +350,56 @@ static double next_forcing_change(const rf_ctx *c, double t)
     return tn;
 }
 
+constexpr size_t kSlotPartials = (size_t)kPartialsMax * kRedSlots;
+
 // Enqueues the copy of the nv-valued block partials of the last kernel into
-// the pinned host buffer (combine_partials reads them after a sync).
-static rf_status copy_partials(rf_ctx *c, const double *dev, int nv)
+// readback slot `slot` (combine_partials reads them after a wait).
+static rf_status copy_partials(rf_ctx *c, const double *dev, int nv, int slot = 0)
 {
-    HIPCHK(c, hipMemcpyAsync(c->hpart, dev + (size_t)c->G.foff * nv,
+    HIPCHK(c, hipMemcpyAsync(c->hpart + slot * kSlotPartials, dev + (size_t)c->G.foff * nv,
                              (size_t)c->G.np * nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     return RF_OK;
 }
 
 // Combines copied partials on the host in block order (sum, or max where
 // bit i of maxmask is set).
-static void combine_partials(const rf_ctx *c, int nv, unsigned maxmask, double *tot)
+static void combine_partials(const rf_ctx *c, int nv, unsigned maxmask, double *tot, int slot = 0)
 {
+    const double *hp = c->hpart + slot * kSlotPartials;
     for (int i = 0; i < nv; i++) tot[i] = 0.0;
     for (int b = 0; b < c->G.np; b++)
         for (int i = 0; i < nv; i++) {
-            const double x = c->hpart[(size_t)b * nv + i];
+            const double x = hp[(size_t)b * nv + i];
             tot[i] = ((maxmask >> i) & 1u) ? std::max(tot[i], x) : tot[i] + x;
         }
 }
 
-// Reads the step's scalars back and waits.  With kAcceptSlots, also the
-// acceptance kernel's partials (storage, face inflows), in the same wait:
-// they are only used when the scalars say the step was accepted, and then
-// the acceptance kernel was the last one to write them.
+// A step's readback: the device scalars and the acceptance kernel's
+// partials (storage, face inflows) into the step's slot, then the slot's
+// event.  The partials are only used when the scalars say the step was
+// accepted, and then the acceptance kernel was the last one to write them.
 constexpr int kAcceptSlots = 7;
-static rf_status sync_scalars(rf_ctx *c, int partial_slots = 0)
+static rf_status enqueue_readback(rf_ctx *c, const StepRec &r)
 {
-    HIPCHK(c, hipMemcpyAsync(c->hsc, c->A.sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
-    if (partial_slots) {
-        rf_status s = copy_partials(c, c->A.ps, partial_slots);
-        if (s) return s;
-    }
+    HIPCHK(c, hipMemcpyAsync(c->hsc + r.slot, c->A.sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                             c->stream));
+    rf_status s = copy_partials(c, c->A.ps, kAcceptSlots, r.slot);
+    if (s) return s;
+    HIPCHK(c, hipEventRecord(c->done_ev[r.slot], c->stream));
+    return RF_OK;
+}
+
+// Waits for the last readback of a slot.  last: nothing is enqueued behind
+// it, so the stream itself can be polled.
+static rf_status wait_readback(rf_ctx *c, int slot, bool last)
+{
     if (c->opt.host_wait == RF_WAIT_BLOCK) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipEventSynchronize(c->done_ev[slot]));
         return RF_OK;
     }
-    // the stream is polled until its work has completed or failed
+    // polled until the work has completed or failed
     for (;;) {
-        const hipError_t q = hipStreamQuery(c->stream);
+        const hipError_t q = last ? hipStreamQuery(c->stream) : hipEventQuery(c->done_ev[slot]);
         if (q == hipSuccess) return RF_OK;
         if (q != hipErrorNotReady) HIPCHK(c, q);
     }
@@ -415,14 +460,18 @@ rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
     rf_default_options(&c->opt);
     c->dt_cur = c->opt.dt0;
     if (hipSetDevice(hip_device) != hipSuccess ||
-        hipHostMalloc((void **)&c->hsc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->hpart, (size_t)kPartialsMax * kRedSlots * sizeof(double),
-                      hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->hsc, 2 * sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->hpart, 2 * kSlotPartials * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->done_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->done_ev[1], hipEventDisableTiming) != hipSuccess) {
         if (c->hsc) (void)hipHostFree(c->hsc);
+        if (c->hpart) (void)hipHostFree(c->hpart);
+        if (c->done_ev[0]) (void)hipEventDestroy(c->done_ev[0]);
         delete c;
         return RF_ERR_HIP;
     }
-    memset(c->hsc, 0, sizeof(Scalars));
+    memset(c->hsc, 0, 2 * sizeof(Scalars));
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess)
         c->n_cu = 0;
     c->tm.cells = 0;
@@ -440,6 +489,8 @@ void rf_destroy(rf_ctx *c)
     for (auto &p : c->freelist) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hpart) (void)hipHostFree(c->hpart);
+    for (hipEvent_t ev : c->done_ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete c;
 }
 
@@ -684,25 +735,25 @@ static bool mixed(const rf_ctx *c) { return c->opt.precision == RF_PREC_MIXED; }
 
 static CgTol cg_tol(const rf_ctx *c) { return CgTol{c->opt.tol_cg, c->opt.cg_rel_tol, c->opt.max_cg}; }
 
-// Enqueues n more PCG iterations of Picard iteration m (the direction
-// buffers alternate with the iteration count).
-static rf_status enqueue_pairs(rf_ctx *c, int m, int n)
+// Enqueues n more PCG iterations of Picard iteration m of step r (the
+// direction buffers alternate with the iteration count).
+static rf_status enqueue_pairs(rf_ctx *c, StepRec &r, int m, int n)
 {
     Arrays &A = c->A;
     const int pc = c->opt.precond;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     for (int i = 0; i < n; i++) {
-        const int j = c->pairs_enq[mi]++;
-        TIMED(c, K_SPMV, m, j, launch_spmv(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
-        TIMED(c, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, c->stream));
+        const int j = r.pairs_enq[mi]++;
+        TIMED(c, r, K_SPMV, m, j, launch_spmv(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
+        TIMED(c, r, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, c->stream));
     }
     return RF_OK;
 }
 
-static rf_status enqueue_apply(rf_ctx *c, int m)
+static rf_status enqueue_apply(rf_ctx *c, StepRec &r, int m)
 {
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
-    TIMED(c, K_APPLYH, m, c->apply_enq[mi]++,
+    TIMED(c, r, K_APPLYH, m, r.apply_enq[mi]++,
           launch_apply_h(c->G, c->A, m, mixed(c), cg_tol(c), c->stream));
     return RF_OK;
 }
@@ -710,101 +761,129 @@ static rf_status enqueue_apply(rf_ctx *c, int m)
 // Picard iteration m: exit test of iteration m-1, coefficients, residual,
 // a predicted number of PCG iterations, Picard update.  Every kernel returns
 // at once when an earlier one has ended the step.
-static rf_status enqueue_iteration(rf_ctx *c, const Bc &bc, double dt, int m)
+static rf_status enqueue_iteration(rf_ctx *c, StepRec &r, int m)
 {
     const Geo &G = c->G;
     Arrays &A = c->A;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
-    if (m > 0) TIMED(c, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
-    TIMED(c, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, dt, c->opt.chord_eps,
-                                          c->opt.picard_variant, c->stream));
+    if (m > 0) TIMED(c, r, K_DECIDE, m, -1, launch_decide(G, A, m, c->opt.tol_picard, c->stream));
+    TIMED(c, r, K_COEFF, m, -1, launch_coeff(G, c->S, A, m, r.dt, c->opt.chord_eps,
+                                             c->opt.picard_variant, c->stream));
     const bool refactor = (m == 0) || c->opt.zline_refactor == RF_REFACTOR_EVERY;
-    TIMED(c, K_RESID, m, -1,
+    TIMED(c, r, K_RESID, m, -1,
           launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), refactor, c->stream));
-    rf_status s = enqueue_pairs(c, m, std::max(1, c->pred_cg[mi]));
+    rf_status s = enqueue_pairs(c, r, m, std::max(1, c->pred_cg[mi]));
     if (s) return s;
-    return enqueue_apply(c, m);
+    return enqueue_apply(c, r, m);
 }
 
 static bool extrapolating(const rf_ctx *c) { return c->opt.first_iterate == RF_FIRST_EXTRAPOLATE; }
 
-static rf_status enqueue_accept(rf_ctx *c, const Bc &bc, int M, int &naccept)
+// Exit test of the last enqueued iteration, acceptance, readback.
+static rf_status enqueue_accept(rf_ctx *c, StepRec &r)
 {
-    TIMED(c, K_DECIDE, M, -1, launch_decide(c->G, c->A, M, c->opt.tol_picard, c->stream));
-    TIMED(c, K_ACCEPT, M, naccept,
-          launch_accept(c->G, c->S, c->A, extrapolating(c), c->stream));
-    naccept++;
-    return RF_OK;
+    TIMED(c, r, K_DECIDE, r.M, -1, launch_decide(c->G, c->A, r.M, c->opt.tol_picard, c->stream));
+    TIMED(c, r, K_ACCEPT, r.M, r.naccept,
+          launch_accept(c->G, c->S, c->A, extrapolating(c), r.serial, c->stream));
+    r.naccept++;
+    return enqueue_readback(c, r);
 }
 
-// One backward-Euler step.  The whole Picard loop is enqueued speculatively
-// (as many iterations and PCG iterations as the previous step needed); the
-// device decides, after every update, whether to go on, and the host waits
-// once.  If the guess fell short (a PCG solve not finished, or the Picard
-// test not yet met), the host enqueues more from where the device stopped.
-static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_picard,
-                             rf_step_stats *st)
+// Fills the record of a step from time t with dt.  dt_prev: the step before
+// it, for the extrapolated first iterate (0: none).
+static void plan_step(rf_ctx *c, StepRec &r, int slot, double t, double dt, double dt_prev,
+                      const double *guess, int max_picard)
 {
-    memset(st, 0, sizeof(*st));
-    st->dt = dt;
-    st->t = c->t;
-    timed_drop(c);   // events of a step that ended in an error
-    const Geo &G = c->G;
-    Arrays &A = c->A;
-    const Bc bc = bc_at(c, c->t);
-    for (int m = 0; m < RF_MAX_PICARD_LOG; m++) c->pairs_enq[m] = c->apply_enq[m] = 0;
-    int naccept = 0;
-    // first iterate: the caller's guess, h^n, or h^n + (dt / dt_prev) (h^n - h^{n-1})
-    const double ratio = (!guess && extrapolating(c) && c->dt_prev > 0.0) ? dt / c->dt_prev : 0.0;
-    TIMED(c, K_BEGIN, -1, -1,
-          launch_step_begin(G, c->S, bc, A, guess ? guess : A.hn, ratio, c->stream));
-    int M = std::max(1, std::min(max_picard, c->pred_picard));
-    for (int m = 0; m < M; m++) {
-        rf_status s = enqueue_iteration(c, bc, dt, m);
+    r.serial = ++c->serial;
+    if (r.serial <= 0) r.serial = c->serial = 1;
+    r.slot = slot;
+    r.timing = (c->timing && (c->timing_count++ % c->timing_every) == 0) ? c->timing : 0;
+    r.t = t;
+    r.dt = dt;
+    r.ratio = (!guess && extrapolating(c) && dt_prev > 0.0) ? dt / dt_prev : 0.0;
+    r.guess = guess;
+    r.max_picard = max_picard;
+    r.M = 0;
+    r.naccept = 0;
+    r.bc = bc_at(c, t);
+    for (int m = 0; m < RF_MAX_PICARD_LOG; m++) r.pairs_enq[m] = r.apply_enq[m] = 0;
+}
+
+// Enqueues a whole step speculatively: as many Picard iterations and PCG
+// iterations as the last step needed, acceptance and readback; the device
+// decides, after every update, whether to go on.  gate >= 0: the step only
+// starts if the step with that serial was accepted (enqueued ahead of it).
+static rf_status enqueue_step(rf_ctx *c, StepRec &r, int gate)
+{
+    TIMED(c, r, K_BEGIN, -1, -1,
+          launch_step_begin(c->G, c->S, r.bc, c->A, r.guess ? r.guess : c->A.hn, r.ratio, gate,
+                            c->stream));
+    r.M = std::max(1, std::min(r.max_picard, c->pred_picard));
+    for (int m = 0; m < r.M; m++) {
+        rf_status s = enqueue_iteration(c, r, m);
         if (s) return s;
     }
-    rf_status s = enqueue_accept(c, bc, M, naccept);
-    if (s) return s;
+    return enqueue_accept(c, r);
+}
+
+// Waits for step r and completes it: if the enqueued work fell short (a PCG
+// solve not finished, or the Picard test not yet met) enqueues more from
+// where the device stopped, until the step is accepted, fails or runs out of
+// Picard iterations; then the statistics and the host-side bookkeeping.
+// last: nothing is enqueued behind the step's readback.  first_batch: the
+// step was accepted by the work enqueued up front (a step enqueued behind it
+// with this step's serial as gate has then run).
+static rf_status finish_step(rf_ctx *c, StepRec &r, bool last, rf_step_stats *st, bool *first_batch)
+{
+    memset(st, 0, sizeof(*st));
+    st->dt = r.dt;
+    st->t = r.t;
+    Arrays &A = c->A;
+    *first_batch = true;
     rf_status status = RF_OK;
     for (;;) {
-        s = sync_scalars(c, kAcceptSlots);
+        rf_status s = wait_readback(c, r.slot, last);
         if (s) return s;
-        const Scalars &h = *c->hsc;
+        const Scalars &h = c->hsc[r.slot];
         if (h.accepted) break;
         if (h.fail) {
             status = (h.fail == 3) ? RF_ERR_NONFINITE : RF_ERR_LINEAR;
             break;
         }
-        if (h.stall) {
-            // PCG of iteration ms needs more iterations than were enqueued
-            const int ms = h.stall_m;
-            HIPCHK(c, hipMemsetAsync(&A.sc->stall, 0, sizeof(int), c->stream));
-            s = enqueue_pairs(c, ms, std::max(1, c->opt.check_every / 2));
-            if (s) return s;
-            s = enqueue_apply(c, ms);
-            if (s) return s;
-            for (int m = ms + 1; m < M; m++) {
-                s = enqueue_iteration(c, bc, dt, m);
-                if (s) return s;
-            }
-            s = enqueue_accept(c, bc, M, naccept);
-            if (s) return s;
-            continue;
-        }
-        if (M >= max_picard) {
+        if (!h.stall && r.M >= r.max_picard) {
             status = RF_ERR_NOT_CONVERGED;
             break;
         }
-        const int M2 = std::min(max_picard, M + std::max(1, M / 2));
-        for (int m = M; m < M2; m++) {
-            s = enqueue_iteration(c, bc, dt, m);
+        // more work for this step, behind everything enqueued so far; the
+        // stall flag (raised by this step's PCG, or by a step enqueued behind
+        // this one that found it not accepted) is cleared first
+        *first_batch = false;
+        last = true;
+        HIPCHK(c, hipMemsetAsync(&A.sc->stall, 0, sizeof(int), c->stream));
+        if (h.stall) {
+            // PCG of iteration ms needs more iterations than were enqueued
+            const int ms = h.stall_m;
+            s = enqueue_pairs(c, r, ms, std::max(1, c->opt.check_every / 2));
             if (s) return s;
+            s = enqueue_apply(c, r, ms);
+            if (s) return s;
+            for (int m = ms + 1; m < r.M; m++) {
+                s = enqueue_iteration(c, r, m);
+                if (s) return s;
+            }
+        } else {
+            const int M2 = std::min(r.max_picard, r.M + std::max(1, r.M / 2));
+            for (int m = r.M; m < M2; m++) {
+                s = enqueue_iteration(c, r, m);
+                if (s) return s;
+            }
+            r.M = M2;
         }
-        M = M2;
-        s = enqueue_accept(c, bc, M, naccept);
+        s = enqueue_accept(c, r);
         if (s) return s;
     }
-    const Scalars h = *c->hsc;
+    const Scalars h = c->hsc[r.slot];
+    const int M = r.M;
     const int last_m = h.accepted ? h.accept_m : (status == RF_ERR_NOT_CONVERGED ? M - 1 : h.cur_m);
     st->picard_iters = last_m + 1;
     for (int m = 0; m <= last_m && m < RF_MAX_PICARD_LOG; m++) {
@@ -816,12 +895,12 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     int cgl[RF_MAX_PICARD_LOG], napp[RF_MAX_PICARD_LOG];
     for (int m = 0; m < RF_MAX_PICARD_LOG; m++) {
         cgl[m] = (m <= last_m) ? st->cg_iters[m] : 0;
-        napp[m] = c->apply_enq[m];
+        napp[m] = r.apply_enq[m];
     }
-    timed_collect(c, last_m, cgl, napp, h.accepted ? naccept : -1);
+    timed_collect(c, r.serial, last_m, cgl, napp, h.accepted ? r.naccept : -1);
     if (status != RF_OK) {
         if (status == RF_ERR_NOT_CONVERGED)
-            fail(c, status, "Picard did not converge in %d iterations (dt %g)", max_picard, dt);
+            fail(c, status, "Picard did not converge in %d iterations (dt %g)", r.max_picard, r.dt);
         else
             fail(c, status, "PCG %s in Picard iteration %d after %d iterations",
                  h.fail == 1 ? "breakdown" : h.fail == 2 ? "hit max_cg" : "produced NaN/Inf",
@@ -832,14 +911,26 @@ static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_
     c->pred_picard = last_m + 1;
     for (int m = 0; m <= last_m && m < RF_MAX_PICARD_LOG; m++) c->pred_cg[m] = std::max(1, st->cg_iters[m]);
     double sums[kAcceptSlots];
-    combine_partials(c, kAcceptSlots, 0u, sums);   // copied with the last scalars
+    combine_partials(c, kAcceptSlots, 0u, sums, r.slot);   // read back with the scalars
     c->storage = sums[0];
-    for (int f = 0; f < 6; f++) c->inflow[f] += dt * sums[1 + f];
-    c->t += dt;
-    c->dt_prev = extrapolating(c) ? dt : 0.0;
+    for (int f = 0; f < 6; f++) c->inflow[f] += r.dt * sums[1 + f];
+    c->t = r.t + r.dt;
+    c->dt_prev = extrapolating(c) ? r.dt : 0.0;
     st->converged = 1;
     st->t = c->t;
     return RF_OK;
+}
+
+// One backward-Euler step from c->t, enqueued and completed on its own.
+static rf_status picard_step(rf_ctx *c, double dt, const double *guess, int max_picard,
+                             rf_step_stats *st)
+{
+    StepRec &r = c->rec[0];
+    plan_step(c, r, 0, c->t, dt, c->dt_prev, guess, max_picard);
+    rf_status s = enqueue_step(c, r, -1);
+    if (s) return s;
+    bool first = true;
+    return finish_step(c, r, true, st, &first);
 }
 
 rf_status rf_step(rf_ctx *c, double dt, const double *h_guess_dev, rf_step_stats *out)
@@ -847,10 +938,113 @@ rf_status rf_step(rf_ctx *c, double dt, const double *h_guess_dev, rf_step_stats
     if (!c) return RF_ERR_ARG;
     if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_step before rf_set_state");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(c, RF_ERR_ARG, "invalid dt %g", dt);
+    timed_drop(c);   // events of a step that ended in an error
     rf_step_stats st;
     rf_status s = picard_step(c, dt, h_guess_dev, c->opt.max_picard, &st);
     if (out) *out = st;
     return s;
+}
+
+static bool before(double t, double t_end) { return t < t_end * (1.0 - 1e-15) - 1e-12; }
+
+// Step from t: dt0 clipped at the next change of the forcing and at t_end.
+static double fixed_dt(const rf_ctx *c, double t, double t_end, bool *clipped = nullptr)
+{
+    double dt = c->opt.dt0;
+    bool cl = false;
+    const double tf = next_forcing_change(c, t);
+    if (t + dt > tf) { dt = tf - t; cl = true; }
+    if (t + dt > t_end) { dt = t_end - t; cl = true; }
+    if (clipped) *clipped = cl;
+    return dt;
+}
+
+// Fixed steps.  The next step does not depend on how this one went (it is
+// this step's end, with dt0), so it is enqueued before this one is waited
+// for, gated on this step's acceptance: the device goes from one step to the
+// next without waiting for the host.  If this step needed more work than was
+// enqueued up front, the next one found it not accepted, did nothing, and is
+// enqueued again behind that work.
+static rf_status run_fixed(rf_ctx *c, double t_end, rf_run_stats &rs)
+{
+    if (!before(c->t, t_end)) return RF_OK;
+    StepRec *cur = &c->rec[0], *nxt = &c->rec[1];
+    plan_step(c, *cur, 0, c->t, fixed_dt(c, c->t, t_end), c->dt_prev, nullptr, c->opt.max_picard);
+    rf_status s = enqueue_step(c, *cur, -1);
+    if (s) return s;
+    for (;;) {
+        const double tn = cur->t + cur->dt;
+        const bool ahead = before(tn, t_end);
+        const double dt_prev = extrapolating(c) ? cur->dt : 0.0;
+        if (ahead) {
+            plan_step(c, *nxt, cur->slot ^ 1, tn, fixed_dt(c, tn, t_end), dt_prev, nullptr,
+                      c->opt.max_picard);
+            s = enqueue_step(c, *nxt, cur->serial);
+            if (s) return s;
+        }
+        rf_step_stats st;
+        bool first = true;
+        s = finish_step(c, *cur, !ahead, &st, &first);
+        rs.picard_total += st.picard_iters;
+        rs.cg_total += st.cg_iters_total;
+        if (s != RF_OK) {
+            if (s != RF_ERR_HIP) rs.rejected++;
+            if (ahead && s != RF_ERR_HIP) {
+                // the step behind found this one not accepted and did nothing
+                const rf_status w = wait_readback(c, nxt->slot, true);
+                if (w) return w;
+                timed_drop(c, nxt->serial);
+            }
+            return s;
+        }
+        rs.accepted++;
+        if (!ahead) return RF_OK;
+        if (!first) {
+            timed_drop(c, nxt->serial);
+            plan_step(c, *nxt, nxt->slot, tn, nxt->dt, dt_prev, nullptr, c->opt.max_picard);
+            s = enqueue_step(c, *nxt, -1);
+            if (s) return s;
+        }
+        std::swap(cur, nxt);
+    }
+}
+
+// EBATS (Sec. 2.2): the next step's dt depends on how this one went, so
+// steps are enqueued one at a time.
+static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
+{
+    rf_step_stats st;
+    while (before(c->t, t_end)) {
+        double dt = c->dt_cur;
+        bool clipped = false;
+        const double tf = next_forcing_change(c, c->t);
+        if (c->t + dt > tf) { dt = tf - c->t; clipped = true; }
+        if (c->t + dt > t_end) { dt = t_end - c->t; clipped = true; }
+        rf_status s = picard_step(c, dt, nullptr, c->opt.max_iters, &st);
+        rs.picard_total += st.picard_iters;
+        rs.cg_total += st.cg_iters_total;
+        if (s == RF_ERR_HIP || s == RF_ERR_ARG || s == RF_ERR_STATE) return s;
+        if (s != RF_OK) {
+            rs.rejected++;
+            c->dt_cur = dt / c->opt.factor;
+            c->easy = 0;
+            if (c->dt_cur < c->opt.dt_min)
+                return fail(c, RF_ERR_NOT_CONVERGED, "EBATS: dt %g fell below dt_min %g", c->dt_cur,
+                            c->opt.dt_min);
+            continue;
+        }
+        rs.accepted++;
+        if (!clipped) c->dt_cur = dt;
+        if (st.picard_iters <= c->opt.few_iters) {
+            if (++c->easy >= c->opt.inc_after) {
+                c->dt_cur = std::min(c->dt_cur * c->opt.factor, c->opt.dt_max);
+                c->easy = 0;
+            }
+        } else {
+            c->easy = 0;
+        }
+    }
+    return RF_OK;
 }
 
 rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
@@ -859,44 +1053,8 @@ rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
     if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_run before rf_set_state");
     rf_run_stats rs;
     memset(&rs, 0, sizeof(rs));
-    rf_step_stats st;
-    rf_status ret = RF_OK;
-    while (c->t < t_end * (1.0 - 1e-15) - 1e-12) {
-        double dt = c->opt.ebats ? c->dt_cur : c->opt.dt0;
-        bool clipped = false;
-        const double tf = next_forcing_change(c, c->t);
-        if (c->t + dt > tf) { dt = tf - c->t; clipped = true; }
-        if (c->t + dt > t_end) { dt = t_end - c->t; clipped = true; }
-        const int maxp = c->opt.ebats ? c->opt.max_iters : c->opt.max_picard;
-        rf_status s = picard_step(c, dt, nullptr, maxp, &st);
-        rs.picard_total += st.picard_iters;
-        rs.cg_total += st.cg_iters_total;
-        if (s == RF_ERR_HIP || s == RF_ERR_ARG || s == RF_ERR_STATE) { ret = s; break; }
-        if (s != RF_OK) {
-            rs.rejected++;
-            if (!c->opt.ebats) { ret = s; break; }
-            c->dt_cur = dt / c->opt.factor;
-            c->easy = 0;
-            if (c->dt_cur < c->opt.dt_min) {
-                ret = fail(c, RF_ERR_NOT_CONVERGED, "EBATS: dt %g fell below dt_min %g", c->dt_cur,
-                           c->opt.dt_min);
-                break;
-            }
-            continue;
-        }
-        rs.accepted++;
-        if (c->opt.ebats) {
-            if (!clipped) c->dt_cur = dt;
-            if (st.picard_iters <= c->opt.few_iters) {
-                if (++c->easy >= c->opt.inc_after) {
-                    c->dt_cur = std::min(c->dt_cur * c->opt.factor, c->opt.dt_max);
-                    c->easy = 0;
-                }
-            } else {
-                c->easy = 0;
-            }
-        }
-    }
+    timed_drop(c);
+    const rf_status ret = c->opt.ebats ? run_ebats(c, t_end, rs) : run_fixed(c, t_end, rs);
     rs.t = c->t;
     rs.dt_last = c->opt.ebats ? c->dt_cur : c->opt.dt0;
     if (out) *out = rs;
@@ -937,7 +1095,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     const Bc bc = bc_at(c, c->t);
     (void)N;
-    HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, c->stream));
+    HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, -1, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
                            c->stream));
     HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, true, c->stream));
@@ -971,6 +1129,8 @@ rf_status rf_set_timing(rf_ctx *c, int mask)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     timed_drop(c);
     c->timing = mask & 0xff;
+    c->timing_every = 1;
+    c->timing_count = 0;
     const long cells = c->active;
     memset(&c->tm, 0, sizeof(c->tm));
     for (int k = 0; k < RF_NKERNELS; k++) c->tm.name[k] = kKernelNames[k];
@@ -978,10 +1138,12 @@ rf_status rf_set_timing(rf_ctx *c, int mask)
     return RF_OK;
 }
 
-rf_status rf_select_timing(rf_ctx *c, int mask)
+rf_status rf_select_timing(rf_ctx *c, int mask, int every)
 {
-    if (!c) return RF_ERR_ARG;
+    if (!c || every < 1) return RF_ERR_ARG;
     c->timing = mask & 0xff;
+    c->timing_every = every;
+    c->timing_count = 0;
     return RF_OK;
 }
 

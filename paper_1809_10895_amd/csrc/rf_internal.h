@@ -74,7 +74,8 @@ struct Scalars {
     int accepted;     // the step was accepted
     int accept_m;
     int cur_m;        // Picard iteration whose residual was formed last
-    int pad[2];
+    int accepted_serial;  // host serial of the last step accepted (written by k_accept only)
+    int pad;
     double tol_eff;   // PCG exit tolerance of the current solve (absolute, or relative in FP32)
     int cg_log[RF_MAX_PICARD_LOG];       // PCG iterations of each Picard iteration
     double delta_log[RF_MAX_PICARD_LOG]; // max |h^{m+1} - h^m| of each Picard iteration
@@ -125,9 +126,11 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s);
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             hipStream_t s);
-// hb0 = h0 + ratio * dh (ratio 0: a copy of h0).
+// hb0 = h0 + ratio * dh (ratio 0: a copy of h0).  gate >= 0: only if the
+// step with that serial has been accepted; otherwise nothing is done and the
+// step's later kernels are held (stall raised with stall_m = -1).
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                             const double *h0, double ratio, hipStream_t s);
+                             const double *h0, double ratio, int gate, hipStream_t s);
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s);
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, int variant, hipStream_t s);
@@ -148,8 +151,10 @@ hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed,
                          hipStream_t s);
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s);
-// track: also dh = h^{n+1} - h^n.
-hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, hipStream_t s);
+// track: also dh = h^{n+1} - h^n.  serial: the host's tag of the step,
+// recorded on acceptance.
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, int serial,
+                         hipStream_t s);
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             double *theta, double *C, double *K, hipStream_t s);
 hipError_t launch_operator(const Geo &g, const Arrays &a, const double *x, double *y,

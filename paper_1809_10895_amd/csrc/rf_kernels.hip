@@ -327,8 +327,19 @@ __global__ void __launch_bounds__(kThreads) k_set_state(Geo g, Soil so, Arrays a
 // every Dirichlet face for every layer (the face conductivity of a cell is
 // its own Ks times that entry).
 __global__ void __launch_bounds__(kThreads) k_step_begin(Geo g, Soil so, Bc bc, Arrays a,
-                                                         const double *h0, double ratio)
+                                                         const double *h0, double ratio, int gate)
 {
+    if (gate >= 0 && a.sc->accepted_serial != gate) {
+        // enqueued behind a step that its own work did not accept: nothing
+        // is done, and the stall flag holds every later kernel of this step
+        // (no block of this kernel writes accepted_serial, so all blocks
+        // take the same branch)
+        if (lead_thread() && !a.sc->stall) {
+            a.sc->stall = 1;
+            a.sc->stall_m = -1;
+        }
+        return;
+    }
     if (blockIdx.x == 0 && threadIdx.x < 6 * RF_MAX_LAYERS) {
         const int f = threadIdx.x / RF_MAX_LAYERS, l = threadIdx.x % RF_MAX_LAYERS;
         double kr = 0.0;
@@ -1225,7 +1236,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
 // Block partials (ps): [0] storage sum V theta~(h); [1+f] inflow rate through
 // face f with h = h^{m+1} and K = K(h^m) (the converged system).
 template <bool TRACK>
-__global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a)
+__global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a, int serial)
 {
     Scalars *s = a.sc;
     if (s->fail || s->stall || !s->picard_done) return;
@@ -1316,6 +1327,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a
     if (lead_thread()) {
         s->accepted = 1;
         s->accept_m = mf;
+        s->accepted_serial = serial;
     }
 }
 
@@ -1487,9 +1499,9 @@ hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const
 }
 
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
-                             const double *h0, double ratio, hipStream_t s)
+                             const double *h0, double ratio, int gate, hipStream_t s)
 {
-    RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0, ratio);
+    RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0, ratio, gate);
 }
 
 hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard, hipStream_t s)
@@ -1559,10 +1571,11 @@ hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, cons
                    t.max_cg);
 }
 
-hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, hipStream_t s)
+hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, int serial,
+                         hipStream_t s)
 {
-    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<true>, g, so, a);
-    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<false>, g, so, a);
+    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<true>, g, so, a, serial);
+    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<false>, g, so, a, serial);
 }
 
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,

@@ -108,3 +108,11 @@ def test_select_timing_keeps_counters_and_times_a_sample():
     tm = S.get_timing()
     assert tm["update"]["launches"] == cg_timed and tm["update"]["ms"] > 0.0
     assert tm["spmv"]["launches"] == 0
+    # a stride: steps 0, 3, 6 of nine
+    S.select_timing(["update"], every=3)
+    for i in range(9):
+        s, st = S.step(w.dt)
+        assert s == 0, S.last_error()
+        if i % 3 == 0:
+            cg_timed += st["cg_iters_total"]
+    assert S.get_timing()["update"]["launches"] == cg_timed
