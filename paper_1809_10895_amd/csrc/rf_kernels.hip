@@ -928,8 +928,10 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
     if (g.nz <= kWave) {
         // p_new = z + beta p_old and K at the cell and its lateral
         // neighbours for G2 columns, then the stencil; the vertical
-        // neighbours come from the adjacent lanes
-        constexpr int G2 = 2;
+        // neighbours come from the adjacent lanes.  FP64: one column at a
+        // time (70 VGPRs, so more waves are resident on large grids; two
+        // took 126); FP32: two, whose loads interleave
+        constexpr int G2 = std::is_same<T, double>::value ? 1 : 2;
         if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
         const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
         SpmvGroup<PRECOND, T, G2> gr;
