@@ -44,6 +44,7 @@ struct StepRec {
     double t = 0.0, dt = 0.0;   // start time and time step
     double ratio = 0.0;         // first iterate h^n + ratio (h^n - h^{n-1})
     const double *guess = nullptr;
+    const double *h0m = nullptr;   // where Picard iteration 0 reads h^0
     int max_picard = 1;
     int M = 0;                  // Picard iterations enqueued
     int naccept = 0;            // acceptance launches enqueued
@@ -287,6 +288,7 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
     a.layers = (Layer *)take(RF_MAX_LAYERS * sizeof(Layer));
     a.bt = (double *)take(24 * sizeof(double));
     a.sc = (Scalars *)take(sizeof(Scalars));
+    a.h0m = a.hb0;
     if (A) *A = a;
     return off;
 }
@@ -739,6 +741,7 @@ static CgTol cg_tol(const rf_ctx *c) { return CgTol{c->opt.tol_cg, c->opt.cg_rel
 // direction buffers alternate with the iteration count).
 static rf_status enqueue_pairs(rf_ctx *c, StepRec &r, int m, int n)
 {
+    c->A.h0m = r.h0m;
     Arrays &A = c->A;
     const int pc = c->opt.precond;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
@@ -752,6 +755,7 @@ static rf_status enqueue_pairs(rf_ctx *c, StepRec &r, int m, int n)
 
 static rf_status enqueue_apply(rf_ctx *c, StepRec &r, int m)
 {
+    c->A.h0m = r.h0m;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
     TIMED(c, r, K_APPLYH, m, r.apply_enq[mi]++,
           launch_apply_h(c->G, c->A, m, mixed(c), cg_tol(c), c->stream));
@@ -763,6 +767,7 @@ static rf_status enqueue_apply(rf_ctx *c, StepRec &r, int m)
 // at once when an earlier one has ended the step.
 static rf_status enqueue_iteration(rf_ctx *c, StepRec &r, int m)
 {
+    c->A.h0m = r.h0m;
     const Geo &G = c->G;
     Arrays &A = c->A;
     const int mi = std::min(m, RF_MAX_PICARD_LOG - 1);
@@ -782,6 +787,7 @@ static bool extrapolating(const rf_ctx *c) { return c->opt.first_iterate == RF_F
 // Exit test of the last enqueued iteration, acceptance, readback.
 static rf_status enqueue_accept(rf_ctx *c, StepRec &r)
 {
+    c->A.h0m = r.h0m;
     TIMED(c, r, K_DECIDE, r.M, -1, launch_decide(c->G, c->A, r.M, c->opt.tol_picard, c->stream));
     TIMED(c, r, K_ACCEPT, r.M, r.naccept,
           launch_accept(c->G, c->S, c->A, extrapolating(c), r.serial, c->stream));
@@ -802,6 +808,9 @@ static void plan_step(rf_ctx *c, StepRec &r, int slot, double t, double dt, doub
     r.dt = dt;
     r.ratio = (!guess && extrapolating(c) && dt_prev > 0.0) ? dt / dt_prev : 0.0;
     r.guess = guess;
+    // a step from h^n reads it in place; a guess or an extrapolated start is
+    // formed in hb0 by k_step_begin
+    r.h0m = (guess || r.ratio != 0.0) ? c->A.hb0 : c->A.hn;
     r.max_picard = max_picard;
     r.M = 0;
     r.naccept = 0;
@@ -815,9 +824,10 @@ static void plan_step(rf_ctx *c, StepRec &r, int slot, double t, double dt, doub
 // starts if the step with that serial was accepted (enqueued ahead of it).
 static rf_status enqueue_step(rf_ctx *c, StepRec &r, int gate)
 {
+    c->A.h0m = r.h0m;
+    const double *h0 = (r.h0m == c->A.hn) ? nullptr : (r.guess ? r.guess : c->A.hn);
     TIMED(c, r, K_BEGIN, -1, -1,
-          launch_step_begin(c->G, c->S, r.bc, c->A, r.guess ? r.guess : c->A.hn, r.ratio, gate,
-                            c->stream));
+          launch_step_begin(c->G, c->S, r.bc, c->A, h0, r.ratio, gate, c->stream));
     r.M = std::max(1, std::min(r.max_picard, c->pred_picard));
     for (int m = 0; m < r.M; m++) {
         rf_status s = enqueue_iteration(c, r, m);
@@ -1095,6 +1105,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     const size_t N = (size_t)c->nx * c->ny * c->nz;
     const Bc bc = bc_at(c, c->t);
     (void)N;
+    c->A.h0m = c->A.hb0;
     HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, -1, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
                            c->stream));

@@ -89,10 +89,13 @@ struct CgVec {
     T *K, *Dd, *diag, *tz, *rdp, *r, *p0, *p1, *q, *e, *z;
 };
 
-// Device arrays inside the bound workspace.  The Picard iterate h^m lives in
-// hb[m & 1]; iteration m writes h^{m+1} into hb[(m + 1) & 1].
+// Device arrays inside the bound workspace.  The Picard iterate h^m (m >= 1)
+// lives in hb[m & 1], h^0 at h0m; iteration m writes h^{m+1} into
+// hb[(m + 1) & 1].
 struct Arrays {
     double *hn, *thn, *hb0, *hb1, *K, *Dd, *bst, *diag, *r, *p0, *p1, *q, *e, *z, *Ks;
+    const double *h0m;        // iterate of Picard iteration 0: hn when the step starts
+                              // from h^n, else hb0 (filled by k_step_begin)
     double *dh;               // last accepted increment h^n - h^{n-1} (extrapolated first iterate)
     double *tz;               // z-line: coupling of cell k with k+1 (A_z K_f / dz)
     double *rdp;              // z-line: reciprocal pivots
@@ -126,7 +129,9 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s);
 hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const double *h,
                             hipStream_t s);
-// hb0 = h0 + ratio * dh (ratio 0: a copy of h0).  gate >= 0: only if the
+// Step flags and boundary tables; with h0 (not null) also hb0 = h0 + ratio *
+// dh (ratio 0: a copy of h0), for a.h0m = hb0.  Without h0 the step starts
+// from h^n (a.h0m = hn) and one block does the rest.  gate >= 0: only if the
 // step with that serial has been accepted; otherwise nothing is done and the
 // step's later kernels are held (stall raised with stall_m = -1).
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,

@@ -368,6 +368,7 @@ __global__ void __launch_bounds__(kThreads) k_step_begin(Geo g, Soil so, Bc bc, 
     int cb, ce;
     block_columns(g, g.cpb_w, cb, ce);
     RF_WAVE_IDS;
+    if (h0)
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
         for (int k0 = 0; k0 < kt; k0 += kWave) {
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_coeff(Geo g, Soil so, Arrays a,
     __shared__ double sKR[6 * RF_MAX_LAYERS];
     stage_bc(a, sBT, sKR);
     stage_layers(a, so.nlayer, sL);
-    const double *hmv = (m & 1) ? a.hb1 : a.hb0;
+    const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     const double vdt = g.V / dt;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
@@ -602,7 +603,7 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
     constexpr bool kCopyKD = !std::is_same<T, double>::value;
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
-    const double *hmv = (m & 1) ? a.hb1 : a.hb0;
+    const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
@@ -1155,7 +1156,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
-    const double *__restrict__ hmv = (m & 1) ? a.hb1 : a.hb0;
+    const double *__restrict__ hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
     const T *__restrict__ ev = e_in;
     int cb, ce;
@@ -1503,6 +1504,7 @@ hipError_t launch_set_state(const Geo &g, const Soil &so, const Arrays &a, const
 hipError_t launch_step_begin(const Geo &g, const Soil &so, const Bc &bc, const Arrays &a,
                              const double *h0, double ratio, int gate, hipStream_t s)
 {
+    if (!h0) RF_LAUNCH_N(1, k_step_begin, g, so, bc, a, h0, ratio, gate);
     RF_LAUNCH_W(k_step_begin, g, so, bc, a, h0, ratio, gate);
 }
 
