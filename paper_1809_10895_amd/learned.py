@@ -86,9 +86,14 @@ def crop(t, shape, x0, y0, cx, cy):
     return v.reshape(t.shape[:-1] + (cy * cx * nz,)).contiguous()
 
 
-def train(trajs, shape, steps, crop_xy=(32, 32), lr=1e-3, seed=0, log_every=0, init=None):
+def train(trajs, shape, steps, crop_xy=(32, 32), lr=1e-3, seed=0, log_every=0, init=None,
+          decay=0.3):
     """Adam on random (trajectory, step, crop) samples; returns the trained
-    parameters and the loss history."""
+    parameters and the loss history.  The step size is lr, then falls
+    linearly to zero over the last `decay` fraction of the steps: at a
+    constant rate the loss of single samples swings by more than an order of
+    magnitude from one stretch of steps to the next, and the parameters
+    depend on where training happens to stop."""
     nx, ny, nz = shape
     cx, cy = crop_xy
     rng = np.random.default_rng(seed)
@@ -105,7 +110,9 @@ def train(trajs, shape, steps, crop_xy=(32, 32), lr=1e-3, seed=0, log_every=0, i
         hp = crop(tr.states[max(n - 1, 0)], shape, x0, y0, cx, cy)
         tg = crop(tr.states[n + 1], shape, x0, y0, cx, cy)
         lk = crop(tr.lnks, shape, x0, y0, cx, cy)
-        losses.append(G.train_step(hn, hp, lk, tr.rain[n], tg, lr))
+        left = steps - it
+        rate = lr * min(1.0, left / (decay * steps)) if decay > 0 else lr
+        losses.append(G.train_step(hn, hp, lk, tr.rain[n], tg, rate))
         if log_every and (it + 1) % log_every == 0:
             print("train step %d loss %.4e" % (it + 1, np.mean(losses[-log_every:])), flush=True)
     return G.get_params(), np.array(losses)
