@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--ebats-days", type=float, default=1.0,
+                    help="simulated days of the adaptive-step extra (0: skip)")
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the dominant kernel in every N-th step of the timed region")
     ap.add_argument("--driver", choices=("run", "step"), default="run",
@@ -265,6 +267,48 @@ def timed_case(args, w, precision):
             "roofline": roof, "kernels_warmup": kernels}, h
 
 
+def ebats_day(args, w, days, dt0):
+    """Wall time per simulated day with adaptive steps (EBATS, Sec. 2.2: dt
+    from dt0 up to dt_max, x1.3 after ten easy steps, /1.3 and rerun above
+    eight Picard iterations) from the workload's initial state: the paper's
+    loop in FP64 and in mixed precision, and the extrapolated first iterate
+    with mixed precision; the largest head difference from the FP64 run."""
+    import numpy as np
+    import torch
+    from paper_1809_10895_amd import Solver, workloads as W
+    pc = 1 if args.precond == "zline" else 0
+    h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
+    out = {"days": days, "dt0_s": dt0, "dt_max_s": w.dt_max}
+    finals = {}
+    m = w.active_mask()
+    for name, prec, fi in (("plain_fp64", 0, 0), ("plain_mixed", 1, 0), ("extrapolate_mixed", 1, 1)):
+        S = Solver(0)
+        S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
+        W.configure(w, S)
+        S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=dt0,
+                      dt_max=w.dt_max, ebats=1, precision=prec, first_iterate=fi,
+                      cols_per_wave=args.cols_per_wave)
+        S.bind()
+        assert S.set_state(h0) == 0, S.last_error()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, rs = S.run(days * 86400.0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"status": s, "wall_s_per_simulated_day": el / days,
+                     "accepted": rs["accepted"], "rejected": rs["rejected"],
+                     "picard_total": rs["picard_total"], "cg_total": rs["cg_total"],
+                     "dt_last_s": rs["dt_last"]}
+        finals[name] = S.get_state()[0].cpu().numpy()
+        del S
+    out["max_abs_h_diff_m"] = {k: float(np.abs(v[m] - finals["plain_fp64"][m]).max())
+                               for k, v in finals.items() if k != "plain_fp64"}
+    base = out["plain_fp64"]["wall_s_per_simulated_day"]
+    out["speedup_vs_plain_fp64"] = {k: base / out[k]["wall_s_per_simulated_day"]
+                                    for k in ("plain_mixed", "extrapolate_mixed")}
+    return out
+
+
 def copy_reference(nbytes, reps=20):
     """Same-box reference rate: a device-to-device copy (the runtime's copy
     kernel) of nbytes, read + write counted, GB/s."""
@@ -366,7 +410,7 @@ def main():
     cells = w.active_cells
     progress("%s %s" % (args.workload, args.precision))
     main_r, h_main = timed_case(args, w, args.precision)
-    variant = learned_res = ens_res = None
+    variant = learned_res = ens_res = ebats_res = None
     if not args.no_extras:
         other = "mixed" if args.precision == "fp64" else "fp64"
         progress("%s %s" % (args.workload, other))
@@ -377,6 +421,12 @@ def main():
                    "max_abs_h_diff_m": float(np.abs(h_other[m] - h_main[m]).max()),
                    "roofline": r["roofline"]}
 
+    if not args.no_extras and args.ebats_days > 0:
+        progress("EBATS day")
+        # adaptive steps start from the workload's own first step (the
+        # watershed's 60 s; the fixed-step timing above uses 600 s there)
+        dt0 = 60.0 if args.workload == "watershed" else w.dt
+        ebats_res = ebats_day(args, w, args.ebats_days, dt0)
     if not args.no_extras and args.learned_steps > 0:
         progress("learned guess")
         learned_res = learned_guess(args.learned_steps)
@@ -403,6 +453,7 @@ def main():
         "roofline": main_r["roofline"],
         "kernels_warmup": main_r["kernels_warmup"],
         "other_precision": variant,
+        "ebats_day": ebats_res,
         "learned_guess": learned_res,
         "ensemble": ens_res,
         "cpu_baseline": cpu,
