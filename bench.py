@@ -368,7 +368,9 @@ def learned_guess(nsteps):
             "extrapolate_mixed_vs_plain_fp64": base / mixed["extrapolate"]["wall_s_per_simulated_day"],
             "max_abs_h_diff_m": max(fp64["max_abs_h_diff_m"], mixed["max_abs_h_diff_m"],
                                     fp64["max_abs_h_diff_m_extrapolate"],
-                                    mixed["max_abs_h_diff_m_extrapolate"])}
+                                    mixed["max_abs_h_diff_m_extrapolate"]),
+            # the paper's adaptive steps (EBATS) over a simulated day
+            "ebats_day": learned.evaluate_ebats(params, 200, days=1.0)}
 
 
 def ensemble(seconds):

@@ -2,12 +2,17 @@
 forward pass and the hand-written gradients against the CPU reference
 (oracle/guess_net.py, with the same BF16 roundings), training, and what a
 trained network gains over plain Picard on held-out seeds."""
+import os
+
 import numpy as np
 import pytest
 
 from oracle import guess_net as R
 from paper_1809_10895_amd import learned
+from paper_1809_10895_amd import workloads as W
 from paper_1809_10895_amd.binding import Guess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -108,3 +113,45 @@ def test_learned_guess_cuts_picard_iterations():
     # the runs converge every step to tol_picard = 1e-6 from different first
     # iterates; their states differ by the Picard stopping error only
     assert ev["max_abs_h_diff_m"] <= 2e-5, ev
+
+
+def test_ebats_loop_from_python_equals_rf_run():
+    """learned.ebats_run drives the library's adaptive time loop one rf_step
+    at a time: without a network it takes the same steps as rf_run (same
+    accepted and rejected steps, Picard totals and heads, bit for bit), with
+    a change of the rain rate inside the run."""
+    nx, ny, nz = 32, 24, 64
+    w = W.hillslope(nx=nx, ny=ny, nz=nz, seed=201)
+    t_end = 6 * 3600.0
+    t0q = learned.rain_steps(201, 40, 600.0)
+    out = []
+    for driver in ("rf_run", "loop"):
+        S = learned.make_solver(w, t0q)
+        S.set_options(dt0=600.0, dt_max=3600.0, precond=1, tol_picard=1e-6, tol_cg=1e-8, ebats=1,
+                      max_picard=8 if driver == "loop" else 50)
+        if driver == "rf_run":
+            s, rs = S.run(t_end)
+            assert s == 0, S.last_error()
+            r = (rs["accepted"], rs["rejected"], rs["picard_total"])
+        else:
+            e = learned.ebats_run(S, t0q, t_end, 600.0, 3600.0)
+            r = (e["accepted"], e["rejected"], e["picard_total"])
+        out.append((r, S.get_state()[0].cpu().numpy()))
+    assert out[0][0] == out[1][0], (out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_learned_guess_under_ebats_closes_the_water_balance():
+    """The committed network as the first iterate of the adaptive loop, with
+    mixed precision: every step converges to tol_picard, the network starts
+    most steps, and the water balance closes as in the plain run."""
+    params = np.fromfile(os.path.join(ROOT, "paper_1809_10895_amd", "data", "guess_hillslope.f32"),
+                         dtype=np.float32)
+    ev = learned.evaluate_ebats(params, 202, days=0.25, nx=48, ny=48, nz=64)
+    for k in ("plain_fp64", "plain_fp64_loop", "extrapolate_mixed", "learned_mixed"):
+        r = ev[k]
+        assert r["accepted"] > 0
+        assert abs(r["water_balance_error_m3"]) <= 1e-6 * max(abs(r["storage_change_m3"]), 1.0), (k, r)
+    assert ev["plain_fp64_loop"]["picard_total"] == ev["plain_fp64"]["picard_total"]
+    lm = ev["learned_mixed"]
+    assert lm["learned_steps"] >= 0.5 * lm["accepted"], lm
