@@ -933,11 +933,15 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
         // time (70 VGPRs, so more waves are resident on large grids; two
         // took 126); FP32: two, whose loads interleave
         constexpr int G2 = std::is_same<T, double>::value ? 1 : 2;
+        // FP64: the first group's loads are in flight while the partials are
+        // combined (2 % on this kernel; with FP32's two columns it was slower)
+        constexpr bool kAhead = std::is_same<T, double>::value;
+        SpmvGroup<PRECOND, T, G2> gr;
+        if (kAhead && cb + w < ce) gr.load(g, a, cv, p_in, cb + w, ce, lane);
         if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
         const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
-        SpmvGroup<PRECOND, T, G2> gr;
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            gr.load(g, a, cv, p_in, c0, ce, lane);
+            if (!kAhead || c0 != cb + w) gr.load(g, a, cv, p_in, c0, ce, lane);
             T pp[G2], pn[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
