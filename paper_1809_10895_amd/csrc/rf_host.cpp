@@ -1019,32 +1019,64 @@ static rf_status run_fixed(rf_ctx *c, double t_end, rf_run_stats &rs)
     }
 }
 
-// EBATS (Sec. 2.2): the next step's dt depends on how this one went, so
-// steps are enqueued one at a time.
+// EBATS (Sec. 2.2).  The next step's dt depends on how this one goes only
+// through acceptance (a rejected step is rerun with dt / factor) and when
+// this step could complete a run of inc_after easy steps (dt then grows).
+// Otherwise the next step is enqueued ahead, as with fixed steps, with the
+// dt it will have if this one is accepted; if it is not, the step behind
+// found it not accepted and did nothing.
 static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
 {
-    rf_step_stats st;
-    while (before(c->t, t_end)) {
-        double dt = c->dt_cur;
-        bool clipped = false;
-        const double tf = next_forcing_change(c, c->t);
-        if (c->t + dt > tf) { dt = tf - c->t; clipped = true; }
-        if (c->t + dt > t_end) { dt = t_end - c->t; clipped = true; }
-        rf_status s = picard_step(c, dt, nullptr, c->opt.max_iters, &st);
+    if (!before(c->t, t_end)) return RF_OK;
+    auto plan_at = [&](StepRec &r, int slot, double t, double dt, double dt_prev, bool &clipped) {
+        clipped = false;
+        const double tf = next_forcing_change(c, t);
+        if (t + dt > tf) { dt = tf - t; clipped = true; }
+        if (t + dt > t_end) { dt = t_end - t; clipped = true; }
+        plan_step(c, r, slot, t, dt, dt_prev, nullptr, c->opt.max_iters);
+    };
+    StepRec *cur = &c->rec[0], *nxt = &c->rec[1];
+    bool clipped = false, clipped_nxt = false;
+    plan_at(*cur, 0, c->t, c->dt_cur, c->dt_prev, clipped);
+    rf_status s = enqueue_step(c, *cur, -1);
+    if (s) return s;
+    for (;;) {
+        const double tn = cur->t + cur->dt;
+        const bool ahead = before(tn, t_end) && c->easy + 1 < c->opt.inc_after;
+        if (ahead) {
+            // dt_cur after this step if it is accepted (no growth possible here)
+            const double dt_next = clipped ? c->dt_cur : cur->dt;
+            plan_at(*nxt, cur->slot ^ 1, tn, dt_next, extrapolating(c) ? cur->dt : 0.0,
+                    clipped_nxt);
+            s = enqueue_step(c, *nxt, cur->serial);
+            if (s) return s;
+        }
+        rf_step_stats st;
+        bool first = true;
+        s = finish_step(c, *cur, !ahead, &st, &first);
         rs.picard_total += st.picard_iters;
         rs.cg_total += st.cg_iters_total;
         if (s == RF_ERR_HIP || s == RF_ERR_ARG || s == RF_ERR_STATE) return s;
         if (s != RF_OK) {
             rs.rejected++;
-            c->dt_cur = dt / c->opt.factor;
+            if (ahead) {
+                // the step behind found this one not accepted and did nothing
+                const rf_status w = wait_readback(c, nxt->slot, true);
+                if (w) return w;
+                timed_drop(c, nxt->serial);
+            }
+            c->dt_cur = cur->dt / c->opt.factor;
             c->easy = 0;
             if (c->dt_cur < c->opt.dt_min)
                 return fail(c, RF_ERR_NOT_CONVERGED, "EBATS: dt %g fell below dt_min %g", c->dt_cur,
                             c->opt.dt_min);
+            plan_at(*cur, cur->slot, cur->t, c->dt_cur, c->dt_prev, clipped);
+            s = enqueue_step(c, *cur, -1);
+            if (s) return s;
             continue;
         }
         rs.accepted++;
-        if (!clipped) c->dt_cur = dt;
+        if (!clipped) c->dt_cur = cur->dt;
         if (st.picard_iters <= c->opt.few_iters) {
             if (++c->easy >= c->opt.inc_after) {
                 c->dt_cur = std::min(c->dt_cur * c->opt.factor, c->opt.dt_max);
@@ -1053,8 +1085,17 @@ static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
         } else {
             c->easy = 0;
         }
+        if (!before(tn, t_end)) return RF_OK;
+        if (!ahead || !first) {
+            // the next step was not enqueued, or did nothing: enqueue it now
+            if (ahead) timed_drop(c, nxt->serial);
+            plan_at(*nxt, cur->slot ^ 1, tn, c->dt_cur, c->dt_prev, clipped_nxt);
+            s = enqueue_step(c, *nxt, -1);
+            if (s) return s;
+        }
+        std::swap(cur, nxt);
+        clipped = clipped_nxt;
     }
-    return RF_OK;
 }
 
 rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
