@@ -234,7 +234,10 @@ rf_status rf_step(rf_ctx *ctx, double dt, const double *h_guess_dev, rf_step_sta
  * with dt/factor; after inc_after consecutive accepted steps with at most
  * few_iters iterations dt grows by factor, up to dt_max.  Returns
  * RF_ERR_NOT_CONVERGED if dt falls below dt_min (state at the last accepted
- * step).  *out (may be NULL) receives the totals. */
+ * step).  *out (may be NULL) receives the totals.  The next step is enqueued
+ * before the current one is waited for whenever its dt does not depend on
+ * how the current one goes; the results are those of the same steps taken
+ * one rf_step at a time.  Nothing is left in flight on return. */
 rf_status rf_run(rf_ctx *ctx, double t_end, rf_run_stats *out);
 
 /* Water balance since rf_set_state: storage sum V theta~(h) (Eq. 2 plus
