@@ -10,7 +10,8 @@ the oracle does in seconds:
    every column of the oracle's matrix;
 4. one GPU step of 60 s: its heads are a fixed point of the oracle's Picard
    map to within the Picard tolerance, and its water balance closes to the
-   bound the chord scheme implies.
+   bound the chord scheme implies; the same with the PCG in FP32 under the
+   FP64 Picard loop (the benchmark's mixed-precision options).
 """
 import numpy as np
 import pytest
@@ -90,6 +91,19 @@ def test_watershed_full_size_step_is_a_picard_fixed_point(ws):
     while the storage uses theta~(h); the difference per cell is
     V |C(h*) - C*| |h - h*| <= V 2 C_max tol_picard."""
     w, P, S = ws
+    fixed_point_checks(w, P, S)
+
+
+def test_watershed_full_size_mixed_step_is_a_picard_fixed_point(ws):
+    """As above with FP32 PCG (tol_cg 1e-8, no relative test): the Picard
+    residual is formed in FP64, so the stop on an increment below
+    tol_picard bounds the FP64 residual at the heads the same way."""
+    w, P, _ = ws
+    S = make_solver(w, precond=1, precision=1, tol_cg=1e-8, cg_rel_tol=0.0, max_picard=50)
+    fixed_point_checks(w, P, S)
+
+
+def fixed_point_checks(w, P, S):
     tol = 1e-6
     assert S.set_state(dev(w.h0)) == 0
     s, st = S.step(w.dt)
