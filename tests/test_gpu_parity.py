@@ -271,12 +271,15 @@ def test_error_paths():
     assert S2.L.rf_step(S2.h, -1.0, None, None) == -1       # RF_ERR_ARG
 
 
-def test_hillslope_full_size_one_step(orc):
+@pytest.mark.parametrize("precond", [1, 0])
+def test_hillslope_full_size_one_step(orc, precond):
     """The 128x128x64 hillslope in the launch shape the benchmark times: one
-    600 s step against the oracle (tight PCG tolerance on both sides)."""
+    600 s step against the oracle (tight PCG tolerance on both sides, so the
+    result does not depend on the preconditioner), with the z-line and the
+    Jacobi preconditioner on the GPU."""
     w = W.hillslope()
     P = make_oracle(orc, w)
-    S = make_solver(w, precond=1)
+    S = make_solver(w, precond=precond)
     s_o, st_o = P.step(w.dt)
     s_g, st_g = S.step(w.dt)
     assert s_o == 0 and s_g == 0
