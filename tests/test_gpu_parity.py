@@ -271,15 +271,16 @@ def test_error_paths():
     assert S2.L.rf_step(S2.h, -1.0, None, None) == -1       # RF_ERR_ARG
 
 
-@pytest.mark.parametrize("precond", [1, 0])
-def test_hillslope_full_size_one_step(orc, precond):
+@pytest.mark.parametrize("precond,variant", [(1, 0), (0, 0), (1, 1)])
+def test_hillslope_full_size_one_step(orc, precond, variant):
     """The 128x128x64 hillslope in the launch shape the benchmark times: one
     600 s step against the oracle (tight PCG tolerance on both sides, so the
     result does not depend on the preconditioner), with the z-line and the
-    Jacobi preconditioner on the GPU."""
+    Jacobi preconditioner on the GPU, and with the modified Picard
+    linearisation on both sides."""
     w = W.hillslope()
-    P = make_oracle(orc, w)
-    S = make_solver(w, precond=precond)
+    P = make_oracle(orc, w, picard_variant=variant)
+    S = make_solver(w, precond=precond, picard_variant=variant)
     s_o, st_o = P.step(w.dt)
     s_g, st_g = S.step(w.dt)
     assert s_o == 0 and s_g == 0
