@@ -177,14 +177,16 @@ def test_appendix_b_steep_front_modified_picard(orc):
     run_both(orc, w, tol_picard=1e-4, picard_variant=1)
 
 
-@pytest.mark.parametrize("case", ["column100", "small_3d"])
+@pytest.mark.parametrize("case", ["column100", "small_3d", "hillslope_full"])
 def test_extrapolated_first_iterate(orc, case):
     """first_iterate = RF_FIRST_EXTRAPOLATE: the GPU starts each Picard loop
     from h^n + (h^n - h^{n-1}); the oracle is handed the same first iterate
     (computed here from its own states).  Same Picard counts and heads; on
-    the smoothly advancing column also fewer iterations than from h^n."""
-    w = W.column100() if case == "column100" else small_3d()
-    nsteps = 30 if case == "column100" else 5
+    the smoothly advancing column also fewer iterations than from h^n.  Also
+    the 128x128x64 hillslope in the benchmark's launch shape (three steps,
+    two of them extrapolated)."""
+    w = {"column100": W.column100, "small_3d": small_3d, "hillslope_full": W.hillslope}[case]()
+    nsteps = {"column100": 30, "small_3d": 5, "hillslope_full": 3}[case]
     P = make_oracle(orc, w)
     S = make_solver(w, precond=1, first_iterate=1)
     P0 = make_oracle(orc, w)                       # plain start, for the iteration count
