@@ -144,8 +144,8 @@ def test_run_ahead_failing_step_leaves_last_accepted_state():
     assert np.array_equal(state(Sa)[0], state(Sb)[0])
 
 
-@pytest.mark.parametrize("max_iters,precision", [(4, 0), (8, 0), (8, 1)])
-def test_run_ahead_under_ebats_matches_single_steps(max_iters, precision):
+@pytest.mark.parametrize("max_iters,precision,first", [(4, 0, 0), (8, 0, 0), (8, 1, 0), (4, 0, 1)])
+def test_run_ahead_under_ebats_matches_single_steps(max_iters, precision, first):
     """rf_run with EBATS runs ahead while the step in flight cannot lengthen
     dt; it must take the steps that the same rules take one rf_step at a
     time (learned.ebats_run without a network): same accepted and rejected
@@ -153,7 +153,8 @@ def test_run_ahead_under_ebats_matches_single_steps(max_iters, precision):
     step, and with eight, the rain jump makes steps fail and rerun (about 240
     and 50 steps over the six hours; a heavier rain that ponds the surface
     drives dt down to tens of thousands of steps); with eight also in mixed
-    precision."""
+    precision, and with four from the extrapolated first iterate, whose ratio
+    follows dt through the reruns."""
     from paper_1809_10895_amd import learned
     w = rainy(jump=3.5, q2=2.5e-6)
     t_end = 6 * 3600.0
@@ -162,7 +163,7 @@ def test_run_ahead_under_ebats_matches_single_steps(max_iters, precision):
     for driver in ("rf_run", "steps"):
         S = make_solver(w, precond=1, tol_cg=1e-8, ebats=1, dt0=w.dt, dt_max=3600.0,
                         max_iters=max_iters, max_picard=max_iters if driver == "steps" else 50,
-                        precision=precision)
+                        precision=precision, first_iterate=first)
         if driver == "rf_run":
             s, rs = S.run(t_end)
             assert s == 0, S.last_error()
