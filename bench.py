@@ -65,13 +65,10 @@ def parse():
     ap.add_argument("--cg-rel-tol", type=float, default=0.0,
                     help="relative PCG exit test (0 = absolute tol_cg only)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="time the headline line only (no other precision, learned guess or "
-                         "ensemble): profiler runs")
+                    help="time the headline line only (no other precision, adaptive-step day or "
+                         "learned guess): profiler runs")
     ap.add_argument("--learned-steps", type=int, default=24,
                     help="steps of the learned-guess comparison (0 = skip)")
-    ap.add_argument("--ensemble-seconds", type=float, default=0.0,
-                    help="simulated span of the 4096-column ensemble, run in a child process "
-                         "(0 = skip, the default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -373,21 +370,6 @@ def learned_guess(nsteps):
             "ebats_day": learned.evaluate_ebats(params, 200, days=1.0)}
 
 
-def ensemble(seconds):
-    """The 4096-column ensemble, measured in a child process of its own (see
-    paper_1809_10895_amd/ensemble_bench.py) with a time limit."""
-    import subprocess
-    try:
-        r = subprocess.run([sys.executable, "-m", "paper_1809_10895_amd.ensemble_bench", "--seconds",
-                            str(seconds)], cwd=ROOT, capture_output=True, text=True, timeout=150)
-    except subprocess.TimeoutExpired:
-        return {"error": "the ensemble process did not finish within 150 s"}
-    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
-    if r.returncode != 0 or not lines:
-        return {"error": "ensemble process exited with %d" % r.returncode}
-    return json.loads(lines[-1])
-
-
 def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
@@ -412,7 +394,7 @@ def main():
     cells = w.active_cells
     progress("%s %s" % (args.workload, args.precision))
     main_r, h_main = timed_case(args, w, args.precision)
-    variant = learned_res = ens_res = ebats_res = None
+    variant = learned_res = ebats_res = None
     if not args.no_extras:
         other = "mixed" if args.precision == "fp64" else "fp64"
         progress("%s %s" % (args.workload, other))
@@ -432,9 +414,6 @@ def main():
     if not args.no_extras and args.learned_steps > 0:
         progress("learned guess")
         learned_res = learned_guess(args.learned_steps)
-    if not args.no_extras and args.ensemble_seconds > 0:
-        progress("ensemble (child process)")
-        ens_res = ensemble(args.ensemble_seconds)
     add_copy_reference(main_r["roofline"])
     progress("cpu baseline")
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
@@ -457,7 +436,6 @@ def main():
         "other_precision": variant,
         "ebats_day": ebats_res,
         "learned_guess": learned_res,
-        "ensemble": ens_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -117,7 +117,9 @@ rf_status rf_ens_get_state(const rf_ens *e, double *h_dev);
  * registers.  A column that fails keeps its last accepted state and its
  * status; the others go on.  Returns
  * RF_ERR_NOT_CONVERGED or RF_ERR_NONFINITE if any column failed (the
- * summary says how many), RF_OK otherwise.  *out may be NULL. */
+ * summary says how many), RF_OK otherwise.  *out may be NULL.
+ * Currently switched off: returns RF_ERR_STATE (rf_ens_last_error says why)
+ * without launching anything, as does rf_ens_autotune. */
 rf_status rf_ens_run(rf_ens *e, double t_end, rf_ens_summary *out);
 
 /* Copies the ncol per-column records to host memory out[ncol]. */

@@ -379,11 +379,21 @@ static rf_status ens_run(rf_ens *e, double t_end, rf_ens_summary *out)
     return RF_OK;
 }
 
+// The persistent run kernel is switched off: its launches did not return on
+// the GPU after other GPU work in the same process, with no fault reported,
+// and that cause has not been shown.  Until it is, rf_ens_run and
+// rf_ens_autotune refuse to launch it.
+static const bool kEnsRunEnabled = false;
+static const char *kEnsRunOff =
+    "the column-ensemble run kernel is switched off: its launches did not return on the GPU "
+    "and the cause has not been shown";
+
 rf_status rf_ens_run(rf_ens *e, double t_end, rf_ens_summary *out)
 {
     if (!e) return RF_ERR_ARG;
     if (!e->have_state) return efail(e, RF_ERR_STATE, "rf_ens_run before rf_ens_set_state");
     if (!std::isfinite(t_end)) return efail(e, RF_ERR_ARG, "non-finite t_end");
+    if (!kEnsRunEnabled) return efail(e, RF_ERR_STATE, "%s", kEnsRunOff);
     EHIP(e, hipSetDevice(e->device));
     return ens_run(e, t_end, out);
 }
@@ -404,6 +414,7 @@ rf_status rf_ens_autotune(rf_ens *e, double t_span, rf_ens_tile *best)
     if (!e) return RF_ERR_ARG;
     if (!e->have_state) return efail(e, RF_ERR_STATE, "rf_ens_autotune before rf_ens_set_state");
     if (!(t_span > 0) || !std::isfinite(t_span)) return efail(e, RF_ERR_ARG, "invalid t_span");
+    if (!kEnsRunEnabled) return efail(e, RF_ERR_STATE, "%s", kEnsRunOff);
     EHIP(e, hipSetDevice(e->device));
     const size_t hb = (size_t)e->ncell * sizeof(double), cb = (size_t)e->ncol * sizeof(rf_ens_column);
     EHIP(e, hipMemcpyAsync(e->A.h_bak, e->A.h, hb, hipMemcpyDeviceToDevice, e->stream));
