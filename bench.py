@@ -2,19 +2,26 @@
 """Benchmark of the Richards-equation hot path on one MI355X.
 
 One step = one backward-Euler time step with its whole Picard loop (soil
-coefficients, assembly, PCG solve, Picard exit test, step acceptance) on the
-3-D hillslope workload (128 x 128 x 64 cells, lognormal Ks, rain on top),
-inputs resident in HBM.  Prints ONE JSON line with the throughput in
+coefficients, assembly, PCG solve, Picard exit test, step acceptance) of the
+watershed workload: 512 x 512 x 64 cells of 2 x 2 x 0.2 m under a fractal
+surface (12.46 M active cells), three soil layers (Eq. 5) with a lognormal Ks
+field, hourly seeded rain, adaptive steps (EBATS) from 60 s up to 3600 s,
+FP64; inputs resident in HBM.  Prints ONE JSON line with the throughput in
 cell-steps/s, the roofline of the dominant kernel (HIP events on the library
 stream, inside the timed region; also against device copies measured on the
-same box, outside it) and the CPU oracle timed on a bounded sample.
+same box, outside it) and the CPU oracle timed on a bounded sample (the
+serial method and the multi-core slab mode).
 
-    python bench.py [--gpus 1] [--steps 144] [--warmup 64] [--workload hillslope]
+    python bench.py [--gpus 1] [--steps 40] [--warmup 5] [--workload watershed]
                     [--precision fp64|mixed]
 
-The headline line is FP64 (the paper's arithmetic); the same steps are then
-timed in the other precision and reported under "other_precision", with the
-largest head difference between the two final states.
+The timed steps are the run's steps warmup+1 .. warmup+steps, taken from the
+initial state by the library's own adaptive time loop (rf_run_steps).  The
+one-time costs of a process (code objects, the first long queue of work) are
+paid on a separate context before.  The same steps are then timed in the
+other precision ("other_precision"), and a whole simulated day is timed with
+the paper's loop, mixed precision and the extrapolated first iterate
+("ebats_day").
 """
 import argparse
 import hashlib
@@ -56,9 +63,9 @@ PRECISION = {"fp64": 0, "mixed": 1}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=144)
-    ap.add_argument("--warmup", type=int, default=64)
-    ap.add_argument("--workload", default="hillslope", choices=["hillslope", "watershed", "column100"])
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="watershed", choices=["watershed", "hillslope", "column100"])
     ap.add_argument("--precond", default="zline", choices=["zline", "jacobi"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="arithmetic of the timed line (fp64 = the paper's)")
@@ -70,7 +77,9 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=24,
                     help="steps of the learned-guess comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="budget of the CPU-oracle sample (0 = skip)")
+                    help="budget of the CPU-oracle sample in slab mode on all threads (0 = skip)")
+    ap.add_argument("--cpu-serial-steps", type=int, default=1,
+                    help="steps of the one-thread CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--ebats-days", type=float, default=1.0,
                     help="simulated days of the adaptive-step extra (0: skip)")
@@ -88,41 +97,82 @@ def parse():
 
 def make_workload(name):
     from paper_1809_10895_amd import workloads as W
-    if name == "hillslope":
+    if name == "watershed":
+        w = W.watershed()
+        desc = ("watershed 512x512x64 cells of 2x2x0.2 m, fractal (Hurst 0.8) surface mask, three "
+                "Eq.-5 layers with lognormal Ks (ln-sigma 1), hourly seeded rain (10% wet, "
+                "exponential depths of mean 2 mm), EBATS dt 60 s -> 3600 s, FP64 PCG tol 1e-8 m")
+    elif name == "hillslope":
         w = W.hillslope()
         desc = "hillslope 128x128x64, 1x1x0.1 m cells, lognormal Ks (ln-sigma 1), rain 1e-7 m/s, dt 600 s"
-    elif name == "watershed":
-        w = W.watershed()
-        desc = "watershed 512x512x64 (fractal surface mask), 2x2x0.2 m cells, 3 Eq.-5 layers, dt 600 s"
-        w.dt = 600.0
     else:
         w = W.column100()
         desc = "1-D column 1x1x100, dz 1 cm, top Dirichlet -0.75 m, dt 10 s"
     return w, desc
 
 
-def cpu_baseline(w, seconds):
-    """The oracle as it stands, single thread, on as many steps of the same
-    workload as fit in `seconds` (at least one)."""
+def host_info():
+    """CPU model, sockets and cores of this host (lscpu), and os.cpu_count()."""
+    import subprocess
+    info = {"os_cpu_count": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(w, seconds, serial_steps):
+    """The oracle as it stands on the first steps of the same workload from its
+    initial state (each of the workload's first step size, dt0 = EBATS's
+    first step): as many steps as fit in `seconds` in the slab mode (block-
+    Jacobi DIC over one sub-domain of whole y-rows per thread, the 'simple'
+    decomposition of Sec. 2.3) on every OpenMP thread, and `serial_steps`
+    steps of the serial method (natural-order DIC-PCG, one thread)."""
     import oracle
-    P = oracle.Problem(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, ktop=w.ktop, grad_elev=w.grad_elev)
     from paper_1809_10895_amd import workloads as W
-    W.configure(w, P)
-    P.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, ebats=0, dt0=w.dt)
-    P.set_state(w.h0)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        s, _ = P.step(w.dt)
-        if s != 0:
-            break
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    el = time.perf_counter() - t0
-    return {"value": w.active_cells * n / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d backward-Euler steps of the same workload from its initial state, "
-                      "DIC-PCG in natural order, one thread (%.1f s)" % (n, el)}
+
+    def run(nslab, budget, nmax):
+        P = oracle.Problem(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, ktop=w.ktop, grad_elev=w.grad_elev)
+        W.configure(w, P)
+        P.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, ebats=0, dt0=w.dt)
+        P.set_slabs(nslab)
+        P.set_state(w.h0)
+        t0 = time.perf_counter()
+        n = 0
+        while n < nmax:
+            s, _ = P.step(w.dt)
+            if s != 0:
+                break
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return n, time.perf_counter() - t0
+
+    nthr = oracle.threads()
+    out = {"unit": "cell-steps/s", "kind": "oracle", "host": host_info()}
+    if seconds > 0:
+        nslab = max(1, min(nthr, w.ny))
+        n, el = run(nslab, seconds, 10 ** 9)
+        out.update({"value": w.active_cells * n / el, "cores": nthr,
+                    "sample": "%d backward-Euler steps of %g s of the same workload from its initial "
+                              "state, DIC-PCG with block-Jacobi DIC over %d slabs of whole y-rows "
+                              "(the 'simple' decomposition), %d OpenMP threads (%.1f s)"
+                              % (n, w.dt, nslab, nthr, el)})
+    if serial_steps > 0:
+        n, el = run(1, 0.0, serial_steps)
+        one = {"value": w.active_cells * n / el, "cores": 1,
+               "sample": "%d backward-Euler step(s) of %g s from the initial state, DIC-PCG in "
+                         "natural order, one thread (%.1f s)" % (n, w.dt, el)}
+        if "value" in out:
+            out["one_thread"] = one
+        else:
+            out.update(one)
+    return out if "value" in out else None
 
 
 def kernel_source_hash():
@@ -149,74 +199,74 @@ def measured_traffic(workload, kernel, precision):
 
 
 def timed_case(args, w, precision):
-    """Warm-up, then `args.steps` timed steps of `w` in the given precision.
+    """`args.warmup` untimed steps, then `args.steps` timed steps of `w` from its
+    initial state in the given precision, through the library's time loop
+    (rf_run_steps: EBATS when the workload adapts its steps, else fixed dt).
     Returns the measured figures and the final state (host copy)."""
     import torch
     from paper_1809_10895_amd import Solver, workloads as W
     pc = 1 if args.precond == "zline" else 0
     h0 = torch.tensor(w.h0, dtype=torch.float64, device="cuda:0")
+    far = 1e12          # the runs stop on their step counts
 
     def solver():
         S = Solver(0)
         S.setup_grid(w.nx, w.ny, w.nz, w.dx, w.dy, w.dz, w.ktop, w.grad_elev)
         W.configure(w, S)
         S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt,
-                      ebats=0, cols_per_wave=args.cols_per_wave,
+                      dt_max=w.dt_max, ebats=int(w.ebats), cols_per_wave=args.cols_per_wave,
                       precision=PRECISION[precision], cg_rel_tol=args.cg_rel_tol)
         S.bind()
         assert S.set_state(h0) == 0, S.last_error()
         return S
 
     algo_bytes = ALGO_BYTES[precision]
-    picard = cg = 0
-    # warm-up on a context of its own, so that the timed steps are the
-    # workload's first ones: steps 2-5 time every kernel to find the dominant
-    # one; the rest go through the timed driver untimed
-    # (the HIP runtime sets up, once per process, what a long queue of work
-    # needs: the first few dozen steps run ahead cost about 6 ms more)
+    # One-time costs of the process, on a context of its own: the first step
+    # (code objects loaded, scratch set up at a kernel's first launch), then
+    # steps 2-5 with every kernel timed (the per-kernel table, which names the
+    # dominant kernel), then 48 steps through the time loop, whose first long
+    # queue of enqueued-ahead work the HIP runtime sets up once per process
+    # (a few ms in all).
     S = solver()
-    n_all = min(5, args.warmup)
-    # the first step, which also pays one-time costs (code objects loaded
-    # and scratch set up at a kernel's first launch), is not in the table
-    for _ in range(1 if n_all > 1 else 0):
-        s, st = S.step(w.dt)
-        assert s == 0, S.last_error()
+    s, st = S.step(w.dt)
+    assert s == 0, S.last_error()
     S.set_timing(True)
-    for _ in range(n_all - (1 if n_all > 1 else 0)):
+    for _ in range(4):
         s, st = S.step(w.dt)
         assert s == 0, S.last_error()
     tm_all = S.get_timing()
     S.set_timing(False)
-    rest = args.warmup - n_all
-    if rest and args.driver == "run":
-        s, rs = S.run(S.get_state()[1] + rest * w.dt)
-        assert s == 0 and rs["accepted"] == rest, S.last_error()
-    else:
-        for _ in range(rest):
-            s, st = S.step(w.dt)
-            assert s == 0, S.last_error()
+    s, rs = S.run(far, max_steps=48)
+    assert s == 0 and rs["accepted"] == 48, S.last_error()
     tot_all = sum(v["ms"] for v in tm_all.values() if isinstance(v, dict))
     kern = max((k for k in algo_bytes if k in tm_all and tm_all[k]["launches"]),
                key=lambda k: tm_all[k]["ms"], default=None)
-    S.close() if hasattr(S, "close") else None
     del S
+    # the measured context: from the initial state, warmup steps, then the
+    # timed ones, all through the same adaptive time loop
     S = solver()
+    if args.warmup > 0:
+        s, rs = S.run(far, max_steps=args.warmup)
+        assert s == 0 and rs["accepted"] == args.warmup, S.last_error()
+    t_start = S.get_state()[1]
     # timed region: HIP events time the dominant kernel's launches in every
     # timing_every-th step (a timed launch costs some overhead of its own)
     timed = [kern] if (kern and not args.no_timing) else False
     S.set_timing(timed)
     S.select_timing(timed, every=max(1, args.timing_every))
-    t_start = S.get_state()[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if args.driver == "run":
-        # the library's time loop: fixed steps, each enqueued before the one
-        # ahead of it is waited for
-        s, rs = S.run(t_start + args.steps * w.dt)
+        s, rs = S.run(far, max_steps=args.steps)
         if s != 0 or rs["accepted"] != args.steps:
             raise SystemExit("run failed: %s %s" % (rs, S.last_error()))
-        picard, cg = rs["picard_total"], rs["cg_total"]
+        picard, cg, rejected = rs["picard_total"], rs["cg_total"], rs["rejected"]
     else:
+        # one rf_step call per step, with the step sizes of the time loop
+        # (fixed-step workloads only)
+        if w.ebats:
+            raise SystemExit("--driver step needs a fixed-step workload")
+        picard = cg = rejected = 0
         for i in range(args.steps):
             s, st = S.step(w.dt)
             if s != 0:
@@ -225,6 +275,7 @@ def timed_case(args, w, precision):
             cg += st["cg_iters_total"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    t_stop = S.get_state()[1]
     tm = S.get_timing()
     cells = w.active_cells
 
@@ -260,7 +311,9 @@ def timed_case(args, w, precision):
     h = S.get_state()[0].cpu().numpy()
     return {"value": cells * args.steps / el, "ms_per_step": el / args.steps * 1e3,
             "picard_per_step": picard / args.steps, "cg_per_picard": cg / max(picard, 1),
-            "wall_s_per_simulated_day": el / (args.steps * w.dt) * 86400.0,
+            "rejected_steps": rejected, "simulated_s": [t_start, t_stop],
+            "mean_dt_s": (t_stop - t_start) / args.steps,
+            "wall_s_per_simulated_day": el / (t_stop - t_start) * 86400.0,
             "roofline": roof, "kernels_warmup": kernels}, h
 
 
@@ -407,16 +460,14 @@ def main():
 
     if not args.no_extras and args.ebats_days > 0:
         progress("EBATS day")
-        # adaptive steps start from the workload's own first step (the
-        # watershed's 60 s; the fixed-step timing above uses 600 s there)
-        dt0 = 60.0 if args.workload == "watershed" else w.dt
-        ebats_res = ebats_day(args, w, args.ebats_days, dt0)
+        # adaptive steps from the workload's own first step
+        ebats_res = ebats_day(args, w, args.ebats_days, w.dt)
     if not args.no_extras and args.learned_steps > 0:
         progress("learned guess")
         learned_res = learned_guess(args.learned_steps)
     add_copy_reference(main_r["roofline"])
     progress("cpu baseline")
-    cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    cpu = cpu_baseline(w, args.cpu_seconds, args.cpu_serial_steps)
     out = {
         "metric": "cell-steps/s at Picard tol 1e-6", "value": main_r["value"], "unit": "cell-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -424,12 +475,15 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "active_cells": cells, "grid": [w.nx, w.ny, w.nz],
-                   "dt_s": w.dt, "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
+                   "dt0_s": w.dt, "dt_max_s": w.dt_max if w.ebats else w.dt,
+                   "ebats": bool(w.ebats), "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
                    "cg_rel_tol": args.cg_rel_tol, "precision": args.precision,
                    "precond": args.precond, "cols_per_wave": args.cols_per_wave,
-                   "driver": "rf_run" if args.driver == "run" else "rf_step per step",
+                   "driver": "rf_run_steps" if args.driver == "run" else "rf_step per step",
                    "picard_per_step": main_r["picard_per_step"],
                    "cg_per_picard": main_r["cg_per_picard"],
+                   "rejected_steps": main_r["rejected_steps"],
+                   "simulated_s": main_r["simulated_s"], "mean_dt_s": main_r["mean_dt_s"],
                    "wall_s_per_simulated_day": main_r["wall_s_per_simulated_day"]},
         "roofline": main_r["roofline"],
         "kernels_warmup": main_r["kernels_warmup"],

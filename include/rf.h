@@ -240,6 +240,13 @@ rf_status rf_step(rf_ctx *ctx, double dt, const double *h_guess_dev, rf_step_sta
  * one rf_step at a time.  Nothing is left in flight on return. */
 rf_status rf_run(rf_ctx *ctx, double t_end, rf_run_stats *out);
 
+/* rf_run that also stops after max_steps (>= 1) accepted steps: the same
+ * steps, in the same way, as rf_run up to that point (EBATS state, run-ahead,
+ * statistics); a later rf_run or rf_run_steps continues from there.  Lets a
+ * caller take a fixed number of adaptive steps (Sec. 2.2, EBATS), e.g. to
+ * time them.  RF_ERR_ARG when max_steps < 1. */
+rf_status rf_run_steps(rf_ctx *ctx, double t_end, long max_steps, rf_run_stats *out);
+
 /* Water balance since rf_set_state: storage sum V theta~(h) (Eq. 2 plus
  * S*max(h,0)) and the boundary inflow of every accepted step, evaluated with
  * the converged iterate. */

@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", SRC, "-o", tmp, "-lm"])
+                               "-ffp-contract=off", "-fopenmp", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -106,6 +106,9 @@ def lib():
         L.orc_eval_cells.argtypes = [vp, vp, vp, vp, vp]
         L.orc_storage.restype = C.c_double
         L.orc_storage.argtypes = [vp, vp]
+        L.orc_set_slabs.argtypes = [vp, C.c_int]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
         L.orc_time.restype = C.c_double
         L.orc_time.argtypes = [vp]
         L.orc_dt.restype = C.c_double
@@ -138,6 +141,11 @@ def conductivity(h, p, model=VGM):
     """K(h) of Eq. 4 (Gardner, Eq. A6, with model=GARDNER)."""
     L, pp = lib(), _params(p)
     return np.array([L.orc_conductivity(model, float(x), pp) for x in np.atleast_1d(h)])
+
+
+def threads() -> int:
+    """OpenMP threads the slab mode uses."""
+    return lib().orc_threads()
 
 
 def step_stats_dict(st: StepStats) -> dict:
@@ -179,6 +187,13 @@ class Problem:
                                _ptr(self._lnks))
         if s:
             raise ValueError("set_soil failed %d" % s)
+
+    def set_slabs(self, nslab):
+        """Slab mode: nslab sub-domains of whole y-rows with block-Jacobi DIC
+        (the 'simple' decomposition of Sec. 2.3) and OpenMP threads; 1 = the
+        serial method."""
+        if lib().orc_set_slabs(self.h, int(nslab)):
+            raise ValueError("set_slabs")
 
     def set_bc(self, face, kind, value=0.0):
         if lib().orc_set_bc(self.h, face, kind, float(value)):

@@ -29,11 +29,22 @@
  * assembled explicitly (diagonal + six neighbour coefficients per cell), the
  * preconditioner sweeps run serially, no loop is blocked or fused.
  *
+ * Optional slab mode (orc_set_slabs, used only to time the method on many
+ * host cores): the grid is cut into slabs of whole y-rows, one per
+ * sub-domain, as the paper's 'simple' mesh decomposition does (Sec. 2.3);
+ * the DIC factorisation and sweeps then ignore the couplings between slabs
+ * (block Jacobi over sub-domains, like a decomposed OpenFOAM case whose
+ * processor patches are left out of the preconditioner), and the slabs,
+ * the assembly and the vector operations run on OpenMP threads.  The
+ * converged solution is the same; only the PCG iteration count changes.
+ * With one slab (the default) every loop is the serial one above.
+ *
  * Layout of every per-cell array: cell (i,j,k) is at k + nz*(i + nx*j);
  * k = 0 is the bottom layer, z points up.  Column (i,j) is active for
  * k < ktop[i + nx*j].  Inactive cells are carried unchanged.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -105,6 +116,7 @@ typedef struct {
     double storage0, storage;
     double inflow[6];
     int have_storage0;
+    int nslab;       /* sub-domains of whole y-rows (1 = the serial method) */
 } orc_problem;
 
 /* ======================================================================
@@ -182,7 +194,26 @@ orc_problem *orc_create(int nx, int ny, int nz, double dx, double dy, double dz,
     P->opt.max_iters = 8; P->opt.factor = 1.3;
     P->opt.picard_variant = ORC_PICARD_CHORD;
     P->dt_cur = P->opt.dt0;
+    P->nslab = 1;
     return P;
+}
+
+/* Slab mode: nslab sub-domains of whole y-rows (1 <= nslab <= ny). */
+int orc_set_slabs(orc_problem *P, int nslab)
+{
+    if (nslab < 1 || nslab > P->ny) return ORC_ERR_ARG;
+    P->nslab = nslab;
+    return ORC_OK;
+}
+
+/* Threads the slab mode's parallel loops use (OMP_NUM_THREADS). */
+int orc_threads(void) { return omp_get_max_threads(); }
+
+/* Rows [j0, j1) of slab s. */
+static void slab_rows(const orc_problem *P, int s, int *j0, int *j1)
+{
+    *j0 = (int)((long)s * P->ny / P->nslab);
+    *j1 = (int)((long)(s + 1) * P->ny / P->nslab);
 }
 
 void orc_free(orc_problem *P)
@@ -354,6 +385,7 @@ static void assemble(const orc_problem *P, const double *hm, const double *hn,
 
     memset(S->off, 0, sizeof(double) * 6 * N);
     /* cell coefficients */
+#pragma omp parallel for private(p) schedule(static) if (P->nslab > 1)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++)
             for (int k = 0; k < nz; k++) {
@@ -383,7 +415,8 @@ static void assemble(const orc_problem *P, const double *hm, const double *hn,
                 S->diag[c] = V * C / dt;
                 S->b[c] = V * C * hn[c] / dt;
             }
-    /* faces */
+    /* faces (each cell writes only its own row) */
+#pragma omp parallel for private(p) schedule(static) if (P->nslab > 1)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++)
             for (int k = 0; k < nz; k++) {
@@ -479,6 +512,7 @@ static void neighbour_index(const orc_problem *P, size_t c, int d, size_t *cn, i
 static void matvec(const orc_problem *P, const orc_system *S, const double *x, double *y)
 {
     size_t N = ncell(P);
+#pragma omp parallel for schedule(static) if (P->nslab > 1)
     for (size_t c = 0; c < N; c++) {
         double s = S->diag[c] * x[c];
         for (int d = 0; d < 6; d++) {
@@ -494,15 +528,29 @@ static void matvec(const orc_problem *P, const orc_system *S, const double *x, d
 
 /* Diagonal incomplete Cholesky, M = (Dt + L) Dt^-1 (Dt + L^T), where L is the
  * strictly lower part of A in natural order and Dt is chosen so that
- * Dt_c = A_cc - sum_{lower n} A_cn^2 / Dt_n.  rD = 1/Dt. */
-static int dic_factor(const orc_problem *P, const orc_system *S, double *rD)
+ * Dt_c = A_cc - sum_{lower n} A_cn^2 / Dt_n.  rD = 1/Dt.
+ * In slab mode each slab is factorised on its own: the y-couplings across a
+ * slab boundary are left out (block Jacobi over the sub-domains). */
+
+/* Whether the coupling of cell c (in slab rows [j0, j1)) in direction dd is
+ * kept by the preconditioner: not when it crosses the slab boundary. */
+static int in_slab(const orc_problem *P, size_t c, int dd, int j0, int j1)
+{
+    const int j = (int)(c / ((size_t)P->nz * P->nx));
+    if (dd == 2) return j > j0;        /* -y */
+    if (dd == 3) return j + 1 < j1;    /* +y */
+    return 1;
+}
+
+static int dic_factor_slab(const orc_problem *P, const orc_system *S, double *rD, int j0, int j1)
 {
     size_t N = ncell(P);
-    for (size_t c = 0; c < N; c++) {
+    const size_t row = (size_t)P->nz * P->nx;
+    for (size_t c = (size_t)j0 * row; c < (size_t)j1 * row; c++) {
         double d = S->diag[c];
         for (int dd = 0; dd < 6; dd += 2) {      /* lower neighbours: -x, -y, -z */
             double a = S->off[(size_t)dd * N + c];
-            if (a == 0.0) continue;
+            if (a == 0.0 || !in_slab(P, c, dd, j0, j1)) continue;
             size_t cn; int ok;
             neighbour_index(P, c, dd, &cn, &ok);
             d -= a * a * rD[cn];
@@ -513,26 +561,40 @@ static int dic_factor(const orc_problem *P, const orc_system *S, double *rD)
     return ORC_OK;
 }
 
-static void dic_apply(const orc_problem *P, const orc_system *S, const double *rD,
-                      const double *r, double *w, double *z)
+static int dic_factor(const orc_problem *P, const orc_system *S, double *rD)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(static, 1) reduction(| : bad) if (P->nslab > 1)
+    for (int sl = 0; sl < P->nslab; sl++) {
+        int j0, j1;
+        slab_rows(P, sl, &j0, &j1);
+        if (dic_factor_slab(P, S, rD, j0, j1) != ORC_OK) bad = 1;
+    }
+    return bad ? ORC_ERR_LINEAR : ORC_OK;
+}
+
+static void dic_apply_slab(const orc_problem *P, const orc_system *S, const double *rD,
+                           const double *r, double *w, double *z, int j0, int j1)
 {
     size_t N = ncell(P);
-    for (size_t c = 0; c < N; c++) {           /* forward: (Dt + L) w = r */
+    const size_t row = (size_t)P->nz * P->nx;
+    const size_t c0 = (size_t)j0 * row, c1 = (size_t)j1 * row;
+    for (size_t c = c0; c < c1; c++) {         /* forward: (Dt + L) w = r */
         double s = r[c];
         for (int dd = 0; dd < 6; dd += 2) {
             double a = S->off[(size_t)dd * N + c];
-            if (a == 0.0) continue;
+            if (a == 0.0 || !in_slab(P, c, dd, j0, j1)) continue;
             size_t cn; int ok;
             neighbour_index(P, c, dd, &cn, &ok);
             s -= a * w[cn];
         }
         w[c] = s * rD[c];
     }
-    for (size_t cc = N; cc-- > 0;) {           /* backward: (I + Dt^-1 L^T) z = w */
+    for (size_t cc = c1; cc-- > c0;) {         /* backward: (I + Dt^-1 L^T) z = w */
         double s = 0.0;
         for (int dd = 1; dd < 6; dd += 2) {    /* upper neighbours: +x, +y, +z */
             double a = S->off[(size_t)dd * N + cc];
-            if (a == 0.0) continue;
+            if (a == 0.0 || !in_slab(P, cc, dd, j0, j1)) continue;
             size_t cn; int ok;
             neighbour_index(P, cc, dd, &cn, &ok);
             s += a * z[cn];
@@ -541,17 +603,47 @@ static void dic_apply(const orc_problem *P, const orc_system *S, const double *r
     }
 }
 
-static double dot(size_t N, const double *a, const double *b)
+static void dic_apply(const orc_problem *P, const orc_system *S, const double *rD,
+                      const double *r, double *w, double *z)
 {
+#pragma omp parallel for schedule(static, 1) if (P->nslab > 1)
+    for (int sl = 0; sl < P->nslab; sl++) {
+        int j0, j1;
+        slab_rows(P, sl, &j0, &j1);
+        dic_apply_slab(P, S, rD, r, w, z, j0, j1);
+    }
+}
+
+static double dot(const orc_problem *P, const double *a, const double *b)
+{
+    size_t N = ncell(P);
+    if (P->nslab == 1) {
+        double s = 0.0;
+        for (size_t c = 0; c < N; c++) s += a[c] * b[c];
+        return s;
+    }
+    /* slab mode: one partial sum per slab, added in slab order */
+    double part[P->nslab];
+    const size_t row = (size_t)P->nz * P->nx;
+#pragma omp parallel for schedule(static, 1)
+    for (int sl = 0; sl < P->nslab; sl++) {
+        int j0, j1;
+        slab_rows(P, sl, &j0, &j1);
+        double s = 0.0;
+        for (size_t c = (size_t)j0 * row; c < (size_t)j1 * row; c++) s += a[c] * b[c];
+        part[sl] = s;
+    }
     double s = 0.0;
-    for (size_t c = 0; c < N; c++) s += a[c] * b[c];
+    for (int sl = 0; sl < P->nslab; sl++) s += part[sl];
     return s;
 }
 
 /* Jacobi-scaled residual max |r_c / A_cc|, in metres. */
-static double scaled_res(size_t N, const double *r, const double *diag)
+static double scaled_res(const orc_problem *P, const double *r, const double *diag)
 {
+    size_t N = ncell(P);
     double m = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : m) if (P->nslab > 1)
     for (size_t c = 0; c < N; c++) {
         double v = fabs(r[c] / diag[c]);
         if (v > m) m = v;
@@ -573,27 +665,30 @@ static int pcg_dic(const orc_problem *P, const orc_system *S, double *x, double 
     double *rD = (double *)calloc(N, sizeof(double));
     int it = 0, failed = 0;
     if (dic_factor(P, S, rD) != ORC_OK) failed = 1;
+    const int par = P->nslab > 1;
     if (!failed) {
         matvec(P, S, x, q);
         for (size_t c = 0; c < N; c++) r[c] = S->b[c] - q[c];
     }
-    if (!failed && scaled_res(N, r, S->diag) > tol) {
+    if (!failed && scaled_res(P, r, S->diag) > tol) {
         dic_apply(P, S, rD, r, w, z);
         memcpy(p, z, sizeof(double) * N);
-        double rho = dot(N, r, z);
+        double rho = dot(P, r, z);
         for (;;) {
             if (it >= max_it) { failed = 1; break; }
             matvec(P, S, p, q);
-            double pq = dot(N, p, q);
+            double pq = dot(P, p, q);
             if (!(pq > 0.0)) { failed = 1; break; }
             double alpha = rho / pq;
+#pragma omp parallel for schedule(static) if (par)
             for (size_t c = 0; c < N; c++) { x[c] += alpha * p[c]; r[c] -= alpha * q[c]; }
             it++;
-            if (scaled_res(N, r, S->diag) <= tol) break;
+            if (scaled_res(P, r, S->diag) <= tol) break;
             dic_apply(P, S, rD, r, w, z);
-            double rho_new = dot(N, r, z);
+            double rho_new = dot(P, r, z);
             double beta = rho_new / rho;
             rho = rho_new;
+#pragma omp parallel for schedule(static) if (par)
             for (size_t c = 0; c < N; c++) p[c] = z[c] + beta * p[c];
         }
     }

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "RF_OK", -1: "RF_ERR_ARG", -2: "RF_ERR_STATE", -3: "RF_ERR_HI
 EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf_setup_grid",
            "rf_set_soil", "rf_set_bc", "rf_set_forcing", "rf_set_options", "rf_workspace_bytes",
            "rf_bind_workspace", "rf_set_state", "rf_get_state", "rf_step", "rf_run",
-           "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
+           "rf_run_steps", "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
            "rf_apply_precond", "rf_set_timing", "rf_select_timing", "rf_get_timing",
            # include/rf_ensemble.h
            "rf_ens_create", "rf_ens_destroy", "rf_ens_last_error", "rf_ens_setup", "rf_ens_set_bc",
@@ -137,6 +137,7 @@ def load_library(path: str = LIB):
     L.rf_get_state.argtypes = [vp, vp, C.POINTER(C.c_double)]
     L.rf_step.argtypes = [vp, dp, vp, C.POINTER(RfStepStats)]
     L.rf_run.argtypes = [vp, dp, C.POINTER(RfRunStats)]
+    L.rf_run_steps.argtypes = [vp, dp, C.c_long, C.POINTER(RfRunStats)]
     L.rf_mass_balance.argtypes = [vp, C.POINTER(RfMass)]
     L.rf_eval_soil.argtypes = [vp, vp, vp, vp, vp]
     L.rf_assemble.argtypes = [vp, vp, dp, vp, vp]
@@ -309,9 +310,13 @@ class Solver:
         s = self.L.rf_step(self.h, float(dt), _ptr(guess), C.byref(st))
         return s, step_stats_dict(st)
 
-    def run(self, t_end):
+    def run(self, t_end, max_steps=None):
+        """rf_run to t_end, or rf_run_steps when max_steps (accepted steps) is given."""
         rs = RfRunStats()
-        s = self.L.rf_run(self.h, float(t_end), C.byref(rs))
+        if max_steps is None:
+            s = self.L.rf_run(self.h, float(t_end), C.byref(rs))
+        else:
+            s = self.L.rf_run_steps(self.h, float(t_end), int(max_steps), C.byref(rs))
         return s, {"accepted": rs.accepted, "rejected": rs.rejected,
                    "picard_total": rs.picard_total, "cg_total": rs.cg_total,
                    "dt_last": rs.dt_last, "t": rs.t}

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -975,7 +976,7 @@ static double fixed_dt(const rf_ctx *c, double t, double t_end, bool *clipped = 
 // next without waiting for the host.  If this step needed more work than was
 // enqueued up front, the next one found it not accepted, did nothing, and is
 // enqueued again behind that work.
-static rf_status run_fixed(rf_ctx *c, double t_end, rf_run_stats &rs)
+static rf_status run_fixed(rf_ctx *c, double t_end, long max_acc, rf_run_stats &rs)
 {
     if (!before(c->t, t_end)) return RF_OK;
     StepRec *cur = &c->rec[0], *nxt = &c->rec[1];
@@ -984,7 +985,7 @@ static rf_status run_fixed(rf_ctx *c, double t_end, rf_run_stats &rs)
     if (s) return s;
     for (;;) {
         const double tn = cur->t + cur->dt;
-        const bool ahead = before(tn, t_end);
+        const bool ahead = before(tn, t_end) && rs.accepted + 1 < max_acc;
         const double dt_prev = extrapolating(c) ? cur->dt : 0.0;
         if (ahead) {
             plan_step(c, *nxt, cur->slot ^ 1, tn, fixed_dt(c, tn, t_end), dt_prev, nullptr,
@@ -1025,7 +1026,7 @@ static rf_status run_fixed(rf_ctx *c, double t_end, rf_run_stats &rs)
 // Otherwise the next step is enqueued ahead, as with fixed steps, with the
 // dt it will have if this one is accepted; if it is not, the step behind
 // found it not accepted and did nothing.
-static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
+static rf_status run_ebats(rf_ctx *c, double t_end, long max_acc, rf_run_stats &rs)
 {
     if (!before(c->t, t_end)) return RF_OK;
     auto plan_at = [&](StepRec &r, int slot, double t, double dt, double dt_prev, bool &clipped) {
@@ -1042,7 +1043,8 @@ static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
     if (s) return s;
     for (;;) {
         const double tn = cur->t + cur->dt;
-        const bool ahead = before(tn, t_end) && c->easy + 1 < c->opt.inc_after;
+        const bool ahead = before(tn, t_end) && c->easy + 1 < c->opt.inc_after &&
+                           rs.accepted + 1 < max_acc;
         if (ahead) {
             // dt_cur after this step if it is accepted (no growth possible here)
             const double dt_next = clipped ? c->dt_cur : cur->dt;
@@ -1085,7 +1087,7 @@ static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
         } else {
             c->easy = 0;
         }
-        if (!before(tn, t_end)) return RF_OK;
+        if (!before(tn, t_end) || rs.accepted >= max_acc) return RF_OK;
         if (!ahead || !first) {
             // the next step was not enqueued, or did nothing: enqueue it now
             if (ahead) timed_drop(c, nxt->serial);
@@ -1098,18 +1100,32 @@ static rf_status run_ebats(rf_ctx *c, double t_end, rf_run_stats &rs)
     }
 }
 
-rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
+static rf_status run_capped(rf_ctx *c, double t_end, long max_acc, rf_run_stats *out)
 {
-    if (!c) return RF_ERR_ARG;
-    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_run before rf_set_state");
     rf_run_stats rs;
     memset(&rs, 0, sizeof(rs));
     timed_drop(c);
-    const rf_status ret = c->opt.ebats ? run_ebats(c, t_end, rs) : run_fixed(c, t_end, rs);
+    const rf_status ret = c->opt.ebats ? run_ebats(c, t_end, max_acc, rs)
+                                       : run_fixed(c, t_end, max_acc, rs);
     rs.t = c->t;
     rs.dt_last = c->opt.ebats ? c->dt_cur : c->opt.dt0;
     if (out) *out = rs;
     return ret;
+}
+
+rf_status rf_run(rf_ctx *c, double t_end, rf_run_stats *out)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_run before rf_set_state");
+    return run_capped(c, t_end, LONG_MAX, out);
+}
+
+rf_status rf_run_steps(rf_ctx *c, double t_end, long max_steps, rf_run_stats *out)
+{
+    if (!c) return RF_ERR_ARG;
+    if (!c->have_state) return fail(c, RF_ERR_STATE, "rf_run_steps before rf_set_state");
+    if (max_steps < 1) return fail(c, RF_ERR_ARG, "max_steps %ld < 1", max_steps);
+    return run_capped(c, t_end, max_steps, out);
 }
 
 rf_status rf_mass_balance(const rf_ctx *c, rf_mass *out)

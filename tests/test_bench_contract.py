@@ -27,7 +27,8 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 @pytest.mark.gpu
 def test_one_json_line_with_the_contract_fields():
-    r = run_bench("--steps", "3", "--warmup", "1", "--no-extras", "--cpu-seconds", "2")
+    r = run_bench("--workload", "hillslope", "--steps", "3", "--warmup", "1", "--no-extras",
+                  "--cpu-seconds", "2", "--cpu-serial-steps", "1")
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
     assert len(lines) == 1, r.stdout
@@ -41,3 +42,5 @@ def test_one_json_line_with_the_contract_fields():
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-3)
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
+    assert cpu["one_thread"]["cores"] == 1 and cpu["one_thread"]["value"] > 0
+    assert cpu["host"]["os_cpu_count"] >= 1
