@@ -58,6 +58,7 @@ ALGO_BYTES = {
     },
 }
 PRECISION = {"fp64": 0, "mixed": 1}
+STENCIL = {"columns": 0, "tiles": 1}
 
 
 def parse():
@@ -90,6 +91,9 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy this many MiB with torch before the steps (reference kernel of "
                          "known traffic for hardware-counter runs)")
+    ap.add_argument("--stencil", default="tiles", choices=["tiles", "columns"],
+                    help="how the stencil kernels reach lateral neighbours (LDS tiles or "
+                         "per-wave neighbour columns)")
     ap.add_argument("--cols-per-wave", type=int, default=0,
                     help="launch shape of the PCG kernels (0 = chosen from the grid size)")
     return ap.parse_args()
@@ -215,7 +219,8 @@ def timed_case(args, w, precision):
         W.configure(w, S)
         S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt,
                       dt_max=w.dt_max, ebats=int(w.ebats), cols_per_wave=args.cols_per_wave,
-                      precision=PRECISION[precision], cg_rel_tol=args.cg_rel_tol)
+                      precision=PRECISION[precision], cg_rel_tol=args.cg_rel_tol,
+                      stencil=STENCIL[args.stencil])
         S.bind()
         assert S.set_state(h0) == 0, S.last_error()
         return S
@@ -337,7 +342,7 @@ def ebats_day(args, w, days, dt0):
         W.configure(w, S)
         S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=dt0,
                       dt_max=w.dt_max, ebats=1, precision=prec, first_iterate=fi,
-                      cols_per_wave=args.cols_per_wave)
+                      cols_per_wave=args.cols_per_wave, stencil=STENCIL[args.stencil])
         S.bind()
         assert S.set_state(h0) == 0, S.last_error()
         torch.cuda.synchronize()
@@ -478,7 +483,8 @@ def main():
                    "dt0_s": w.dt, "dt_max_s": w.dt_max if w.ebats else w.dt,
                    "ebats": bool(w.ebats), "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
                    "cg_rel_tol": args.cg_rel_tol, "precision": args.precision,
-                   "precond": args.precond, "cols_per_wave": args.cols_per_wave,
+                   "precond": args.precond, "stencil": args.stencil,
+                   "cols_per_wave": args.cols_per_wave,
                    "driver": "rf_run_steps" if args.driver == "run" else "rf_step per step",
                    "picard_per_step": main_r["picard_per_step"],
                    "cg_per_picard": main_r["cg_per_picard"],

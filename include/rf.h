@@ -99,6 +99,14 @@ enum { RF_REFACTOR_EVERY = 0, RF_REFACTOR_STEP = 1 };
  * RF_WAIT_BLOCK: hipStreamSynchronize, which may put the thread to sleep and
  * wakes it later (3 % slower per step on a 1 M-cell grid). */
 enum { RF_WAIT_SPIN = 0, RF_WAIT_BLOCK = 1 };
+/* How the stencil kernels reach a cell's lateral neighbours (grids of at most
+ * 64 cells per column; taller columns always use RF_STENCIL_COLUMNS).
+ * RF_STENCIL_TILES: a workgroup stages a tile of 8 x 4 columns with its
+ * one-column halo in LDS, each column read once per tile.
+ * RF_STENCIL_COLUMNS: each wavefront loads its column's four neighbour
+ * columns itself.  Results agree to rounding (the same arithmetic per cell,
+ * reductions combined in a different order). */
+enum { RF_STENCIL_COLUMNS = 0, RF_STENCIL_TILES = 1 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -133,6 +141,7 @@ typedef struct {
     int first_iterate;  /* RF_FIRST_PREVIOUS (default) or RF_FIRST_EXTRAPOLATE */
     int zline_refactor; /* RF_REFACTOR_EVERY (default) or RF_REFACTOR_STEP */
     int host_wait;      /* RF_WAIT_SPIN (default) or RF_WAIT_BLOCK */
+    int stencil;        /* RF_STENCIL_TILES (default) or RF_STENCIL_COLUMNS */
 } rf_options;
 
 typedef struct {

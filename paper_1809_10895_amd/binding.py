@@ -25,6 +25,7 @@ RF_PICARD_CHORD, RF_PICARD_MODIFIED = 0, 1
 RF_FIRST_PREVIOUS, RF_FIRST_EXTRAPOLATE = 0, 1
 RF_REFACTOR_EVERY, RF_REFACTOR_STEP = 0, 1
 RF_WAIT_SPIN, RF_WAIT_BLOCK = 0, 1
+RF_STENCIL_COLUMNS, RF_STENCIL_TILES = 0, 1
 RF_MAX_PICARD_LOG = 128
 RF_NKERNELS = 8
 
@@ -59,7 +60,7 @@ class RfOptions(C.Structure):
                 ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double),
                 ("cols_per_wave", C.c_int), ("precision", C.c_int), ("cg_rel_tol", C.c_double),
                 ("picard_variant", C.c_int), ("first_iterate", C.c_int), ("zline_refactor", C.c_int),
-                ("host_wait", C.c_int)]
+                ("host_wait", C.c_int), ("stencil", C.c_int)]
 
 
 class RfStepStats(C.Structure):

@@ -250,7 +250,9 @@ static size_t max_partial_blocks(const rf_ctx *c)
     const size_t ncol = (size_t)c->nx * c->ny;
     size_t nb = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
     if (nb >= 8) nb = (nb + 7) / 8 * 8;
-    return nb;
+    // tiled stencil kernels: one block per tile of kTileX x kTileY columns
+    const size_t nt = (size_t)((c->nx + kTileX - 1) / kTileX) * ((c->ny + kTileY - 1) / kTileY);
+    return std::max(nb, nt);
 }
 
 static size_t layout(const rf_ctx *c, char *base, Arrays *A)
@@ -314,8 +316,7 @@ static void set_shapes(rf_ctx *c)
     if (nb >= 8) nb = (nb + 7) / 8 * 8;
     G.nblk = (int)nb;
     G.cpb = (int)((ncol + nb - 1) / nb);
-    G.np = (G.nblk > kPartialsMax) ? 1 : G.nblk;
-    G.foff = (G.np == 1 && G.nblk > 1) ? G.nblk : 0;
+
     // When the whole grid of the reducing kernels is resident at once (two
     // blocks per CU), give each XCD one slab of consecutive columns: the
     // +-y neighbour columns of a block then sit in its own XCD's L2 instead
@@ -323,6 +324,27 @@ static void set_shapes(rf_ctx *c)
     // bytes with the identity map).  Larger grids stream through in launch
     // order, where the identity map measured faster.
     G.block_map = (c->n_cu > 0 && G.nblk <= 2 * c->n_cu) ? 1 : 0;
+    // tiled stencil kernels (columns of at most one wave, grids of at least
+    // one tile): one block per tile, their own partial count
+    G.ntx = (c->nx + kTileX - 1) / kTileX;
+    G.nblk_t = G.ntx * ((c->ny + kTileY - 1) / kTileY);
+    G.tiled = c->opt.stencil == RF_STENCIL_TILES && c->nz <= kWave && c->nx >= kTileX &&
+              c->ny >= kTileY;
+    // what consumers of block partials read (see Geo): the producers' own
+    // partials if they all have the same, few enough blocks; else a folded
+    // total in the slot after the largest producer's partials
+    const int nprod = std::max(G.nblk, G.tiled ? G.nblk_t : 0);
+    const bool same = !G.tiled || G.nblk_t == G.nblk;
+    if (nprod <= 1) {
+        G.np = 1;
+        G.foff = 0;
+    } else if (nprod > kPartialsMax || !same) {
+        G.np = 1;
+        G.foff = nprod;
+    } else {
+        G.np = G.nblk;
+        G.foff = 0;
+    }
 }
 
 
@@ -450,6 +472,7 @@ void rf_default_options(rf_options *o)
     o->first_iterate = RF_FIRST_PREVIOUS;
     o->zline_refactor = RF_REFACTOR_EVERY;
     o->host_wait = RF_WAIT_SPIN;
+    o->stencil = RF_STENCIL_TILES;
 }
 
 rf_status rf_create(rf_ctx **out, int hip_device, void *hip_stream)
@@ -642,7 +665,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         (o->picard_variant != RF_PICARD_CHORD && o->picard_variant != RF_PICARD_MODIFIED) ||
         (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE) ||
         (o->zline_refactor != RF_REFACTOR_EVERY && o->zline_refactor != RF_REFACTOR_STEP) ||
-        (o->host_wait != RF_WAIT_SPIN && o->host_wait != RF_WAIT_BLOCK))
+        (o->host_wait != RF_WAIT_SPIN && o->host_wait != RF_WAIT_BLOCK) ||
+        (o->stencil != RF_STENCIL_COLUMNS && o->stencil != RF_STENCIL_TILES))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {
         // the FP32 arrays exist only in a workspace laid out for them

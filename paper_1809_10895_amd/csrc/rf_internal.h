@@ -15,6 +15,8 @@ constexpr int kWavesPerBlock = 8;   // one column per wave at a time
 constexpr int kThreads = kWave * kWavesPerBlock;
 constexpr int kPartialsMax = 512;   // partials every block of a consumer kernel may combine
 constexpr int kRedSlots = 8;        // values per block partial
+constexpr int kTileX = 8;           // tiled stencil kernels: interior columns of a tile along x
+constexpr int kTileY = 4;           // ... and along y (kTileX * kTileY / kWavesPerBlock per wave)
 
 // Per-layer van Genuchten parameters (Ks is per cell).
 struct Layer {
@@ -28,17 +30,23 @@ struct Soil {
 };
 
 // Geometry and launch shapes of one grid.  Kernels that write block
-// partials use nblk blocks of cpb columns; when nblk exceeds kPartialsMax a
-// one-block fold kernel combines the partials first, so that every block of
-// the consumer combines np <= kPartialsMax values.  Kernels without a
-// reduction use nblk_w blocks of cpb_w columns (one column per wave).
+// partials use nblk blocks of cpb columns, or, for the tiled stencil kernels,
+// nblk_t blocks of one tile each.  Every consumer combines np partials at
+// offset foff (in values of the partial set): the producer's own partials
+// (np = nblk, foff = 0) when every producer has the same kPartialsMax or
+// fewer blocks; otherwise a one-block fold kernel after each producer
+// combines them into the slot foff (np = 1).  Kernels without a reduction
+// use nblk_w blocks of cpb_w columns (one column per wave).
 struct Geo {
     int nx, ny, nz, ncol;
     int nblk, cpb;          // kernels that write block partials
     int np;                 // partials a consumer combines: nblk, or 1 after a fold kernel
-    int foff;               // where they start, in values of nv: 0, or nblk (the fold output)
+    int foff;               // where they start, in values of nv: 0, or the fold output slot
     int nblk_w, cpb_w;
     int block_map;          // 0 identity, 1 one slab per XCD, 2 slabs entered at staggered points
+    int tiled;              // stencil kernels stage kTileX x kTileY tiles with halo in LDS
+    int ntx;                // tiles along x
+    int nblk_t;             // tiled kernels: blocks (one tile each)
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z
     double Tk[3];           // A / distance between centres, per unit K
@@ -166,11 +174,13 @@ hipError_t launch_operator(const Geo &g, const Arrays &a, const double *x, doubl
                            hipStream_t s);
 hipError_t launch_precond(const Geo &g, const Arrays &a, int precond, const double *r, double *z,
                           hipStream_t s);
-// Folds nblk partials of nv values (max where bit i of maxmask is set) into
-// the slot after them, P[nblk*nv ..], when g.np == 1; no-op otherwise.  The
-// fold reads only block partials, so folding again after a producer that
-// returned early gives the same total.
-hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s);
+// Folds the nprod (default g.nblk) partials of nv values (max where bit i of
+// maxmask is set) of the last producer into the slot P[g.foff*nv ..] when
+// consumers read a folded total (g.np == 1, g.foff > 0); no-op otherwise.
+// The fold reads only block partials, so folding again after a producer
+// that returned early gives the same total.
+hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s,
+                       int nprod = -1);
 hipError_t launch_copy_active(const Geo &g, const Arrays &a, const double *src, double *dst,
                               hipStream_t s);
 

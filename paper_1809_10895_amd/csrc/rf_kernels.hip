@@ -186,6 +186,25 @@ __device__ __forceinline__ void lateral(const Geo &g, const int32_t *__restrict_
     }
 }
 
+// Tiles of the tiled stencil kernels: block b owns the kTileX x kTileY
+// columns of tile (b % ntx, b / ntx); with its one-column halo they form a
+// (kTileX + 2) x (kTileY + 2) array of slots (the four corners unused),
+// slot (sx, sy) = sx + kSlotX sy.
+constexpr int kSlotX = kTileX + 2, kSlotY = kTileY + 2, kSlots = kSlotX * kSlotY;
+constexpr int kSlotsPerWave = (kSlots + kWavesPerBlock - 1) / kWavesPerBlock;
+static_assert(kTileX == kWavesPerBlock, "one tile row along x per wave");
+
+// Column of slot sl of the tile whose slot (0, 0) is the grid column
+// (i0, j0), or -1 (a corner, or outside the grid).
+__device__ __forceinline__ int slot_column(const Geo &g, int i0, int j0, int sl)
+{
+    const int sx = sl % kSlotX, sy = sl / kSlotX;
+    const int gi = i0 + sx, gj = j0 + sy;
+    const bool corner = (sx == 0 || sx == kSlotX - 1) && (sy == 0 || sy == kSlotY - 1);
+    const bool in = sl < kSlots && !corner && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+    return in ? gi + g.nx * gj : -1;
+}
+
 __device__ __forceinline__ bool lead_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // Boundary terms of a cell with face f on the domain boundary, in terms of
@@ -588,6 +607,107 @@ __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 // Residual of the Picard system and PCG start
 // ---------------------------------------------------------------------------
 
+// One column of at most 64 cells (lane = k): the interior faces, the
+// residual r = b - A h^m of the increment system, diag, e = 0, the z-line
+// factors (refactor) and z = M^-1 r, and the block-partial contributions
+// v = (r.z, max|r/diag|).  Kp, hp, Dp, bp: K, h^m, Dd, bst of the lane's
+// cell; Kn, hn, nb: the lateral neighbours (-x, +x, -y, +y) and whether they
+// are active; tzs, rds: the stored z-line factors (used when !refactor).
+// Lanes at or above the active length kt only take part in the scans.
+template <int PRECOND, typename T>
+__device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, double *bout,
+                                             int refactor, bool act, int kt, size_t i, int lane,
+                                             double Kp, double hp, double Dp, double bp,
+                                             const double (&Kn)[4], const double (&hn)[4],
+                                             const bool (&nb)[4], double tzs, double rds,
+                                             double (&v)[2])
+{
+    constexpr bool kCopyKD = !std::is_same<T, double>::value;
+    const double gz[2] = {gdot(g, 4), gdot(g, 5)};
+    const double Kd = from_below(Kp, 0.0), hd = from_below(hp, 0.0);
+    const double Ku = from_above(Kp, 0.0), hu = from_above(hp, 0.0);
+    double diag = act ? Dp : 1.0, Ap = Dp * hp, b = bp, tup = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+        if (!nb[d]) continue;
+        const double Kf = 0.5 * (Kp + Kn[d]);
+        const double Tf = g.Tk[d >> 1] * Kf;
+        diag += Tf;
+        Ap += Tf * (hp - hn[d]);
+        b += g.A[d >> 1] * Kf * gdot(g, d);
+    }
+    if (act && lane > 0) {
+        const double Kf = 0.5 * (Kp + Kd);
+        const double Tf = g.Tk[2] * Kf;
+        diag += Tf;
+        Ap += Tf * (hp - hd);
+        b += g.A[2] * Kf * gz[0];
+    }
+    if (act && lane + 1 < kt) {
+        const double Kf = 0.5 * (Kp + Ku);
+        tup = g.Tk[2] * Kf;
+        diag += tup;
+        Ap += tup * (hp - hu);
+        b += g.A[2] * Kf * gz[1];
+    }
+    const double r = act ? b - Ap : 0.0;
+    const T rs = (T)r, ds = (T)diag;
+    if (act) {
+        if (bout) bout[i] = b;
+        cv.r[i] = rs;
+        cv.e[i] = T(0);
+        cv.diag[i] = ds;
+        if (kCopyKD) {
+            cv.K[i] = (T)Kp;
+            cv.Dd[i] = (T)Dp;
+        }
+        v[1] = fmax(v[1], fabs(r / diag));
+        if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
+    }
+    if (PRECOND == RF_PRECOND_ZLINE) {
+        // factors of this iteration's column tridiagonal, or the stored ones
+        // of the step's first iteration
+        double tzv, rdp;
+        if (refactor) {
+            const double tprev = from_below(tup, 0.0);
+            const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
+            tzv = tup;
+            rdp = act ? 1.0 / dpiv : 0.0;
+        } else {
+            tzv = act ? tzs : 0.0;
+            rdp = act ? rds : 0.0;
+        }
+        const double tprev = from_below(tzv, 0.0);
+        const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
+        const double zk = scan_affine_down<double>(tzv * rdp, wk, 0.0, lane);
+        if (act) {
+            const T zs = (T)zk;
+            if (refactor) {
+                cv.tz[i] = (T)tup;
+                cv.rdp[i] = (T)rdp;
+            }
+            cv.z[i] = zs;
+            v[0] += (double)rs * (double)zs;
+        }
+    }
+}
+
+// The residual kernel's PCG start (every kernel of the solve reads them):
+// written by the lead thread only.
+__device__ __forceinline__ void resid_reset_scalars(Scalars *s, int m)
+{
+    s->rho[0] = 0.0;
+    s->rho[1] = 1.0;
+    s->resmax = 0.0;
+    s->pq = 0.0;
+    s->iters = 0;
+    s->jcur = 0;
+    s->done = 0;
+    s->fail = 0;
+    s->final_iters = 0;
+    s->cur_m = m;
+}
+
 // Adds the interior faces: diag = Dd + sum T_f, b = bst + sum A_f K_f g.n_f
 // with K_f = (K_P + K_N)/2 and T_f = A_f K_f / d_f; r = b - A h^m (the
 // right-hand side of the increment system A e = r, e0 = 0); e = 0.
@@ -612,7 +732,6 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
         // short columns: gather K and h^m at the cell and its lateral
         // neighbours for G2 columns; vertical neighbours from adjacent lanes
         constexpr int G2 = 2;
-        const double gz[2] = {gdot(g, 4), gdot(g, 5)};
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
             ColSlot cs[G2];
             bool nb[G2][4];
@@ -642,77 +761,10 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                 }
             }
 #pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const bool act = cs[u].act;
-                const int kt = cs[u].kt;
-                const size_t i = cs[u].i;
-                const double Kd = from_below(Kp[u], 0.0), hd = from_below(hp[u], 0.0);
-                const double Ku = from_above(Kp[u], 0.0), hu = from_above(hp[u], 0.0);
-                double diag = act ? Dp[u] : 1.0, Ap = Dp[u] * hp[u], b = bp[u], tup = 0.0;
-#pragma unroll
-                for (int d = 0; d < 4; d++) {
-                    if (!nb[u][d]) continue;
-                    const double Kf = 0.5 * (Kp[u] + Kn[u][d]);
-                    const double Tf = g.Tk[d >> 1] * Kf;
-                    diag += Tf;
-                    Ap += Tf * (hp[u] - hn[u][d]);
-                    b += g.A[d >> 1] * Kf * gdot(g, d);
-                }
-                if (act && lane > 0) {
-                    const double Kf = 0.5 * (Kp[u] + Kd);
-                    const double Tf = g.Tk[2] * Kf;
-                    diag += Tf;
-                    Ap += Tf * (hp[u] - hd);
-                    b += g.A[2] * Kf * gz[0];
-                }
-                if (act && lane + 1 < kt) {
-                    const double Kf = 0.5 * (Kp[u] + Ku);
-                    tup = g.Tk[2] * Kf;
-                    diag += tup;
-                    Ap += tup * (hp[u] - hu);
-                    b += g.A[2] * Kf * gz[1];
-                }
-                const double r = act ? b - Ap : 0.0;
-                const T rs = (T)r, ds = (T)diag;
-                if (act) {
-                    if (bout) bout[i] = b;
-                    cv.r[i] = rs;
-                    cv.e[i] = T(0);
-                    cv.diag[i] = ds;
-                    if (kCopyKD) {
-                        cv.K[i] = (T)Kp[u];
-                        cv.Dd[i] = (T)Dp[u];
-                    }
-                    v[1] = fmax(v[1], fabs(r / diag));
-                    if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
-                }
-                if (PRECOND == RF_PRECOND_ZLINE) {
-                    // factors of this iteration's column tridiagonal, or the
-                    // stored ones of the step's first iteration
-                    double tzv, rdp;
-                    if (refactor) {
-                        const double tprev = from_below(tup, 0.0);
-                        const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
-                        tzv = tup;
-                        rdp = act ? 1.0 / dpiv : 0.0;
-                    } else {
-                        tzv = act ? tzs[u] : 0.0;
-                        rdp = act ? rds[u] : 0.0;
-                    }
-                    const double tprev = from_below(tzv, 0.0);
-                    const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
-                    const double zk = scan_affine_down<double>(tzv * rdp, wk, 0.0, lane);
-                    if (act) {
-                        const T zs = (T)zk;
-                        if (refactor) {
-                            cv.tz[i] = (T)tup;
-                            cv.rdp[i] = (T)rdp;
-                        }
-                        cv.z[i] = zs;
-                        v[0] += (double)rs * (double)zs;
-                    }
-                }
-            }
+            for (int u = 0; u < G2; u++)
+                resid_column<PRECOND, T>(g, cv, bout, refactor, cs[u].act, cs[u].kt, cs[u].i, lane,
+                                         Kp[u], hp[u], Dp[u], bp[u], Kn[u], hn[u], nb[u], tzs[u],
+                                         rds[u], v);
         }
     } else
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
@@ -812,18 +864,99 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
         }
     }
     block_partial<2, 2u>(v, a.pr);
-    if (lead_thread()) {
-        s->rho[0] = 0.0;
-        s->rho[1] = 1.0;
-        s->resmax = 0.0;
-        s->pq = 0.0;
-        s->iters = 0;
-        s->jcur = 0;
-        s->done = 0;
-        s->fail = 0;
-        s->final_iters = 0;
-        s->cur_m = m;
+    if (lead_thread()) resid_reset_scalars(s, m);
+}
+
+// The residual kernel with the lateral neighbours staged in LDS (columns of
+// at most one wave; the tile layout of k_spmv_tile): every wave reads K and
+// h^m of its share of the tile's slots (masked by their active lengths, read
+// first) and Dd, bst of its own columns, stages K and h^m in LDS, then forms
+// each of its kTileY interior columns with resid_column, whose arithmetic is
+// that of k_resid.  Writes the (r.z, max|r/diag|) block partials of nblk_t
+// blocks into pr.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_resid_tile(Geo g, Arrays a, CgVec<T> cv, int m,
+                                                         double *bout, int refactor)
+{
+    Scalars *s = a.sc;
+    if (s->fail || s->stall || s->picard_done) return;
+    __shared__ double sH[kSlots][kWave];
+    __shared__ double sK[kSlots][kWave];
+    __shared__ int sKt[kSlots];
+    const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
+    RF_WAVE_IDS;
+    const int i0 = (int)(blockIdx.x % g.ntx) * kTileX - 1;
+    const int j0 = (int)(blockIdx.x / g.ntx) * kTileY - 1;
+    int col[kSlotsPerWave], kt[kSlotsPerWave], oc[kTileY], okt[kTileY];
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        col[u] = slot_column(g, i0, j0, w + u * kWavesPerBlock);
+        kt[u] = (col[u] >= 0) ? a.ktop[col[u]] : 0;
     }
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        oc[t] = slot_column(g, i0, j0, (w + 1) + kSlotX * (t + 1));
+        okt[t] = (oc[t] >= 0) ? a.ktop[oc[t]] : 0;
+    }
+    double K[kSlotsPerWave], h[kSlotsPerWave], Dp[kTileY], bp[kTileY], tzs[kTileY], rds[kTileY];
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        K[u] = 0.0;
+        h[u] = 0.0;
+        if (lane < kt[u]) {
+            const size_t i = (size_t)col[u] * g.nz + lane;
+            K[u] = a.K[i];
+            h[u] = hmv[i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        Dp[t] = 0.0;
+        bp[t] = 0.0;
+        tzs[t] = 0.0;
+        rds[t] = 0.0;
+        if (lane < okt[t]) {
+            const size_t i = (size_t)oc[t] * g.nz + lane;
+            Dp[t] = a.Dd[i];
+            bp[t] = a.bst[i];
+            if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
+                tzs[t] = (double)cv.tz[i];
+                rds[t] = (double)cv.rdp[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        const int sl = w + u * kWavesPerBlock;
+        if (sl >= kSlots) continue;
+        if (lane < kt[u]) {
+            sK[sl][lane] = K[u];
+            sH[sl][lane] = h[u];
+        }
+        if (lane == 0) sKt[sl] = kt[u];
+    }
+    __syncthreads();
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        const int c = (w + 1) + kSlotX * (t + 1);
+        const int nbs[4] = {c - 1, c + 1, c - kSlotX, c + kSlotX};   // -x, +x, -y, +y
+        const bool act = lane < okt[t];
+        const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
+        double Kn[4], hn[4];
+        bool nb[4];
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            nb[d] = act && lane < sKt[nbs[d]];
+            Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
+            hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
+        }
+        const size_t i = (size_t)(oc[t] >= 0 ? oc[t] : 0) * g.nz + lane;
+        resid_column<PRECOND, T>(g, cv, bout, refactor, act, okt[t], i, lane, Kp, hp, Dp[t], bp[t],
+                                 Kn, hn, nb, tzs[t], rds[t], v);
+    }
+    block_partial<2, 2u>(v, a.pr);
+    if (lead_thread()) resid_reset_scalars(s, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -990,6 +1123,107 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
             }
             p_out[c.idx] = pp;
             cv.q[c.idx] = q;
+            v[0] += (double)pp * (double)q;
+        }
+    }
+    block_partial<1, 0u>(v, a.pq);
+}
+
+// The same PCG step with the lateral neighbours staged in LDS (columns of at
+// most one wave).  Block b owns the tile of kTileX x kTileY columns at tile
+// (b % ntx, b / ntx); the tile and its one-column halo (a ring of
+// (kTileX + 2) x (kTileY + 2) slots without the corners) are read once into
+// LDS as p_new = z + beta p_old and K, every wave reading a share of the slots
+// with the loads of all its slots in flight together.  Each column's active
+// length k_top is read first (scalar loads), so that no lane above it loads
+// anything.  Wave w then forms q = A p for the kTileY interior columns at
+// x = w, reading its neighbours from LDS; the arithmetic per cell is that of
+// k_spmv.  Writes p, q and the block partials of p.q (nblk_t blocks).
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv_tile(Geo g, Arrays a, CgVec<T> cv, int parity,
+                                                        double tol_cg, double rel, int max_cg)
+{
+    Scalars *s = a.sc;
+    if (s->done || s->fail || s->stall || s->picard_done) return;
+    __shared__ T sP[kSlots][kWave];
+    __shared__ T sK[kSlots][kWave];
+    __shared__ int sKt[kSlots];
+    const int j = s->iters;
+    const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
+    T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
+    const bool first = (j == 0);
+    RF_WAVE_IDS;
+    const int i0 = (int)(blockIdx.x % g.ntx) * kTileX - 1;
+    const int j0 = (int)(blockIdx.x / g.ntx) * kTileY - 1;
+    // active lengths first: of this wave's slots and of its own columns
+    int col[kSlotsPerWave], kt[kSlotsPerWave], oc[kTileY], okt[kTileY];
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        col[u] = slot_column(g, i0, j0, w + u * kWavesPerBlock);
+        kt[u] = (col[u] >= 0) ? a.ktop[col[u]] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        oc[t] = slot_column(g, i0, j0, (w + 1) + kSlotX * (t + 1));
+        okt[t] = (oc[t] >= 0) ? a.ktop[oc[t]] : 0;
+    }
+    // every load of the wave, masked by the active lengths
+    T z[kSlotsPerWave], po[kSlotsPerWave], K[kSlotsPerWave], Dd[kTileY];
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        z[u] = T(0);
+        po[u] = T(0);
+        K[u] = T(0);
+        if (lane < kt[u]) {
+            const size_t i = (size_t)col[u] * g.nz + lane;
+            z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
+            po[u] = p_in[i];
+            K[u] = cv.K[i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        Dd[t] = T(0);
+        if (lane < okt[t]) Dd[t] = cv.Dd[(size_t)oc[t] * g.nz + lane];
+    }
+    double rho;
+    if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
+    const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
+#pragma unroll
+    for (int u = 0; u < kSlotsPerWave; u++) {
+        const int sl = w + u * kWavesPerBlock;
+        if (sl >= kSlots) continue;
+        if (lane < kt[u]) {
+            sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
+            sK[sl][lane] = K[u];
+        }
+        if (lane == 0) sKt[sl] = kt[u];
+    }
+    __syncthreads();
+    const T tz2 = (T)(0.5 * g.Tk[2]);
+    const T tx2[2] = {(T)(0.5 * g.Tk[0]), (T)(0.5 * g.Tk[1])};
+    double v[1] = {0.0};
+#pragma unroll
+    for (int t = 0; t < kTileY; t++) {
+        const int c = (w + 1) + kSlotX * (t + 1);
+        const int nbs[4] = {c - 1, c + 1, c - kSlotX, c + kSlotX};   // -x, +x, -y, +y
+        const bool act = lane < okt[t];
+        const T pp = act ? sP[c][lane] : T(0);
+        const T Kp = act ? sK[c][lane] : T(0);
+        const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
+        const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
+        T q = Dd[t] * pp;
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            const bool nb = act && lane < sKt[nbs[d]];
+            if (nb) q += tx2[d >> 1] * (Kp + sK[nbs[d]][lane]) * (pp - sP[nbs[d]][lane]);
+        }
+        if (act && lane > 0) q += tz2 * (Kp + Kd) * (pp - pdn);
+        if (act && lane + 1 < okt[t]) q += tz2 * (Kp + Ku) * (pp - pup);
+        if (act) {
+            const size_t i = (size_t)oc[t] * g.nz + lane;
+            p_out[i] = pp;
+            cv.q[i] = q;
             v[0] += (double)pp * (double)q;
         }
     }
@@ -1432,14 +1666,15 @@ __global__ void __launch_bounds__(kThreads) k_copy_active(Geo g, Arrays a, const
     }
 }
 
+// Combines the nblk partials of a producer into slot `out` (in values of NV).
 template <int NV, unsigned MAXMASK>
-__global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk)
+__global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk, int out)
 {
     double tot[NV];
     reduce_partials<NV, MAXMASK>(P, nblk, tot);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int i = 0; i < NV; i++) P[(size_t)nblk * NV + i] = tot[i];
+        for (int i = 0; i < NV; i++) P[(size_t)out * NV + i] = tot[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1494,6 +1729,14 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
         return launch_fold(g, P, nv, mask, s);                                          \
     } while (0)
 
+// A tiled kernel (nblk_t blocks) and the fold of its partials.
+#define RF_LAUNCH_TILED(P, nv, mask, kern, ...)                                         \
+    do {                                                                                \
+        const hipError_t e_ = [&]() { RF_LAUNCH_N(g.nblk_t, kern, __VA_ARGS__); }();      \
+        if (e_ != hipSuccess) return e_;                                                \
+        return launch_fold(g, P, nv, mask, s, g.nblk_t);                                \
+    } while (0)
+
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s)
 {
     RF_LAUNCH_FOLD(a.ps, 1, 0u, k_check_finite, g, a, h);
@@ -1535,6 +1778,18 @@ hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, doubl
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
     const int rf = refactor ? 1 : 0;
+    if (g.tiled) {
+        if (mixed && zl)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
+        if (mixed)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout,
+                            rf);
+        if (zl)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m,
+                            bout, rf);
+        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m,
+                        bout, rf);
+    }
     if (mixed && zl)
         RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
     if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout, rf);
@@ -1546,6 +1801,19 @@ hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, i
                        const CgTol &t, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
+    if (g.tiled) {
+        if (mixed && zl)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, float>), g, a, a.f, parity,
+                            t.tol_cg, t.rel, t.max_cg);
+        if (mixed)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, float>), g, a, a.f, parity,
+                            t.tol_cg, t.rel, t.max_cg);
+        if (zl)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, double>), g, a, dvec(a),
+                            parity, t.tol_cg, t.rel, t.max_cg);
+        RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity,
+                        t.tol_cg, t.rel, t.max_cg);
+    }
     if (mixed && zl)
         RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_ZLINE, float>), g, a, a.f, parity, t.tol_cg,
                        t.rel, t.max_cg);
@@ -1605,14 +1873,15 @@ hipError_t launch_precond(const Geo &g, const Arrays &a, int precond, const doub
     RF_LAUNCH_W(k_precond<RF_PRECOND_JACOBI>, g, a, r, z);
 }
 
-hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s)
+hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStream_t s, int nprod)
 {
-    if (g.np != 1 || g.nblk == 1) return hipSuccess;
+    if (nprod < 0) nprod = g.nblk;
+    if (g.np != 1 || g.foff == 0) return hipSuccess;   // partials read as written
     switch (nv * 16 + (int)maxmask) {
-    case 1 * 16 + 0: RF_LAUNCH_N(1, (k_fold<1, 0u>), P, g.nblk);
-    case 2 * 16 + 1: RF_LAUNCH_N(1, (k_fold<2, 1u>), P, g.nblk);
-    case 2 * 16 + 2: RF_LAUNCH_N(1, (k_fold<2, 2u>), P, g.nblk);
-    case 7 * 16 + 0: RF_LAUNCH_N(1, (k_fold<7, 0u>), P, g.nblk);
+    case 1 * 16 + 0: RF_LAUNCH_N(1, (k_fold<1, 0u>), P, nprod, g.foff);
+    case 2 * 16 + 1: RF_LAUNCH_N(1, (k_fold<2, 1u>), P, nprod, g.foff);
+    case 2 * 16 + 2: RF_LAUNCH_N(1, (k_fold<2, 2u>), P, nprod, g.foff);
+    case 7 * 16 + 0: RF_LAUNCH_N(1, (k_fold<7, 0u>), P, nprod, g.foff);
     default: return hipErrorInvalidValue;
     }
 }

@@ -54,9 +54,10 @@ def test_soil_functions_match_oracle(orc):
         assert err.max() <= 1e-13, err.max()
 
 
+@pytest.mark.parametrize("nz", [70, 48])   # 48: the LDS-tiled stencil kernels
 @pytest.mark.parametrize("precond", [0, 1])
-def test_assembly_operator_preconditioner_match_oracle(orc, precond):
-    w, rng = small_3d(seed=1)
+def test_assembly_operator_preconditioner_match_oracle(orc, precond, nz):
+    w, rng = small_3d(seed=1, nz=nz)
     P = make_oracle(orc, w)
     S = make_solver(w, precond=precond)
     hm = w.h0 + rng.normal(0, 0.02, w.N)
@@ -147,9 +148,10 @@ def test_column100_steps_match_oracle(orc, precond):
     assert np.allclose(mb_g["inflow"], mb_o["inflow"], rtol=1e-8, atol=1e-15)
 
 
+@pytest.mark.parametrize("nz", [70, 48])   # 48: the LDS-tiled stencil kernels
 @pytest.mark.parametrize("precond", [0, 1])
-def test_small_3d_mixed_bcs_steps_match_oracle(orc, precond):
-    w, _ = small_3d(seed=2)
+def test_small_3d_mixed_bcs_steps_match_oracle(orc, precond, nz):
+    w, _ = small_3d(seed=2, nz=nz)
     w.h0 = np.where(w.active_mask(), -1.0, 0.0)
     w.bcs[4] = (W.ZMIN, W.DIRICHLET, -0.2)
     P = make_oracle(orc, w)
