@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--stencil", default="tiles", choices=["tiles", "columns"],
                     help="how the stencil kernels reach lateral neighbours (LDS tiles or "
                          "per-wave neighbour columns)")
+    ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 2, 4],
+                    help="columns of a stencil tile along y (0 = chosen by the library)")
     ap.add_argument("--cols-per-wave", type=int, default=0,
                     help="launch shape of the PCG kernels (0 = chosen from the grid size)")
     return ap.parse_args()
@@ -220,7 +222,7 @@ def timed_case(args, w, precision):
         S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=w.dt,
                       dt_max=w.dt_max, ebats=int(w.ebats), cols_per_wave=args.cols_per_wave,
                       precision=PRECISION[precision], cg_rel_tol=args.cg_rel_tol,
-                      stencil=STENCIL[args.stencil])
+                      stencil=STENCIL[args.stencil], tile_rows=args.tile_rows)
         S.bind()
         assert S.set_state(h0) == 0, S.last_error()
         return S
@@ -342,7 +344,8 @@ def ebats_day(args, w, days, dt0):
         W.configure(w, S)
         S.set_options(tol_picard=1e-6, tol_cg=1e-8, max_picard=50, precond=pc, dt0=dt0,
                       dt_max=w.dt_max, ebats=1, precision=prec, first_iterate=fi,
-                      cols_per_wave=args.cols_per_wave, stencil=STENCIL[args.stencil])
+                      cols_per_wave=args.cols_per_wave, stencil=STENCIL[args.stencil],
+                      tile_rows=args.tile_rows)
         S.bind()
         assert S.set_state(h0) == 0, S.last_error()
         torch.cuda.synchronize()
@@ -483,7 +486,7 @@ def main():
                    "dt0_s": w.dt, "dt_max_s": w.dt_max if w.ebats else w.dt,
                    "ebats": bool(w.ebats), "tol_picard_m": 1e-6, "tol_cg_m": 1e-8,
                    "cg_rel_tol": args.cg_rel_tol, "precision": args.precision,
-                   "precond": args.precond, "stencil": args.stencil,
+                   "precond": args.precond, "stencil": args.stencil, "tile_rows": args.tile_rows,
                    "cols_per_wave": args.cols_per_wave,
                    "driver": "rf_run_steps" if args.driver == "run" else "rf_step per step",
                    "picard_per_step": main_r["picard_per_step"],

@@ -60,7 +60,7 @@ class RfOptions(C.Structure):
                 ("few_iters", C.c_int), ("max_iters", C.c_int), ("factor", C.c_double),
                 ("cols_per_wave", C.c_int), ("precision", C.c_int), ("cg_rel_tol", C.c_double),
                 ("picard_variant", C.c_int), ("first_iterate", C.c_int), ("zline_refactor", C.c_int),
-                ("host_wait", C.c_int), ("stencil", C.c_int)]
+                ("host_wait", C.c_int), ("stencil", C.c_int), ("tile_rows", C.c_int)]
 
 
 class RfStepStats(C.Structure):

@@ -16,7 +16,7 @@ constexpr int kThreads = kWave * kWavesPerBlock;
 constexpr int kPartialsMax = 512;   // partials every block of a consumer kernel may combine
 constexpr int kRedSlots = 8;        // values per block partial
 constexpr int kTileX = 8;           // tiled stencil kernels: interior columns of a tile along x
-constexpr int kTileY = 4;           // ... and along y (kTileX * kTileY / kWavesPerBlock per wave)
+                                    // (one per wave); along y: Geo::tile_y (2 or 4)
 
 // Per-layer van Genuchten parameters (Ks is per cell).
 struct Layer {
@@ -45,8 +45,9 @@ struct Geo {
     int nblk_w, cpb_w;
     int block_map;          // 0 identity, 1 one slab per XCD, 2 slabs entered at staggered points
     int tiled;              // stencil kernels stage kTileX x kTileY tiles with halo in LDS
-    int ntx;                // tiles along x
-    int nblk_t;             // tiled kernels: blocks (one tile each)
+    int tile_y;             // interior columns of a tile along y (2 or 4)
+    int ntx, ntiles;        // tiles along x, tiles of the grid
+    int nblk_t, tpb;        // tiled kernels: blocks, and tiles walked by each block
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z
     double Tk[3];           // A / distance between centres, per unit K

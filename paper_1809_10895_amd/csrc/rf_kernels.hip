@@ -101,14 +101,12 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double *out)
     }
 }
 
-// Combines the nblk block partials written by the previous kernel, in the
-// same fixed order in every block; all threads receive the totals.
+// First half of reduce_partials: this thread's share of the nblk block
+// partials (blocks threadIdx.x, + kThreads, ...), so that their loads can be
+// issued early and combined later with combine_partials.
 template <int NV, unsigned MAXMASK>
-__device__ __forceinline__ void reduce_partials(const double *P, int nblk, double (&tot)[NV])
+__device__ __forceinline__ void gather_partials(const double *P, int nblk, double (&v)[NV])
 {
-    __shared__ double sh[kWavesPerBlock][NV];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    double v[NV];
 #pragma unroll
     for (int i = 0; i < NV; i++) v[i] = 0.0;   // identity of sums and of max over |x|
     for (int b = threadIdx.x; b < nblk; b += kThreads)
@@ -117,6 +115,39 @@ __device__ __forceinline__ void reduce_partials(const double *P, int nblk, doubl
             const double x = P[(size_t)b * NV + i];
             v[i] = ((MAXMASK >> i) & 1u) ? fmax(v[i], x) : v[i] + x;
         }
+}
+
+// Second half: the gathered shares combined over the block in a fixed order;
+// all threads receive the totals.  Call from every thread.
+template <int NV, unsigned MAXMASK>
+__device__ __forceinline__ void combine_partials(double (&v)[NV], double (&tot)[NV])
+{
+    __shared__ double sh[kWavesPerBlock][NV];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < NV; i++) v[i] = ((MAXMASK >> i) & 1u) ? wave_max(v[i]) : wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; i++) sh[w][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+        double a = sh[0][i];
+        for (int ww = 1; ww < kWavesPerBlock; ww++)
+            a = ((MAXMASK >> i) & 1u) ? fmax(a, sh[ww][i]) : a + sh[ww][i];
+        tot[i] = a;
+    }
+}
+
+// Combines the nblk block partials written by the previous kernel, in the
+// same fixed order in every block; all threads receive the totals.
+template <int NV, unsigned MAXMASK>
+__device__ __forceinline__ void reduce_partials(const double *P, int nblk, double (&tot)[NV])
+{
+    __shared__ double sh[kWavesPerBlock][NV];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double v[NV];
+    gather_partials<NV, MAXMASK>(P, nblk, v);
 #pragma unroll
     for (int i = 0; i < NV; i++) v[i] = ((MAXMASK >> i) & 1u) ? wave_max(v[i]) : wave_sum(v[i]);
     if (lane == 0)
@@ -186,23 +217,65 @@ __device__ __forceinline__ void lateral(const Geo &g, const int32_t *__restrict_
     }
 }
 
-// Tiles of the tiled stencil kernels: block b owns the kTileX x kTileY
-// columns of tile (b % ntx, b / ntx); with its one-column halo they form a
-// (kTileX + 2) x (kTileY + 2) array of slots (the four corners unused),
-// slot (sx, sy) = sx + kSlotX sy.
-constexpr int kSlotX = kTileX + 2, kSlotY = kTileY + 2, kSlots = kSlotX * kSlotY;
-constexpr int kSlotsPerWave = (kSlots + kWavesPerBlock - 1) / kWavesPerBlock;
-static_assert(kTileX == kWavesPerBlock, "one tile row along x per wave");
+// Tiles of the tiled stencil kernels: block b owns the kTileX x TY columns
+// of tile (b % ntx, b / ntx); with its one-column halo they form a
+// (kTileX + 2) x (TY + 2) array of slots (the four corners unused), slot
+// (sx, sy) = sx + SX sy.  Wave w owns the TY interior columns at sx = w + 1.
+template <int TY>
+struct Tile {
+    static constexpr int SX = kTileX + 2, SY = TY + 2, NS = SX * SY;
+    static constexpr int PER = (NS + kWavesPerBlock - 1) / kWavesPerBlock;   // slots per wave
+    static_assert(kTileX == kWavesPerBlock, "one tile row along x per wave");
 
-// Column of slot sl of the tile whose slot (0, 0) is the grid column
-// (i0, j0), or -1 (a corner, or outside the grid).
-__device__ __forceinline__ int slot_column(const Geo &g, int i0, int j0, int sl)
+    // Column of slot sl of the tile whose slot (0, 0) is the grid column
+    // (i0, j0), or -1 (a corner, or outside the grid).
+    __device__ static __forceinline__ int column(const Geo &g, int i0, int j0, int sl)
+    {
+        const int sx = sl % SX, sy = sl / SX;
+        const int gi = i0 + sx, gj = j0 + sy;
+        const bool corner = (sx == 0 || sx == SX - 1) && (sy == 0 || sy == SY - 1);
+        const bool in = sl < NS && !corner && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+        return in ? gi + g.nx * gj : -1;
+    }
+    // slot of wave w's interior column t
+    __device__ static __forceinline__ int own(int w, int t) { return (w + 1) + SX * (t + 1); }
+};
+
+// The columns and active lengths one wave needs for tile `tile` (-1: none):
+// its share of the slots (w, w + 8, ...) and its own TY interior columns.
+// The active lengths are scalar loads, issued together.
+template <int TY>
+struct TileCols {
+    int col[Tile<TY>::PER], kt[Tile<TY>::PER], oc[TY], okt[TY];
+
+    __device__ __forceinline__ void fetch(const Geo &g, const int32_t *__restrict__ ktop, int tile,
+                                          int w)
+    {
+        using Tl = Tile<TY>;
+        const int i0 = (tile % g.ntx) * kTileX - 1, j0 = (tile / g.ntx) * TY - 1;
+#pragma unroll
+        for (int u = 0; u < Tl::PER; u++) {
+            col[u] = (tile >= 0) ? Tl::column(g, i0, j0, w + u * kWavesPerBlock) : -1;
+            kt[u] = (col[u] >= 0) ? ktop[col[u]] : 0;
+        }
+#pragma unroll
+        for (int t = 0; t < TY; t++) {
+            oc[t] = (tile >= 0) ? Tl::column(g, i0, j0, Tl::own(w, t)) : -1;
+            okt[t] = (oc[t] >= 0) ? ktop[oc[t]] : 0;
+        }
+    }
+};
+
+// Tiles [tb, te) of this block: a contiguous run of tpb tiles per logical
+// block.  When the grid is a multiple of 8, logical blocks are dealt so that
+// each XCD (hardware block b runs on XCD b % 8) owns one contiguous range of
+// tiles, whose y-halos then mostly sit in its own L2.
+__device__ __forceinline__ void tile_range(const Geo &g, int &tb, int &te)
 {
-    const int sx = sl % kSlotX, sy = sl / kSlotX;
-    const int gi = i0 + sx, gj = j0 + sy;
-    const bool corner = (sx == 0 || sx == kSlotX - 1) && (sy == 0 || sy == kSlotY - 1);
-    const bool in = sl < kSlots && !corner && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-    return in ? gi + g.nx * gj : -1;
+    const int b = blockIdx.x, G = gridDim.x;
+    const int lb = ((G & 7) == 0 && G >= 8) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+    tb = lb * g.tpb;
+    te = min(tb + g.tpb, g.ntiles);
 }
 
 __device__ __forceinline__ bool lead_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -868,92 +941,113 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
 }
 
 // The residual kernel with the lateral neighbours staged in LDS (columns of
-// at most one wave; the tile layout of k_spmv_tile): every wave reads K and
-// h^m of its share of the tile's slots (masked by their active lengths, read
-// first) and Dd, bst of its own columns, stages K and h^m in LDS, then forms
-// each of its kTileY interior columns with resid_column, whose arithmetic is
-// that of k_resid.  Writes the (r.z, max|r/diag|) block partials of nblk_t
-// blocks into pr.
-template <int PRECOND, typename T>
+// at most one wave; the tile layout of Tile<TY>).  Each block walks its run
+// of tiles (tile_range); for every tile the waves read K and h^m of their
+// share of the slots and Dd, bst of their own columns (masked by the active
+// lengths), stage K and h^m in LDS, and form each of their TY interior
+// columns with resid_column, whose arithmetic is that of k_resid.  The next
+// tile's loads are in flight while the current one is computed, and its
+// active lengths were fetched one tile earlier still; the step flags are read
+// with the first tile's active lengths, so that a launch past the end of the
+// step stops after one round trip.  Writes the (r.z, max|r/diag|) block
+// partials of nblk_t blocks into pr.
+template <int PRECOND, typename T, int TY>
 __global__ void __launch_bounds__(kThreads) k_resid_tile(Geo g, Arrays a, CgVec<T> cv, int m,
                                                          double *bout, int refactor)
 {
+    using Tl = Tile<TY>;
     Scalars *s = a.sc;
-    if (s->fail || s->stall || s->picard_done) return;
-    __shared__ double sH[kSlots][kWave];
-    __shared__ double sK[kSlots][kWave];
-    __shared__ int sKt[kSlots];
+    const int stop = s->fail | s->stall | s->picard_done;
+    __shared__ double sH[Tl::NS][kWave];
+    __shared__ double sK[Tl::NS][kWave];
+    __shared__ int sKt[Tl::NS];
     const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     RF_WAVE_IDS;
-    const int i0 = (int)(blockIdx.x % g.ntx) * kTileX - 1;
-    const int j0 = (int)(blockIdx.x / g.ntx) * kTileY - 1;
-    int col[kSlotsPerWave], kt[kSlotsPerWave], oc[kTileY], okt[kTileY];
+    int tb, te;
+    tile_range(g, tb, te);
+    TileCols<TY> cur, nxt;
+    cur.fetch(g, a.ktop, tb < te ? tb : -1, w);
+    nxt.fetch(g, a.ktop, tb + 1 < te ? tb + 1 : -1, w);
+    if (stop) return;
+    double K[Tl::PER], h[Tl::PER], Dp[TY], bp[TY], tzs[TY], rds[TY];
+    auto load = [&](const TileCols<TY> &c) {
 #pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        col[u] = slot_column(g, i0, j0, w + u * kWavesPerBlock);
-        kt[u] = (col[u] >= 0) ? a.ktop[col[u]] : 0;
-    }
-#pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        oc[t] = slot_column(g, i0, j0, (w + 1) + kSlotX * (t + 1));
-        okt[t] = (oc[t] >= 0) ? a.ktop[oc[t]] : 0;
-    }
-    double K[kSlotsPerWave], h[kSlotsPerWave], Dp[kTileY], bp[kTileY], tzs[kTileY], rds[kTileY];
-#pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        K[u] = 0.0;
-        h[u] = 0.0;
-        if (lane < kt[u]) {
-            const size_t i = (size_t)col[u] * g.nz + lane;
-            K[u] = a.K[i];
-            h[u] = hmv[i];
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        Dp[t] = 0.0;
-        bp[t] = 0.0;
-        tzs[t] = 0.0;
-        rds[t] = 0.0;
-        if (lane < okt[t]) {
-            const size_t i = (size_t)oc[t] * g.nz + lane;
-            Dp[t] = a.Dd[i];
-            bp[t] = a.bst[i];
-            if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
-                tzs[t] = (double)cv.tz[i];
-                rds[t] = (double)cv.rdp[i];
+        for (int u = 0; u < Tl::PER; u++) {
+            K[u] = 0.0;
+            h[u] = 0.0;
+            if (lane < c.kt[u]) {
+                const size_t i = (size_t)c.col[u] * g.nz + lane;
+                K[u] = a.K[i];
+                h[u] = hmv[i];
             }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        const int sl = w + u * kWavesPerBlock;
-        if (sl >= kSlots) continue;
-        if (lane < kt[u]) {
-            sK[sl][lane] = K[u];
-            sH[sl][lane] = h[u];
+        for (int t = 0; t < TY; t++) {
+            Dp[t] = 0.0;
+            bp[t] = 0.0;
+            tzs[t] = 0.0;
+            rds[t] = 0.0;
+            if (lane < c.okt[t]) {
+                const size_t i = (size_t)c.oc[t] * g.nz + lane;
+                Dp[t] = a.Dd[i];
+                bp[t] = a.bst[i];
+                if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
+                    tzs[t] = (double)cv.tz[i];
+                    rds[t] = (double)cv.rdp[i];
+                }
+            }
         }
-        if (lane == 0) sKt[sl] = kt[u];
-    }
-    __syncthreads();
+    };
+    load(cur);
     double v[2] = {0.0, 0.0};
+    for (int tile = tb; tile < te; tile++) {
 #pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        const int c = (w + 1) + kSlotX * (t + 1);
-        const int nbs[4] = {c - 1, c + 1, c - kSlotX, c + kSlotX};   // -x, +x, -y, +y
-        const bool act = lane < okt[t];
-        const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
-        double Kn[4], hn[4];
-        bool nb[4];
-#pragma unroll
-        for (int d = 0; d < 4; d++) {
-            nb[d] = act && lane < sKt[nbs[d]];
-            Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
-            hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
+        for (int u = 0; u < Tl::PER; u++) {
+            const int sl = w + u * kWavesPerBlock;
+            if (sl >= Tl::NS) continue;
+            if (lane < cur.kt[u]) {
+                sK[sl][lane] = K[u];
+                sH[sl][lane] = h[u];
+            }
+            if (lane == 0) sKt[sl] = cur.kt[u];
         }
-        const size_t i = (size_t)(oc[t] >= 0 ? oc[t] : 0) * g.nz + lane;
-        resid_column<PRECOND, T>(g, cv, bout, refactor, act, okt[t], i, lane, Kp, hp, Dp[t], bp[t],
-                                 Kn, hn, nb, tzs[t], rds[t], v);
+        __syncthreads();
+        // this tile's own columns; then the next tile's loads go out
+        int oc[TY], okt[TY];
+        double Dc[TY], bc[TY], tzc[TY], rdc[TY];
+#pragma unroll
+        for (int t = 0; t < TY; t++) {
+            oc[t] = cur.oc[t];
+            okt[t] = cur.okt[t];
+            Dc[t] = Dp[t];
+            bc[t] = bp[t];
+            tzc[t] = tzs[t];
+            rdc[t] = rds[t];
+        }
+        if (tile + 1 < te) {
+            cur = nxt;
+            load(cur);
+            nxt.fetch(g, a.ktop, tile + 2 < te ? tile + 2 : -1, w);
+        }
+#pragma unroll
+        for (int t = 0; t < TY; t++) {
+            const int c = Tl::own(w, t);
+            const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
+            const bool act = lane < okt[t];
+            const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
+            double Kn[4], hn[4];
+            bool nb[4];
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                nb[d] = act && lane < sKt[nbs[d]];
+                Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
+                hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
+            }
+            const size_t i = (size_t)(oc[t] >= 0 ? oc[t] : 0) * g.nz + lane;
+            resid_column<PRECOND, T>(g, cv, bout, refactor, act, okt[t], i, lane, Kp, hp, Dc[t],
+                                     bc[t], Kn, hn, nb, tzc[t], rdc[t], v);
+        }
+        __syncthreads();
     }
     block_partial<2, 2u>(v, a.pr);
     if (lead_thread()) resid_reset_scalars(s, m);
@@ -1129,103 +1223,148 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
     block_partial<1, 0u>(v, a.pq);
 }
 
+// The exit decision of PCG iteration j from the combined (r.z, max|r/diag|)
+// totals, as spmv_continue takes it; tol_prev is the solve's tolerance read
+// from the scalars (used for j > 0).  Returns true when the solve goes on.
+__device__ __forceinline__ bool spmv_decide(Scalars *s, int j, const double (&tot)[2],
+                                            double tol_prev, double tol_cg, double rel, int max_cg)
+{
+    const double rho = tot[0], resmax = tot[1];
+    const double tol = (j == 0) ? fmax(tol_cg, rel * resmax) : tol_prev;
+    const bool bad = !isfinite(rho) || !isfinite(resmax);
+    const bool done = bad || resmax <= tol || j >= max_cg;
+    if (lead_thread()) {
+        s->rho[j & 1] = rho;
+        s->resmax = resmax;
+        s->jcur = j;
+        if (j == 0) s->tol_eff = tol;
+        if (done) {
+            s->done = 1;
+            s->final_iters = j;
+            if (bad) s->fail = 3;
+            else if (resmax > tol) s->fail = 2;
+        }
+    }
+    return !done;
+}
+
 // The same PCG step with the lateral neighbours staged in LDS (columns of at
-// most one wave).  Block b owns the tile of kTileX x kTileY columns at tile
-// (b % ntx, b / ntx); the tile and its one-column halo (a ring of
-// (kTileX + 2) x (kTileY + 2) slots without the corners) are read once into
-// LDS as p_new = z + beta p_old and K, every wave reading a share of the slots
-// with the loads of all its slots in flight together.  Each column's active
-// length k_top is read first (scalar loads), so that no lane above it loads
-// anything.  Wave w then forms q = A p for the kTileY interior columns at
-// x = w, reading its neighbours from LDS; the arithmetic per cell is that of
-// k_spmv.  Writes p, q and the block partials of p.q (nblk_t blocks).
-template <int PRECOND, typename T>
+// most one wave; the tile layout of Tile<TY>).  Each block walks its run of
+// tiles (tile_range).  Every tile and its one-column halo are read once into
+// LDS as p_new = z + beta p_old and K, every wave reading a share of the
+// slots with the loads of all its slots in flight together; the next tile's
+// loads are in flight while the current one is computed, and its active
+// lengths were fetched one tile earlier still, so no lane above its column's
+// top loads anything.  The step flags, the iteration count, the rho slots,
+// the solve's tolerance and this thread's share of the last update's
+// partials are read with the first tile's active lengths, in one round trip,
+// so that a launch past the end of the solve stops there.  Wave w forms
+// q = A p for its TY interior columns from LDS, with the arithmetic per cell
+// of k_spmv.  Writes p, q and the block partials of p.q (nblk_t blocks).
+template <int PRECOND, typename T, int TY>
 __global__ void __launch_bounds__(kThreads) k_spmv_tile(Geo g, Arrays a, CgVec<T> cv, int parity,
                                                         double tol_cg, double rel, int max_cg)
 {
+    using Tl = Tile<TY>;
     Scalars *s = a.sc;
-    if (s->done || s->fail || s->stall || s->picard_done) return;
-    __shared__ T sP[kSlots][kWave];
-    __shared__ T sK[kSlots][kWave];
-    __shared__ int sKt[kSlots];
+    const int stop = s->done | s->fail | s->stall | s->picard_done;
     const int j = s->iters;
+    const double rho_slot[2] = {s->rho[0], s->rho[1]};
+    const double tol_prev = s->tol_eff;
+    __shared__ T sP[Tl::NS][kWave];
+    __shared__ T sK[Tl::NS][kWave];
+    __shared__ int sKt[Tl::NS];
     const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
-    const bool first = (j == 0);
     RF_WAVE_IDS;
-    const int i0 = (int)(blockIdx.x % g.ntx) * kTileX - 1;
-    const int j0 = (int)(blockIdx.x / g.ntx) * kTileY - 1;
-    // active lengths first: of this wave's slots and of its own columns
-    int col[kSlotsPerWave], kt[kSlotsPerWave], oc[kTileY], okt[kTileY];
+    int tb, te;
+    tile_range(g, tb, te);
+    TileCols<TY> cur, nxt;
+    cur.fetch(g, a.ktop, tb < te ? tb : -1, w);
+    nxt.fetch(g, a.ktop, tb + 1 < te ? tb + 1 : -1, w);
+    double pv[2];
+    gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
+    if (stop) return;
+    const bool first = (j == 0);
+    T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY];
+    auto load = [&](const TileCols<TY> &c) {
 #pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        col[u] = slot_column(g, i0, j0, w + u * kWavesPerBlock);
-        kt[u] = (col[u] >= 0) ? a.ktop[col[u]] : 0;
-    }
-#pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        oc[t] = slot_column(g, i0, j0, (w + 1) + kSlotX * (t + 1));
-        okt[t] = (oc[t] >= 0) ? a.ktop[oc[t]] : 0;
-    }
-    // every load of the wave, masked by the active lengths
-    T z[kSlotsPerWave], po[kSlotsPerWave], K[kSlotsPerWave], Dd[kTileY];
-#pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        z[u] = T(0);
-        po[u] = T(0);
-        K[u] = T(0);
-        if (lane < kt[u]) {
-            const size_t i = (size_t)col[u] * g.nz + lane;
-            z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
-            po[u] = p_in[i];
-            K[u] = cv.K[i];
+        for (int u = 0; u < Tl::PER; u++) {
+            z[u] = T(0);
+            po[u] = T(0);
+            K[u] = T(0);
+            if (lane < c.kt[u]) {
+                const size_t i = (size_t)c.col[u] * g.nz + lane;
+                z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
+                po[u] = p_in[i];
+                K[u] = cv.K[i];
+            }
         }
-    }
 #pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        Dd[t] = T(0);
-        if (lane < okt[t]) Dd[t] = cv.Dd[(size_t)oc[t] * g.nz + lane];
-    }
-    double rho;
-    if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
-    const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
-#pragma unroll
-    for (int u = 0; u < kSlotsPerWave; u++) {
-        const int sl = w + u * kWavesPerBlock;
-        if (sl >= kSlots) continue;
-        if (lane < kt[u]) {
-            sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
-            sK[sl][lane] = K[u];
+        for (int t = 0; t < TY; t++) {
+            Dd[t] = T(0);
+            if (lane < c.okt[t]) Dd[t] = cv.Dd[(size_t)c.oc[t] * g.nz + lane];
         }
-        if (lane == 0) sKt[sl] = kt[u];
-    }
-    __syncthreads();
+    };
+    load(cur);
+    double tot[2];
+    combine_partials<2, 2u>(pv, tot);
+    if (!spmv_decide(s, j, tot, tol_prev, tol_cg, rel, max_cg)) return;
+    const T beta = first ? T(0) : (T)(tot[0] / rho_slot[(j + 1) & 1]);
     const T tz2 = (T)(0.5 * g.Tk[2]);
     const T tx2[2] = {(T)(0.5 * g.Tk[0]), (T)(0.5 * g.Tk[1])};
     double v[1] = {0.0};
+    for (int tile = tb; tile < te; tile++) {
 #pragma unroll
-    for (int t = 0; t < kTileY; t++) {
-        const int c = (w + 1) + kSlotX * (t + 1);
-        const int nbs[4] = {c - 1, c + 1, c - kSlotX, c + kSlotX};   // -x, +x, -y, +y
-        const bool act = lane < okt[t];
-        const T pp = act ? sP[c][lane] : T(0);
-        const T Kp = act ? sK[c][lane] : T(0);
-        const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
-        const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
-        T q = Dd[t] * pp;
+        for (int u = 0; u < Tl::PER; u++) {
+            const int sl = w + u * kWavesPerBlock;
+            if (sl >= Tl::NS) continue;
+            if (lane < cur.kt[u]) {
+                sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
+                sK[sl][lane] = K[u];
+            }
+            if (lane == 0) sKt[sl] = cur.kt[u];
+        }
+        __syncthreads();
+        // this tile's own columns; then the next tile's loads go out
+        int oc[TY], okt[TY];
+        T Dc[TY];
 #pragma unroll
-        for (int d = 0; d < 4; d++) {
-            const bool nb = act && lane < sKt[nbs[d]];
-            if (nb) q += tx2[d >> 1] * (Kp + sK[nbs[d]][lane]) * (pp - sP[nbs[d]][lane]);
+        for (int t = 0; t < TY; t++) {
+            oc[t] = cur.oc[t];
+            okt[t] = cur.okt[t];
+            Dc[t] = Dd[t];
         }
-        if (act && lane > 0) q += tz2 * (Kp + Kd) * (pp - pdn);
-        if (act && lane + 1 < okt[t]) q += tz2 * (Kp + Ku) * (pp - pup);
-        if (act) {
-            const size_t i = (size_t)oc[t] * g.nz + lane;
-            p_out[i] = pp;
-            cv.q[i] = q;
-            v[0] += (double)pp * (double)q;
+        if (tile + 1 < te) {
+            cur = nxt;
+            load(cur);
+            nxt.fetch(g, a.ktop, tile + 2 < te ? tile + 2 : -1, w);
         }
+#pragma unroll
+        for (int t = 0; t < TY; t++) {
+            const int c = Tl::own(w, t);
+            const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
+            const bool act = lane < okt[t];
+            const T pp = act ? sP[c][lane] : T(0);
+            const T Kp = act ? sK[c][lane] : T(0);
+            const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
+            const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
+            T q = Dc[t] * pp;
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                const bool nb = act && lane < sKt[nbs[d]];
+                if (nb) q += tx2[d >> 1] * (Kp + sK[nbs[d]][lane]) * (pp - sP[nbs[d]][lane]);
+            }
+            if (act && lane > 0) q += tz2 * (Kp + Kd) * (pp - pdn);
+            if (act && lane + 1 < okt[t]) q += tz2 * (Kp + Ku) * (pp - pup);
+            if (act) {
+                const size_t i = (size_t)oc[t] * g.nz + lane;
+                p_out[i] = pp;
+                cv.q[i] = q;
+                v[0] += (double)pp * (double)q;
+            }
+        }
+        __syncthreads();
     }
     block_partial<1, 0u>(v, a.pq);
 }
@@ -1778,16 +1917,28 @@ hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, doubl
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
     const int rf = refactor ? 1 : 0;
+    if (g.tiled && g.tile_y == 2) {
+        if (mixed && zl)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float, 2>), g, a, a.f, m, bout, rf);
+        if (mixed)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float, 2>), g, a, a.f, m,
+                            bout, rf);
+        if (zl)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double, 2>), g, a, dvec(a), m,
+                            bout, rf);
+        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double, 2>), g, a, dvec(a), m,
+                        bout, rf);
+    }
     if (g.tiled) {
         if (mixed && zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float, 4>), g, a, a.f, m, bout, rf);
         if (mixed)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout,
-                            rf);
-        if (zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m,
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float, 4>), g, a, a.f, m,
                             bout, rf);
-        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m,
+        if (zl)
+            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double, 4>), g, a, dvec(a), m,
+                            bout, rf);
+        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double, 4>), g, a, dvec(a), m,
                         bout, rf);
     }
     if (mixed && zl)
@@ -1801,18 +1952,31 @@ hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, i
                        const CgTol &t, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
-    if (g.tiled) {
+    if (g.tiled && g.tile_y == 2) {
         if (mixed && zl)
-            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, float>), g, a, a.f, parity,
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, float, 2>), g, a, a.f, parity,
                             t.tol_cg, t.rel, t.max_cg);
         if (mixed)
-            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, float>), g, a, a.f, parity,
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, float, 2>), g, a, a.f, parity,
                             t.tol_cg, t.rel, t.max_cg);
         if (zl)
-            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, double>), g, a, dvec(a),
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, double, 2>), g, a, dvec(a),
                             parity, t.tol_cg, t.rel, t.max_cg);
-        RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity,
-                        t.tol_cg, t.rel, t.max_cg);
+        RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, double, 2>), g, a, dvec(a),
+                        parity, t.tol_cg, t.rel, t.max_cg);
+    }
+    if (g.tiled) {
+        if (mixed && zl)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, float, 4>), g, a, a.f, parity,
+                            t.tol_cg, t.rel, t.max_cg);
+        if (mixed)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, float, 4>), g, a, a.f, parity,
+                            t.tol_cg, t.rel, t.max_cg);
+        if (zl)
+            RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_ZLINE, double, 4>), g, a, dvec(a),
+                            parity, t.tol_cg, t.rel, t.max_cg);
+        RF_LAUNCH_TILED(a.pq, 1, 0u, (k_spmv_tile<RF_PRECOND_JACOBI, double, 4>), g, a, dvec(a),
+                        parity, t.tol_cg, t.rel, t.max_cg);
     }
     if (mixed && zl)
         RF_LAUNCH_FOLD(a.pq, 1, 0u, (k_spmv<RF_PRECOND_ZLINE, float>), g, a, a.f, parity, t.tol_cg,

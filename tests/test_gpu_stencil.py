@@ -25,11 +25,12 @@ def masked_grid(nx=37, ny=26, nz=64, seed=7):
     return w
 
 
+@pytest.mark.parametrize("tile_rows", [2, 4])   # tiles of 8 x 2 and 8 x 4 columns
 @pytest.mark.parametrize("precision", [0, 1])
-def test_tiles_and_columns_take_the_same_steps(precision):
+def test_tiles_and_columns_take_the_same_steps(precision, tile_rows):
     w = masked_grid()
     opts = dict(ebats=1, dt0=300.0, precision=precision)
-    S_t = make_solver(w, stencil=1, **opts)
+    S_t = make_solver(w, stencil=1, tile_rows=tile_rows, **opts)
     S_c = make_solver(w, stencil=0, **opts)
     s_t, r_t = S_t.run(4 * 3600.0)
     s_c, r_c = S_c.run(4 * 3600.0)
@@ -41,6 +42,23 @@ def test_tiles_and_columns_take_the_same_steps(precision):
     h_c = S_c.get_state()[0].cpu().numpy()
     assert rel_err(h_t, h_c, m) <= 1e-12
     assert np.array_equal(h_t[~m], w.h0[~m])         # inactive cells untouched
+
+
+def test_tiles_walked_per_block_on_a_large_grid():
+    """A grid of more than 512 tiles (each block walks a run of tiles, the next
+    one's loads in flight): the same steps as the per-wave column kernels."""
+    w = masked_grid(nx=136, ny=130, nz=24, seed=5)      # 17 x 65 = 1105 tiles of 8 x 2
+    opts = dict(ebats=0, dt0=900.0)
+    S_t = make_solver(w, stencil=1, **opts)
+    S_c = make_solver(w, stencil=0, **opts)
+    for _ in range(3):
+        s_t, st_t = S_t.step(900.0)
+        s_c, st_c = S_c.step(900.0)
+        assert s_t == 0 and s_c == 0
+        assert st_t["picard_iters"] == st_c["picard_iters"]
+        assert st_t["cg_iters"] == st_c["cg_iters"]
+    m = w.active_mask()
+    assert rel_err(S_t.get_state()[0].cpu().numpy(), S_c.get_state()[0].cpu().numpy(), m) <= 1e-12
 
 
 def test_tiled_steps_match_oracle(orc):
