@@ -58,7 +58,7 @@ ALGO_BYTES = {
     },
 }
 PRECISION = {"fp64": 0, "mixed": 1}
-STENCIL = {"columns": 0, "tiles": 1}
+STENCIL = {"columns": 0, "tiles": 1, "auto": 2}
 
 
 def parse():
@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="copy this many MiB with torch before the steps (reference kernel of "
                          "known traffic for hardware-counter runs)")
-    ap.add_argument("--stencil", default="tiles", choices=["tiles", "columns"],
+    ap.add_argument("--stencil", default="auto", choices=["auto", "tiles", "columns"],
                     help="how the stencil kernels reach lateral neighbours (LDS tiles or "
                          "per-wave neighbour columns)")
     ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 2, 4],

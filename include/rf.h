@@ -102,12 +102,14 @@ enum { RF_WAIT_SPIN = 0, RF_WAIT_BLOCK = 1 };
 /* How the stencil kernels reach a cell's lateral neighbours (grids of at most
  * 64 cells per column; taller columns always use RF_STENCIL_COLUMNS).
  * RF_STENCIL_TILES: a workgroup stages a tile of 8 x tile_rows columns with
- * its one-column halo in LDS, each column read once per tile, and walks a
- * run of such tiles.
+ * its one-column halo in LDS, each column read once per tile.
  * RF_STENCIL_COLUMNS: each wavefront loads its column's four neighbour
- * columns itself.  Results agree to rounding (the same arithmetic per cell,
- * reductions combined in a different order). */
-enum { RF_STENCIL_COLUMNS = 0, RF_STENCIL_TILES = 1 };
+ * columns itself.
+ * RF_STENCIL_AUTO: tiles on grids of more than 16384 columns, where they
+ * measure faster; columns otherwise.
+ * Results agree to rounding (the same arithmetic per cell, reductions
+ * combined in a different order). */
+enum { RF_STENCIL_COLUMNS = 0, RF_STENCIL_TILES = 1, RF_STENCIL_AUTO = 2 };
 
 #define RF_MAX_LAYERS 16
 #define RF_MAX_PICARD_LOG 128
@@ -142,7 +144,7 @@ typedef struct {
     int first_iterate;  /* RF_FIRST_PREVIOUS (default) or RF_FIRST_EXTRAPOLATE */
     int zline_refactor; /* RF_REFACTOR_EVERY (default) or RF_REFACTOR_STEP */
     int host_wait;      /* RF_WAIT_SPIN (default) or RF_WAIT_BLOCK */
-    int stencil;        /* RF_STENCIL_TILES (default) or RF_STENCIL_COLUMNS */
+    int stencil;        /* RF_STENCIL_AUTO (default), RF_STENCIL_TILES or RF_STENCIL_COLUMNS */
     int tile_rows;      /* launch shape of RF_STENCIL_TILES: columns of a tile along
                            y, 2 or 4 (0 = chosen: 2) */
 } rf_options;

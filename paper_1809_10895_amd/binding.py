@@ -25,7 +25,7 @@ RF_PICARD_CHORD, RF_PICARD_MODIFIED = 0, 1
 RF_FIRST_PREVIOUS, RF_FIRST_EXTRAPOLATE = 0, 1
 RF_REFACTOR_EVERY, RF_REFACTOR_STEP = 0, 1
 RF_WAIT_SPIN, RF_WAIT_BLOCK = 0, 1
-RF_STENCIL_COLUMNS, RF_STENCIL_TILES = 0, 1
+RF_STENCIL_COLUMNS, RF_STENCIL_TILES, RF_STENCIL_AUTO = 0, 1, 2
 RF_MAX_PICARD_LOG = 128
 RF_NKERNELS = 8
 

@@ -250,8 +250,10 @@ static size_t max_partial_blocks(const rf_ctx *c)
     const size_t ncol = (size_t)c->nx * c->ny;
     size_t nb = (ncol + kWavesPerBlock - 1) / kWavesPerBlock;
     if (nb >= 8) nb = (nb + 7) / 8 * 8;
-    // tiled stencil kernels: at most kPartialsMax blocks
-    return std::max(nb, (size_t)kPartialsMax);
+    // tiled stencil kernels: one block per tile of kTileX x 2 or more columns
+    size_t nt = (size_t)((c->nx + kTileX - 1) / kTileX) * ((c->ny + 1) / 2);
+    nt = std::min<size_t>(nt, (size_t)1 << 20);
+    return std::max(nb, nt);
 }
 
 static size_t layout(const rf_ctx *c, char *base, Arrays *A)
@@ -325,16 +327,22 @@ static void set_shapes(rf_ctx *c)
     G.block_map = (c->n_cu > 0 && G.nblk <= 2 * c->n_cu) ? 1 : 0;
     // tiled stencil kernels (columns of at most one wave, grids of at least
     // one tile): one block per tile, their own partial count
-    // tile height (a taller tile reads fewer halo columns but takes more
-    // LDS); blocks walk contiguous runs of tiles, at most kPartialsMax blocks
+    // tile height (a taller tile reads fewer halo columns from L2 or HBM
+    // LDS but takes more LDS per block); one block per tile (many short
+    // blocks hide latency better than fewer blocks walking runs of tiles,
+    // measured), runs of tiles only beyond 2^20 tiles
     G.tile_y = (c->opt.tile_rows > 0) ? c->opt.tile_rows : 2;
     G.ntx = (c->nx + kTileX - 1) / kTileX;
     G.ntiles = G.ntx * ((c->ny + G.tile_y - 1) / G.tile_y);
-    G.nblk_t = std::min(G.ntiles, kPartialsMax);
+    G.nblk_t = std::min(G.ntiles, 1 << 20);
     G.tpb = (G.ntiles + G.nblk_t - 1) / G.nblk_t;
     G.nblk_t = (G.ntiles + G.tpb - 1) / G.tpb;
-    G.tiled = c->opt.stencil == RF_STENCIL_TILES && c->nz <= kWave && c->nx >= kTileX &&
-              c->ny >= G.tile_y;
+    // tiles where the column kernels' own grid already needs fold kernels
+    // (large grids); on smaller grids both measure alike and tiles would add
+    // folds
+    const bool want = c->opt.stencil == RF_STENCIL_TILES ||
+                      (c->opt.stencil == RF_STENCIL_AUTO && G.nblk > kPartialsMax);
+    G.tiled = want && c->nz <= kWave && c->nx >= kTileX && c->ny >= G.tile_y;
     // what consumers of block partials read (see Geo): the producers' own
     // partials if they all have the same, few enough blocks; else a folded
     // total in the slot after the largest producer's partials
@@ -477,7 +485,7 @@ void rf_default_options(rf_options *o)
     o->first_iterate = RF_FIRST_PREVIOUS;
     o->zline_refactor = RF_REFACTOR_EVERY;
     o->host_wait = RF_WAIT_SPIN;
-    o->stencil = RF_STENCIL_TILES;
+    o->stencil = RF_STENCIL_AUTO;
     o->tile_rows = 0;
 }
 
@@ -672,7 +680,8 @@ rf_status rf_set_options(rf_ctx *c, const rf_options *o)
         (o->first_iterate != RF_FIRST_PREVIOUS && o->first_iterate != RF_FIRST_EXTRAPOLATE) ||
         (o->zline_refactor != RF_REFACTOR_EVERY && o->zline_refactor != RF_REFACTOR_STEP) ||
         (o->host_wait != RF_WAIT_SPIN && o->host_wait != RF_WAIT_BLOCK) ||
-        (o->stencil != RF_STENCIL_COLUMNS && o->stencil != RF_STENCIL_TILES) ||
+        (o->stencil != RF_STENCIL_COLUMNS && o->stencil != RF_STENCIL_TILES &&
+         o->stencil != RF_STENCIL_AUTO) ||
         (o->tile_rows != 0 && o->tile_rows != 2 && o->tile_rows != 4))
         return fail(c, RF_ERR_ARG, "invalid options");
     if (c->have_ws && o->precision != c->opt.precision) {

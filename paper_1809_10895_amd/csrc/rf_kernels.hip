@@ -1399,28 +1399,75 @@ __device__ __forceinline__ bool update_alpha(const Geo &g, const Arrays &a, Scal
     return true;
 }
 
-// Values of G columns of one wave read by the update kernel.
-template <int PRECOND, typename T, int G>
-struct UpdGroup {
-    ColSlot cs[G];
-    T p[G], r[G], q[G], d[G], e[G], rd[G], t[G];
 
-    __device__ __forceinline__ void load(const Geo &g, const Arrays &a, const CgVec<T> &cv,
-                                         const T *__restrict__ pv, int c0, int ce, int lane)
+// alpha = rho_j / pq from the combined p.q total, or a breakdown (p.q not
+// positive or not finite) that ends the solve; rho_j is read by the caller
+// beforehand.  Called by every thread; returns false on breakdown.
+__device__ __forceinline__ bool update_decide(Scalars *s, int j, double pq, double rho_j,
+                                              double &alpha)
+{
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (lead_thread()) {
+            s->pq = pq;
+            s->fail = 1;
+            s->done = 1;
+            s->final_iters = j;
+        }
+        return false;
+    }
+    alpha = rho_j / pq;
+    if (lead_thread()) {
+        s->pq = pq;
+        s->iters = j + 1;
+    }
+    return true;
+}
+
+// Columns of one group of a wave (G columns, 8 apart) and their active
+// lengths: wave-uniform, fetched by scalar loads ahead of the group's data so
+// that the data loads can be masked without waiting for them.
+template <int G>
+struct GroupCols {
+    int col[G], kt[G];
+
+    __device__ __forceinline__ void fetch(const int32_t *__restrict__ ktop, int c0, int ce)
     {
 #pragma unroll
-        for (int u = 0; u < G; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+        for (int u = 0; u < G; u++) {
+            const int c = c0 + u * kWavesPerBlock;
+            col[u] = (c < ce) ? c : -1;
+            kt[u] = (c < ce) ? ktop[c] : 0;
+        }
+    }
+};
+
+// Values of G columns of one wave read by the update kernel, loaded by the
+// lanes below each column's active length only.
+template <int PRECOND, typename T, int G>
+struct UpdGroupM {
+    int col[G], kt[G];
+    T p[G], r[G], q[G], d[G], e[G], rd[G], t[G];
+
+    __device__ __forceinline__ void load(const Geo &g, const CgVec<T> &cv, const T *__restrict__ pv,
+                                         const GroupCols<G> &gc, int lane)
+    {
 #pragma unroll
         for (int u = 0; u < G; u++) {
-            const size_t i = cs[u].i;
-            p[u] = pv[i];
-            r[u] = cv.r[i];
-            q[u] = cv.q[i];
-            d[u] = cv.diag[i];
-            e[u] = cv.e[i];
-            if (PRECOND == RF_PRECOND_ZLINE) {
-                rd[u] = cv.rdp[i];
-                t[u] = cv.tz[i];
+            col[u] = gc.col[u];
+            kt[u] = gc.kt[u];
+            p[u] = r[u] = q[u] = e[u] = rd[u] = t[u] = T(0);
+            d[u] = T(1);
+            if (lane < kt[u]) {
+                const size_t i = (size_t)col[u] * g.nz + lane;
+                p[u] = pv[i];
+                r[u] = cv.r[i];
+                q[u] = cv.q[i];
+                d[u] = cv.diag[i];
+                e[u] = cv.e[i];
+                if (PRECOND == RF_PRECOND_ZLINE) {
+                    rd[u] = cv.rdp[i];
+                    t[u] = cv.tz[i];
+                }
             }
         }
     }
@@ -1436,8 +1483,6 @@ template <int PRECOND, typename T>
 __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
 {
     Scalars *s = a.sc;
-    if (s->done || s->fail || s->stall || s->picard_done) return;
-    const int j = s->jcur;
     const T *__restrict__ p = parity ? cv.p0 : cv.p1;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
@@ -1445,20 +1490,36 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
     double v[2] = {0.0, 0.0};
     double alpha_d;
     if (g.nz <= kWave) {
+        // short columns: two groups of G columns in turn, the next group's
+        // loads in flight while the current one is computed, and the active
+        // lengths of the group after it fetched with them; the step flags,
+        // rho, the iteration index, the first two groups' active lengths and
+        // this thread's share of the p.q partials are read in one round trip
         constexpr int G = 2;
         constexpr int step = kWavesPerBlock * G;
-        UpdGroup<PRECOND, T, G> ga, gb;
-        ga.load(g, a, cv, p, cb + w, ce, lane);
-        if (!update_alpha(g, a, s, j, alpha_d)) return;
+        const int stop = s->done | s->fail | s->stall | s->picard_done;
+        const int j = s->jcur;
+        const double rho_slot[2] = {s->rho[0], s->rho[1]};
+        GroupCols<G> ka, kb;
+        ka.fetch(a.ktop, cb + w, ce);
+        kb.fetch(a.ktop, cb + w + step, ce);
+        double pv[1];
+        gather_partials<1, 0u>(a.pq + g.foff, g.np, pv);
+        if (stop) return;
+        UpdGroupM<PRECOND, T, G> ga, gb;
+        ga.load(g, cv, p, ka, lane);
+        double tot[1];
+        combine_partials<1, 0u>(pv, tot);
+        if (!update_decide(s, j, tot[0], rho_slot[j & 1], alpha_d)) return;
         const T alpha = (T)alpha_d;
         T *__restrict__ ev = cv.e;
         T *__restrict__ rv = cv.r;
         T *__restrict__ zv = cv.z;
-        auto work = [&](const UpdGroup<PRECOND, T, G> &gr) {
+        auto work = [&](const UpdGroupM<PRECOND, T, G> &gr) {
 #pragma unroll
             for (int u = 0; u < G; u++) {
-                const bool act = gr.cs[u].act;
-                const size_t i = gr.cs[u].i;
+                const bool act = lane < gr.kt[u];
+                const size_t i = (size_t)(gr.col[u] >= 0 ? gr.col[u] : 0) * g.nz + lane;
                 const T r = act ? gr.r[u] - alpha * gr.q[u] : T(0);
                 if (act) {
                     ev[i] = gr.e[u] + alpha * gr.p[u];
@@ -1476,19 +1537,25 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                 }
             }
         };
-        // two groups in turn: the next group's loads are in flight while
-        // the current one is computed
         for (int c0 = cb + w; c0 < ce; c0 += 2 * step) {
             const bool more = c0 + step < ce;
-            if (more) gb.load(g, a, cv, p, c0 + step, ce, lane);
+            if (more) {
+                gb.load(g, cv, p, kb, lane);
+                ka.fetch(a.ktop, c0 + 2 * step, ce);
+            }
             work(ga);
             if (!more) break;
-            if (c0 + 2 * step < ce) ga.load(g, a, cv, p, c0 + 2 * step, ce, lane);
+            if (c0 + 2 * step < ce) {
+                ga.load(g, cv, p, ka, lane);
+                kb.fetch(a.ktop, c0 + 3 * step, ce);
+            }
             work(gb);
         }
         block_partial<2, 2u>(v, a.pr);
         return;
     }
+    if (s->done || s->fail || s->stall || s->picard_done) return;
+    const int j = s->jcur;
     if (!update_alpha(g, a, s, j, alpha_d)) return;
     const T alpha = (T)alpha_d;
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
@@ -1531,35 +1598,45 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
                                                       double tol_cg, double rel, int max_cg)
 {
     Scalars *s = a.sc;
-    if (s->fail || s->stall || s->picard_done) return;
+    // the step flags, the solve's state, the first group's active lengths and
+    // this thread's share of the last update's partials in one round trip;
+    // short columns: the loads of the first group (masked by the active
+    // lengths) are in flight while the partials are combined
+    const int stop = s->fail | s->stall | s->picard_done;
     const int j = s->iters;
+    const int sdone = s->done;
+    const double tol_prev = s->tol_eff;
     const double *__restrict__ hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
     const T *__restrict__ ev = e_in;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
-    // short columns: the first group of e and h^m is in flight while the
-    // partials are combined
-    ColSlot cs[kColGroup];
+    GroupCols<kColGroup> kc;
+    if (g.nz <= kWave) kc.fetch(a.ktop, cb + w, ce);
+    double pv[2];
+    gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
+    if (stop) return;
     double e[kColGroup], hv[kColGroup];   // e widened to FP64
-    auto load = [&](int c0) {
-#pragma unroll
-        for (int u = 0; u < kColGroup; u++)
-            cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
+    auto load = [&]() {
 #pragma unroll
         for (int u = 0; u < kColGroup; u++) {
-            e[u] = (double)ev[cs[u].i];
-            hv[u] = hmv[cs[u].i];
+            e[u] = 0.0;
+            hv[u] = 0.0;
+            if (lane < kc.kt[u]) {
+                const size_t i = (size_t)kc.col[u] * g.nz + lane;
+                e[u] = (double)ev[i];
+                hv[u] = hmv[i];
+            }
         }
     };
-    if (g.nz <= kWave) load(cb + w);
+    if (g.nz <= kWave) load();
     double tot[2];
-    reduce_partials<2, 2u>(a.pr + 2 * g.foff, g.np, tot);
+    combine_partials<2, 2u>(pv, tot);
     // the exit tolerance of this solve (fixed by its first direction update)
-    const double tol = (j == 0 && !s->done) ? fmax(tol_cg, rel * tot[1]) : s->tol_eff;
+    const double tol = (j == 0 && !sdone) ? fmax(tol_cg, rel * tot[1]) : tol_prev;
     const bool bad = !isfinite(tot[0]) || !isfinite(tot[1]);
-    const bool finished = s->done || bad || !(tot[1] > tol) || j >= max_cg;
+    const bool finished = sdone || bad || !(tot[1] > tol) || j >= max_cg;
     if (!finished) {
         if (lead_thread()) {
             s->stall = 1;
@@ -1567,7 +1644,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
         }
         return;
     }
-    if (!s->done && (bad || tot[1] > tol)) {
+    if (!sdone && (bad || tot[1] > tol)) {
         if (lead_thread()) {   // the next direction update would stop with this status
             s->fail = bad ? 3 : 2;
             s->done = 1;
@@ -1578,12 +1655,15 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
     double v[2] = {0.0, 0.0};
     if (g.nz <= kWave) {
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * kColGroup) {
-            if (c0 != cb + w) load(c0);
+            if (c0 != cb + w) {
+                kc.fetch(a.ktop, c0, ce);
+                load();
+            }
 #pragma unroll
             for (int u = 0; u < kColGroup; u++) {
-                if (!cs[u].act) continue;
+                if (lane >= kc.kt[u]) continue;
                 const double h = hv[u] + e[u];
-                hnext[cs[u].i] = h;
+                hnext[(size_t)kc.col[u] * g.nz + lane] = h;
                 v[0] = fmax(v[0], fabs(e[u]));
                 if (!isfinite(h)) v[1] += 1.0;
             }
