@@ -252,7 +252,7 @@ static size_t max_partial_blocks(const rf_ctx *c)
     if (nb >= 8) nb = (nb + 7) / 8 * 8;
     // tiled stencil kernels: one block per tile of kTileX x 2 or more columns
     size_t nt = (size_t)((c->nx + kTileX - 1) / kTileX) * ((c->ny + 1) / 2);
-    nt = std::min<size_t>(nt, (size_t)1 << 20);
+    nt = std::min<size_t>(nt, (size_t)1 << 22);
     return std::max(nb, nt);
 }
 
@@ -328,21 +328,19 @@ static void set_shapes(rf_ctx *c)
     // tiled stencil kernels (columns of at most one wave, grids of at least
     // one tile): one block per tile, their own partial count
     // tile height (a taller tile reads fewer halo columns from L2 or HBM
-    // LDS but takes more LDS per block); one block per tile (many short
-    // blocks hide latency better than fewer blocks walking runs of tiles,
-    // measured), runs of tiles only beyond 2^20 tiles
+    // but takes more LDS per block, and fewer blocks fit a CU); one block
+    // per tile, on grids of at most 2^22 tiles
     G.tile_y = (c->opt.tile_rows > 0) ? c->opt.tile_rows : 2;
     G.ntx = (c->nx + kTileX - 1) / kTileX;
-    G.ntiles = G.ntx * ((c->ny + G.tile_y - 1) / G.tile_y);
-    G.nblk_t = std::min(G.ntiles, 1 << 20);
-    G.tpb = (G.ntiles + G.nblk_t - 1) / G.nblk_t;
-    G.nblk_t = (G.ntiles + G.tpb - 1) / G.tpb;
+    const long ntiles = (long)G.ntx * ((c->ny + G.tile_y - 1) / G.tile_y);
+    G.nblk_t = (int)std::min<long>(ntiles, 1L << 22);
     // tiles where the column kernels' own grid already needs fold kernels
     // (large grids); on smaller grids both measure alike and tiles would add
     // folds
     const bool want = c->opt.stencil == RF_STENCIL_TILES ||
                       (c->opt.stencil == RF_STENCIL_AUTO && G.nblk > kPartialsMax);
-    G.tiled = want && c->nz <= kWave && c->nx >= kTileX && c->ny >= G.tile_y;
+    G.tiled = want && c->nz <= kWave && c->nx >= kTileX && c->ny >= G.tile_y &&
+              ntiles <= (1L << 22);
     // what consumers of block partials read (see Geo): the producers' own
     // partials if they all have the same, few enough blocks; else a folded
     // total in the slot after the largest producer's partials

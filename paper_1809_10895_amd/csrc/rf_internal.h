@@ -46,8 +46,8 @@ struct Geo {
     int block_map;          // 0 identity, 1 one slab per XCD, 2 slabs entered at staggered points
     int tiled;              // stencil kernels stage kTileX x kTileY tiles with halo in LDS
     int tile_y;             // interior columns of a tile along y (2 or 4)
-    int ntx, ntiles;        // tiles along x, tiles of the grid
-    int nblk_t, tpb;        // tiled kernels: blocks, and tiles walked by each block
+    int ntx;                // tiles along x
+    int nblk_t;             // tiled kernels: blocks (one tile each)
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z
     double Tk[3];           // A / distance between centres, per unit K

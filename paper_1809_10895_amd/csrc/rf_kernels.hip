@@ -266,18 +266,6 @@ struct TileCols {
     }
 };
 
-// Tiles [tb, te) of this block: a contiguous run of tpb tiles per logical
-// block.  When the grid is a multiple of 8, logical blocks are dealt so that
-// each XCD (hardware block b runs on XCD b % 8) owns one contiguous range of
-// tiles, whose y-halos then mostly sit in its own L2.
-__device__ __forceinline__ void tile_range(const Geo &g, int &tb, int &te)
-{
-    const int b = blockIdx.x, G = gridDim.x;
-    const int lb = ((G & 7) == 0 && G >= 8) ? (b & 7) * (G >> 3) + (b >> 3) : b;
-    tb = lb * g.tpb;
-    te = min(tb + g.tpb, g.ntiles);
-}
-
 __device__ __forceinline__ bool lead_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // Boundary terms of a cell with face f on the domain boundary, in terms of
@@ -941,19 +929,20 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
 }
 
 // The residual kernel with the lateral neighbours staged in LDS (columns of
-// at most one wave; the tile layout of Tile<TY>).  Each block walks its run
-// of tiles (tile_range); for every tile the waves read K and h^m of their
-// share of the slots and Dd, bst of their own columns (masked by the active
-// lengths), stage K and h^m in LDS, and form each of their TY interior
-// columns with resid_column, whose arithmetic is that of k_resid.  The next
-// tile's loads are in flight while the current one is computed, and its
-// active lengths were fetched one tile earlier still; the step flags are read
-// with the first tile's active lengths, so that a launch past the end of the
-// step stops after one round trip.  Writes the (r.z, max|r/diag|) block
-// partials of nblk_t blocks into pr.
+// at most one wave; the tile layout of Tile<TY>, one tile per block).  Every
+// wave reads K and h^m of its share of the tile's slots and Dd, bst of its
+// own columns (masked by their active lengths), stages K and h^m in LDS, and
+// forms each of its TY interior columns with resid_column, whose arithmetic
+// is that of k_resid.  The step flags and the active lengths are read
+// together first, so that a launch past the end of the step stops after one
+// round trip and no lane above its column's top loads anything.  Three
+// blocks fit a CU (LDS and the register bound), which hides the latency of
+// each block's two round trips better than fewer blocks walking several
+// tiles (measured).  Writes the (r.z, max|r/diag|) block partials of nblk_t
+// blocks into pr.
 template <int PRECOND, typename T, int TY>
-__global__ void __launch_bounds__(kThreads) k_resid_tile(Geo g, Arrays a, CgVec<T> cv, int m,
-                                                         double *bout, int refactor)
+__global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgVec<T> cv, int m,
+                                                            double *bout, int refactor)
 {
     using Tl = Tile<TY>;
     Scalars *s = a.sc;
@@ -963,91 +952,65 @@ __global__ void __launch_bounds__(kThreads) k_resid_tile(Geo g, Arrays a, CgVec<
     __shared__ int sKt[Tl::NS];
     const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     RF_WAVE_IDS;
-    int tb, te;
-    tile_range(g, tb, te);
-    TileCols<TY> cur, nxt;
-    cur.fetch(g, a.ktop, tb < te ? tb : -1, w);
-    nxt.fetch(g, a.ktop, tb + 1 < te ? tb + 1 : -1, w);
+    TileCols<TY> tc;
+    tc.fetch(g, a.ktop, blockIdx.x, w);
     if (stop) return;
     double K[Tl::PER], h[Tl::PER], Dp[TY], bp[TY], tzs[TY], rds[TY];
-    auto load = [&](const TileCols<TY> &c) {
 #pragma unroll
-        for (int u = 0; u < Tl::PER; u++) {
-            K[u] = 0.0;
-            h[u] = 0.0;
-            if (lane < c.kt[u]) {
-                const size_t i = (size_t)c.col[u] * g.nz + lane;
-                K[u] = a.K[i];
-                h[u] = hmv[i];
+    for (int u = 0; u < Tl::PER; u++) {
+        K[u] = 0.0;
+        h[u] = 0.0;
+        if (lane < tc.kt[u]) {
+            const size_t i = (size_t)tc.col[u] * g.nz + lane;
+            K[u] = a.K[i];
+            h[u] = hmv[i];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TY; t++) {
+        Dp[t] = 0.0;
+        bp[t] = 0.0;
+        tzs[t] = 0.0;
+        rds[t] = 0.0;
+        if (lane < tc.okt[t]) {
+            const size_t i = (size_t)tc.oc[t] * g.nz + lane;
+            Dp[t] = a.Dd[i];
+            bp[t] = a.bst[i];
+            if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
+                tzs[t] = (double)cv.tz[i];
+                rds[t] = (double)cv.rdp[i];
             }
         }
+    }
 #pragma unroll
-        for (int t = 0; t < TY; t++) {
-            Dp[t] = 0.0;
-            bp[t] = 0.0;
-            tzs[t] = 0.0;
-            rds[t] = 0.0;
-            if (lane < c.okt[t]) {
-                const size_t i = (size_t)c.oc[t] * g.nz + lane;
-                Dp[t] = a.Dd[i];
-                bp[t] = a.bst[i];
-                if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
-                    tzs[t] = (double)cv.tz[i];
-                    rds[t] = (double)cv.rdp[i];
-                }
-            }
+    for (int u = 0; u < Tl::PER; u++) {
+        const int sl = w + u * kWavesPerBlock;
+        if (sl >= Tl::NS) continue;
+        if (lane < tc.kt[u]) {
+            sK[sl][lane] = K[u];
+            sH[sl][lane] = h[u];
         }
-    };
-    load(cur);
+        if (lane == 0) sKt[sl] = tc.kt[u];
+    }
+    __syncthreads();
     double v[2] = {0.0, 0.0};
-    for (int tile = tb; tile < te; tile++) {
 #pragma unroll
-        for (int u = 0; u < Tl::PER; u++) {
-            const int sl = w + u * kWavesPerBlock;
-            if (sl >= Tl::NS) continue;
-            if (lane < cur.kt[u]) {
-                sK[sl][lane] = K[u];
-                sH[sl][lane] = h[u];
-            }
-            if (lane == 0) sKt[sl] = cur.kt[u];
-        }
-        __syncthreads();
-        // this tile's own columns; then the next tile's loads go out
-        int oc[TY], okt[TY];
-        double Dc[TY], bc[TY], tzc[TY], rdc[TY];
+    for (int t = 0; t < TY; t++) {
+        const int c = Tl::own(w, t);
+        const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
+        const bool act = lane < tc.okt[t];
+        const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
+        double Kn[4], hn[4];
+        bool nb[4];
 #pragma unroll
-        for (int t = 0; t < TY; t++) {
-            oc[t] = cur.oc[t];
-            okt[t] = cur.okt[t];
-            Dc[t] = Dp[t];
-            bc[t] = bp[t];
-            tzc[t] = tzs[t];
-            rdc[t] = rds[t];
+        for (int d = 0; d < 4; d++) {
+            nb[d] = act && lane < sKt[nbs[d]];
+            Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
+            hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
         }
-        if (tile + 1 < te) {
-            cur = nxt;
-            load(cur);
-            nxt.fetch(g, a.ktop, tile + 2 < te ? tile + 2 : -1, w);
-        }
-#pragma unroll
-        for (int t = 0; t < TY; t++) {
-            const int c = Tl::own(w, t);
-            const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
-            const bool act = lane < okt[t];
-            const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
-            double Kn[4], hn[4];
-            bool nb[4];
-#pragma unroll
-            for (int d = 0; d < 4; d++) {
-                nb[d] = act && lane < sKt[nbs[d]];
-                Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
-                hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
-            }
-            const size_t i = (size_t)(oc[t] >= 0 ? oc[t] : 0) * g.nz + lane;
-            resid_column<PRECOND, T>(g, cv, bout, refactor, act, okt[t], i, lane, Kp, hp, Dc[t],
-                                     bc[t], Kn, hn, nb, tzc[t], rdc[t], v);
-        }
-        __syncthreads();
+        const size_t i = (size_t)(tc.oc[t] >= 0 ? tc.oc[t] : 0) * g.nz + lane;
+        resid_column<PRECOND, T>(g, cv, bout, refactor, act, tc.okt[t], i, lane, Kp, hp, Dp[t],
+                                 bp[t], Kn, hn, nb, tzs[t], rds[t], v);
     }
     block_partial<2, 2u>(v, a.pr);
     if (lead_thread()) resid_reset_scalars(s, m);
@@ -1249,21 +1212,19 @@ __device__ __forceinline__ bool spmv_decide(Scalars *s, int j, const double (&to
 }
 
 // The same PCG step with the lateral neighbours staged in LDS (columns of at
-// most one wave; the tile layout of Tile<TY>).  Each block walks its run of
-// tiles (tile_range).  Every tile and its one-column halo are read once into
-// LDS as p_new = z + beta p_old and K, every wave reading a share of the
-// slots with the loads of all its slots in flight together; the next tile's
-// loads are in flight while the current one is computed, and its active
-// lengths were fetched one tile earlier still, so no lane above its column's
-// top loads anything.  The step flags, the iteration count, the rho slots,
-// the solve's tolerance and this thread's share of the last update's
-// partials are read with the first tile's active lengths, in one round trip,
-// so that a launch past the end of the solve stops there.  Wave w forms
-// q = A p for its TY interior columns from LDS, with the arithmetic per cell
-// of k_spmv.  Writes p, q and the block partials of p.q (nblk_t blocks).
+// most one wave; the tile layout of Tile<TY>, one tile per block).  The tile
+// and its one-column halo are read once into LDS as p_new = z + beta p_old
+// and K, every wave reading a share of the slots with the loads of all its
+// slots in flight together.  The step flags, the iteration count, the rho
+// slots, the solve's tolerance, the active lengths and this thread's share of
+// the last update's partials are read in one round trip first, so that a
+// launch past the end of the solve stops there and no lane above its column's
+// top loads anything.  Wave w forms q = A p for its TY interior columns from
+// LDS, with the arithmetic per cell of k_spmv.  Three blocks fit a CU.
+// Writes p, q and the block partials of p.q (nblk_t blocks).
 template <int PRECOND, typename T, int TY>
-__global__ void __launch_bounds__(kThreads) k_spmv_tile(Geo g, Arrays a, CgVec<T> cv, int parity,
-                                                        double tol_cg, double rel, int max_cg)
+__global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVec<T> cv, int parity,
+                                                           double tol_cg, double rel, int max_cg)
 {
     using Tl = Tile<TY>;
     Scalars *s = a.sc;
@@ -1277,94 +1238,71 @@ __global__ void __launch_bounds__(kThreads) k_spmv_tile(Geo g, Arrays a, CgVec<T
     const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
     RF_WAVE_IDS;
-    int tb, te;
-    tile_range(g, tb, te);
-    TileCols<TY> cur, nxt;
-    cur.fetch(g, a.ktop, tb < te ? tb : -1, w);
-    nxt.fetch(g, a.ktop, tb + 1 < te ? tb + 1 : -1, w);
+    TileCols<TY> tc;
+    tc.fetch(g, a.ktop, blockIdx.x, w);
     double pv[2];
     gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
     if (stop) return;
     const bool first = (j == 0);
     T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY];
-    auto load = [&](const TileCols<TY> &c) {
 #pragma unroll
-        for (int u = 0; u < Tl::PER; u++) {
-            z[u] = T(0);
-            po[u] = T(0);
-            K[u] = T(0);
-            if (lane < c.kt[u]) {
-                const size_t i = (size_t)c.col[u] * g.nz + lane;
-                z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
-                po[u] = p_in[i];
-                K[u] = cv.K[i];
-            }
+    for (int u = 0; u < Tl::PER; u++) {
+        z[u] = T(0);
+        po[u] = T(0);
+        K[u] = T(0);
+        if (lane < tc.kt[u]) {
+            const size_t i = (size_t)tc.col[u] * g.nz + lane;
+            z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
+            po[u] = p_in[i];
+            K[u] = cv.K[i];
         }
+    }
 #pragma unroll
-        for (int t = 0; t < TY; t++) {
-            Dd[t] = T(0);
-            if (lane < c.okt[t]) Dd[t] = cv.Dd[(size_t)c.oc[t] * g.nz + lane];
-        }
-    };
-    load(cur);
+    for (int t = 0; t < TY; t++) {
+        Dd[t] = T(0);
+        if (lane < tc.okt[t]) Dd[t] = cv.Dd[(size_t)tc.oc[t] * g.nz + lane];
+    }
     double tot[2];
     combine_partials<2, 2u>(pv, tot);
     if (!spmv_decide(s, j, tot, tol_prev, tol_cg, rel, max_cg)) return;
     const T beta = first ? T(0) : (T)(tot[0] / rho_slot[(j + 1) & 1]);
+#pragma unroll
+    for (int u = 0; u < Tl::PER; u++) {
+        const int sl = w + u * kWavesPerBlock;
+        if (sl >= Tl::NS) continue;
+        if (lane < tc.kt[u]) {
+            sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
+            sK[sl][lane] = K[u];
+        }
+        if (lane == 0) sKt[sl] = tc.kt[u];
+    }
+    __syncthreads();
     const T tz2 = (T)(0.5 * g.Tk[2]);
     const T tx2[2] = {(T)(0.5 * g.Tk[0]), (T)(0.5 * g.Tk[1])};
     double v[1] = {0.0};
-    for (int tile = tb; tile < te; tile++) {
 #pragma unroll
-        for (int u = 0; u < Tl::PER; u++) {
-            const int sl = w + u * kWavesPerBlock;
-            if (sl >= Tl::NS) continue;
-            if (lane < cur.kt[u]) {
-                sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
-                sK[sl][lane] = K[u];
-            }
-            if (lane == 0) sKt[sl] = cur.kt[u];
-        }
-        __syncthreads();
-        // this tile's own columns; then the next tile's loads go out
-        int oc[TY], okt[TY];
-        T Dc[TY];
+    for (int t = 0; t < TY; t++) {
+        const int c = Tl::own(w, t);
+        const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
+        const bool act = lane < tc.okt[t];
+        const T pp = act ? sP[c][lane] : T(0);
+        const T Kp = act ? sK[c][lane] : T(0);
+        const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
+        const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
+        T q = Dd[t] * pp;
 #pragma unroll
-        for (int t = 0; t < TY; t++) {
-            oc[t] = cur.oc[t];
-            okt[t] = cur.okt[t];
-            Dc[t] = Dd[t];
+        for (int d = 0; d < 4; d++) {
+            const bool nb = act && lane < sKt[nbs[d]];
+            if (nb) q += tx2[d >> 1] * (Kp + sK[nbs[d]][lane]) * (pp - sP[nbs[d]][lane]);
         }
-        if (tile + 1 < te) {
-            cur = nxt;
-            load(cur);
-            nxt.fetch(g, a.ktop, tile + 2 < te ? tile + 2 : -1, w);
+        if (act && lane > 0) q += tz2 * (Kp + Kd) * (pp - pdn);
+        if (act && lane + 1 < tc.okt[t]) q += tz2 * (Kp + Ku) * (pp - pup);
+        if (act) {
+            const size_t i = (size_t)tc.oc[t] * g.nz + lane;
+            p_out[i] = pp;
+            cv.q[i] = q;
+            v[0] += (double)pp * (double)q;
         }
-#pragma unroll
-        for (int t = 0; t < TY; t++) {
-            const int c = Tl::own(w, t);
-            const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
-            const bool act = lane < okt[t];
-            const T pp = act ? sP[c][lane] : T(0);
-            const T Kp = act ? sK[c][lane] : T(0);
-            const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
-            const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
-            T q = Dc[t] * pp;
-#pragma unroll
-            for (int d = 0; d < 4; d++) {
-                const bool nb = act && lane < sKt[nbs[d]];
-                if (nb) q += tx2[d >> 1] * (Kp + sK[nbs[d]][lane]) * (pp - sP[nbs[d]][lane]);
-            }
-            if (act && lane > 0) q += tz2 * (Kp + Kd) * (pp - pdn);
-            if (act && lane + 1 < okt[t]) q += tz2 * (Kp + Ku) * (pp - pup);
-            if (act) {
-                const size_t i = (size_t)oc[t] * g.nz + lane;
-                p_out[i] = pp;
-                cv.q[i] = q;
-                v[0] += (double)pp * (double)q;
-            }
-        }
-        __syncthreads();
     }
     block_partial<1, 0u>(v, a.pq);
 }
