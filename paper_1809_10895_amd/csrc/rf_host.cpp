@@ -585,7 +585,7 @@ static rf_status upload_soil(rf_ctx *c)
         HIPCHK(c, hipMemcpyAsync(A.Ks, c->lnks.data(), N * sizeof(double), hipMemcpyHostToDevice,
                                  c->stream));
     else
-        HIPCHK(c, hipMemsetAsync(A.Ks, 0, N * sizeof(double), c->stream));
+        HIPCHK(c, launch_zero(A.Ks, N * sizeof(double), c->stream));
     double ksl[RF_MAX_LAYERS];
     for (int l = 0; l < c->nlayer; l++) ksl[l] = c->params[l][4];
     HIPCHK(c, hipMemcpyAsync(A.ks_layer, ksl, sizeof(ksl), hipMemcpyHostToDevice, c->stream));
@@ -704,11 +704,17 @@ rf_status rf_workspace_bytes(const rf_ctx *c, size_t *bytes)
     return RF_OK;
 }
 
-rf_status rf_bind_workspace(rf_ctx *c, void *dev_ptr, size_t bytes)
+}  // extern "C"
+
+int rf::ctx_device(const rf_ctx *c) { return c->device; }
+
+// Binds `bytes` of device memory at dev_ptr as the workspace: lays out the
+// arrays, uploads the grid and soil tables and clears the device scalars.
+// Allocates nothing.
+rf_status rf::ctx_bind(rf_ctx *c, void *dev_ptr, size_t bytes)
 {
-    if (!c) return RF_ERR_ARG;
     if (!c->have_grid || !c->have_soil)
-        return fail(c, RF_ERR_STATE, "rf_bind_workspace before grid and soil");
+        return fail(c, RF_ERR_STATE, "workspace bound before grid and soil");
     if (!dev_ptr || ((uintptr_t)dev_ptr % kAlign) != 0)
         return fail(c, RF_ERR_ARG, "workspace must be a 256-byte aligned device pointer");
     const size_t need = layout(c, nullptr, nullptr);
@@ -720,13 +726,21 @@ rf_status rf_bind_workspace(rf_ctx *c, void *dev_ptr, size_t bytes)
     c->ws_bytes = bytes;
     HIPCHK(c, hipMemcpyAsync(c->A.ktop, c->ktop.data(), c->ktop.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->A.sc, 0, sizeof(Scalars), c->stream));
+    HIPCHK(c, launch_zero(c->A.sc, sizeof(Scalars), c->stream));
     rf_status s = upload_soil(c);
     if (s) return s;
     c->have_ws = true;
     c->have_state = false;
     c->assembled = false;
     return RF_OK;
+}
+
+extern "C" {
+
+rf_status rf_bind_workspace(rf_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return RF_ERR_ARG;
+    return ctx_bind(c, dev_ptr, bytes);
 }
 
 rf_status rf_set_state(rf_ctx *c, const double *h_dev, double t)
@@ -908,7 +922,7 @@ static rf_status finish_step(rf_ctx *c, StepRec &r, bool last, rf_step_stats *st
         // this one that found it not accepted) is cleared first
         *first_batch = false;
         last = true;
-        HIPCHK(c, hipMemsetAsync(&A.sc->stall, 0, sizeof(int), c->stream));
+        HIPCHK(c, launch_zero(&A.sc->stall, sizeof(int), c->stream));
         if (h.stall) {
             // PCG of iteration ms needs more iterations than were enqueued
             const int ms = h.stall_m;

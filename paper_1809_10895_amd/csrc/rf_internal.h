@@ -184,5 +184,13 @@ hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStr
                        int nprod = -1);
 hipError_t launch_copy_active(const Geo &g, const Arrays &a, const double *src, double *dst,
                               hipStream_t s);
+// Zeroes `bytes` (a multiple of 4) at device address p with a kernel.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+// Host-side entry points shared by the C ABI's source files (rf_host.cpp).
+// The device of a context, and the binding of a device workspace of `bytes`
+// at dev_ptr (what rf_bind_workspace does after its argument checks).
+int ctx_device(const rf_ctx *c);
+rf_status ctx_bind(rf_ctx *c, void *dev_ptr, size_t bytes);
 
 }  // namespace rf

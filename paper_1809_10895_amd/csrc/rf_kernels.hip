@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "rf_internal.h"
@@ -1824,6 +1825,15 @@ __global__ void __launch_bounds__(kThreads) k_copy_active(Geo g, Arrays a, const
 }
 
 // Combines the nblk partials of a producer into slot `out` (in values of NV).
+// Zeroes n 32-bit words (a kernel rather than a memset, so that the work
+// stays a kernel node when a caller captures the stream into a graph).
+__global__ void __launch_bounds__(kThreads) k_zero(uint32_t *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kThreads)
+        p[i] = 0u;
+}
+
 template <int NV, unsigned MAXMASK>
 __global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk, int out)
 {
@@ -2066,6 +2076,14 @@ hipError_t launch_fold(const Geo &g, double *P, int nv, unsigned maxmask, hipStr
     case 7 * 16 + 0: RF_LAUNCH_N(1, (k_fold<7, 0u>), P, nprod, g.foff);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / sizeof(uint32_t);
+    if (n == 0) return hipSuccess;
+    const size_t nb = std::min<size_t>((n + kThreads - 1) / kThreads, 4096);
+    RF_LAUNCH_N(nb, k_zero, (uint32_t *)p, n);
 }
 
 hipError_t launch_copy_active(const Geo &g, const Arrays &a, const double *src, double *dst,

@@ -42,6 +42,7 @@ def test_default_options_host_only():
     assert o["precision"] == 0 and o["cg_rel_tol"] == 0.0
     assert (o["picard_variant"], o["first_iterate"], o["zline_refactor"]) == (0, 0, 0)
     assert o["host_wait"] == 0
+    assert o["stencil"] == 2 and o["tile_rows"] == 0          # RF_STENCIL_AUTO, tiles chosen
 
 
 def test_null_arguments_rejected_without_gpu():
@@ -51,6 +52,7 @@ def test_null_arguments_rejected_without_gpu():
     assert L.rf_setup_grid(None, 1, 1, 1, 1.0, 1.0, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_step(None, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_mass_balance(None, None) == binding.RF_ERR_ARG
+    assert L.rf_run_steps(None, 1.0, 1, None) == binding.RF_ERR_ARG
     assert L.rf_ens_create(None, 0, None) == binding.RF_ERR_ARG
     assert L.rf_ens_setup(None, 1, None, 0.01, 0, None) == binding.RF_ERR_ARG
     assert L.rf_ens_run(None, 1.0, None) == binding.RF_ERR_ARG
