@@ -229,6 +229,23 @@ rf_status rf_workspace_bytes(const rf_ctx *ctx, size_t *bytes);
  * workspace; uploads grid and soil tables into it. */
 rf_status rf_bind_workspace(rf_ctx *ctx, void *dev_ptr, size_t bytes);
 
+/* Size of the library's static workspace (rf_bind_static_workspace). */
+#define RF_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rf_bind_workspace
+ * with the library's own static workspace, a device array of
+ * RF_STATIC_WORKSPACE_BYTES (64 MiB) that each GPU holds from the library's
+ * load until the process ends.  Calls no hipMalloc or other allocating
+ * routine.  RF_ERR_NOMEM when the grid needs more than that (as
+ * rf_workspace_bytes says: about 144 bytes per cell in FP64, so up to about
+ * 4.4e5 cells).  Every context bound this way on one GPU shares that GPU's
+ * array: binding clears what must start at zero, but work of two such
+ * contexts that overlaps in time on one GPU races, and a context's state is
+ * lost when another one binds; rf_set_state again after any other context
+ * has bound it. */
+rf_status rf_bind_static_workspace(rf_ctx *ctx);
+
 /* Sets h^n from h_dev (device, N doubles) at time t; resets the water-balance
  * accumulators and the EBATS state.  RF_ERR_NONFINITE if an active cell of
  * h_dev is not finite (the state is then unchanged). */

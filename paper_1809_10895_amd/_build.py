@@ -5,8 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRCS = [os.path.join(HERE, "csrc", f) for f in
-        ("rf_kernels.hip", "rf_host.cpp", "rf_ensemble.hip", "rf_ensemble_host.cpp", "rf_guess.hip",
-         "rf_guess_host.cpp")]
+        ("rf_kernels.hip", "rf_host.cpp", "rf_noalloc.hip", "rf_ensemble.hip", "rf_ensemble_host.cpp",
+         "rf_guess.hip", "rf_guess_host.cpp")]
 LIB = os.path.join(HERE, "librf_mi355x.so")
 
 # -packed-fp32-ops keeps the compiler from emitting packed FP32 VALU forms.

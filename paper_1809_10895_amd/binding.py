@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "RF_OK", -1: "RF_ERR_ARG", -2: "RF_ERR_STATE", -3: "RF_ERR_HI
 EXPORTS = ["rf_default_options", "rf_create", "rf_destroy", "rf_last_error", "rf_setup_grid",
            "rf_set_soil", "rf_set_bc", "rf_set_forcing", "rf_set_options", "rf_workspace_bytes",
            "rf_bind_workspace", "rf_set_state", "rf_get_state", "rf_step", "rf_run",
-           "rf_run_steps", "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
+           "rf_run_steps", "rf_bind_static_workspace", "rf_mass_balance", "rf_eval_soil", "rf_assemble", "rf_apply_operator",
            "rf_apply_precond", "rf_set_timing", "rf_select_timing", "rf_get_timing",
            # include/rf_ensemble.h
            "rf_ens_create", "rf_ens_destroy", "rf_ens_last_error", "rf_ens_setup", "rf_ens_set_bc",
@@ -139,6 +139,7 @@ def load_library(path: str = LIB):
     L.rf_step.argtypes = [vp, dp, vp, C.POINTER(RfStepStats)]
     L.rf_run.argtypes = [vp, dp, C.POINTER(RfRunStats)]
     L.rf_run_steps.argtypes = [vp, dp, C.c_long, C.POINTER(RfRunStats)]
+    L.rf_bind_static_workspace.argtypes = [vp]
     L.rf_mass_balance.argtypes = [vp, C.POINTER(RfMass)]
     L.rf_eval_soil.argtypes = [vp, vp, vp, vp, vp]
     L.rf_assemble.argtypes = [vp, vp, dp, vp, vp]
@@ -294,6 +295,11 @@ class Solver:
         nbytes = self.workspace_bytes()
         self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
         self._check(self.L.rf_bind_workspace(self.h, _ptr(self.ws), nbytes))
+
+    def bind_static(self):
+        """rf_bind_static_workspace: the library's own static workspace; returns the status."""
+        self.ws = None
+        return self.L.rf_bind_static_workspace(self.h)
 
     # --- state --------------------------------------------------------------
     def set_state(self, h, t=0.0):

@@ -52,6 +52,7 @@ def test_null_arguments_rejected_without_gpu():
     assert L.rf_setup_grid(None, 1, 1, 1, 1.0, 1.0, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_step(None, 1.0, None, None) == binding.RF_ERR_ARG
     assert L.rf_mass_balance(None, None) == binding.RF_ERR_ARG
+    assert L.rf_bind_static_workspace(None) == binding.RF_ERR_ARG
     assert L.rf_run_steps(None, 1.0, 1, None) == binding.RF_ERR_ARG
     assert L.rf_ens_create(None, 0, None) == binding.RF_ERR_ARG
     assert L.rf_ens_setup(None, 1, None, 0.01, 0, None) == binding.RF_ERR_ARG
