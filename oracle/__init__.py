@@ -107,6 +107,7 @@ def lib():
         L.orc_storage.restype = C.c_double
         L.orc_storage.argtypes = [vp, vp]
         L.orc_set_slabs.argtypes = [vp, C.c_int]
+        L.orc_picard_iterate.argtypes = [vp, vp, C.c_double, C.c_int, vp]
         L.orc_threads.restype = C.c_int
         L.orc_threads.argtypes = []
         L.orc_time.restype = C.c_double
@@ -239,6 +240,15 @@ class Problem:
         g = None if guess is None else np.ascontiguousarray(guess, np.float64).ravel()
         s = lib().orc_step(self.h, float(dt), _ptr(g), C.byref(st))
         return s, step_stats_dict(st)
+
+    def picard_iterate(self, hn, dt, m):
+        """The Picard iterate h^m of a step of size dt from the state hn (at
+        the problem's current time): the iterates the step takes, state
+        unchanged."""
+        hn = np.ascontiguousarray(hn, np.float64).ravel()
+        out = np.empty(self.N)
+        lib().orc_picard_iterate(self.h, _ptr(hn), float(dt), int(m), _ptr(out))
+        return out
 
     def run(self, t_end):
         rs = RunStats()

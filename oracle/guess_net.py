@@ -158,3 +158,41 @@ def init_params(seed=0, scale_out=0.0):
         p[wo:bo] = rng.normal(0.0, sd, bo - wo)
         p[bo:bo + COUT[l]] = rng.normal(0.0, 0.05, COUT[l])
     return p
+
+
+def loss_grad_abs(params, hn, hprev, lnks, rain, target, shape):
+    """loss_and_grad with the BF16 roundings (rnd=True), and for every
+    parameter the sum of the magnitudes of the terms its gradient adds up:
+    sum over cells of |d| |x| for a weight, of |d| for a bias.  A difference
+    between two evaluations that round their operands to BF16 (2^-8 relative)
+    and add in different orders is bounded by a few 2^-8 times that sum."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    f = features(hn, hprev, lnks, rain, shape)
+    Ws, bs = unpack(params, True)
+    y, xs = forward(params, f, True)
+    r = (first_iterate(hn, hprev, y.reshape(-1)).reshape(ny, nx, nz)
+         - np.asarray(target).reshape(ny, nx, nz)) / OUT_SCALE
+    loss = 0.5 * np.sum(r * r) / N
+    d = bf16((r / N)[..., None])
+    grad, mag = np.zeros(NPARAMS), np.zeros(NPARAMS)
+    for l in (3, 2, 1, 0):
+        wo, bo = OFFSETS[l]
+        grad[wo:bo] = conv_weight_grad(xs[l], d).reshape(-1)
+        mag[wo:bo] = conv_weight_grad(np.abs(xs[l]), np.abs(d)).reshape(-1)
+        grad[bo:bo + COUT[l]] = d.reshape(-1, COUT[l]).sum(0)
+        mag[bo:bo + COUT[l]] = np.abs(d).reshape(-1, COUT[l]).sum(0)
+        if l > 0:
+            d = bf16(conv_transpose(d, Ws[l]) * (xs[l] > 0))
+    return loss, grad, mag
+
+
+def predict_abs(params, hn, hprev, lnks, rain, shape):
+    """The network output y (BF16 roundings) and, per cell, the sum of the
+    magnitudes of the terms of the output layer: sum over taps and channels of
+    |W| |x| plus |b|."""
+    Ws, bs = unpack(params, True)
+    y, xs = forward(params, features(hn, hprev, lnks, rain, shape), True)
+    mag = conv(np.abs(xs[3]), np.abs(Ws[3]))[..., 0] + abs(bs[3][0])
+    return y.reshape(-1), mag.reshape(-1)
+

@@ -718,8 +718,20 @@ static void free_system(orc_system *S)
  * h^{m+1} by DIC-PCG started from h^m, delta = max|h^{m+1}-h^m| over active
  * cells; converged when delta < tol_picard.  On success the state advances
  * and the water balance is updated; on failure the state is untouched. */
+static int picard_loop(orc_problem *P, double dt, const double *guess, int max_picard,
+                       orc_step_stats *st, int stop_after, double *h_out);
+
 static int picard_step(orc_problem *P, double dt, const double *guess, int max_picard,
                        orc_step_stats *st)
+{
+    return picard_loop(P, dt, guess, max_picard, st, 0, NULL);
+}
+
+/* The Picard loop of picard_step.  With stop_after > 0 the loop stops after
+ * that many iterations (or earlier, on convergence or failure), copies the
+ * last iterate into h_out and leaves the state untouched. */
+static int picard_loop(orc_problem *P, double dt, const double *guess, int max_picard,
+                       orc_step_stats *st, int stop_after, double *h_out)
 {
     size_t N = ncell(P);
     memset(st, 0, sizeof(*st));
@@ -753,6 +765,12 @@ static int picard_step(orc_problem *P, double dt, const double *guess, int max_p
         memcpy(hm, x, sizeof(double) * N);
         if (!finite) { status = ORC_ERR_NONFINITE; break; }
         if (delta < P->opt.tol_picard) { status = ORC_OK; break; }
+        if (stop_after > 0 && m + 1 >= stop_after) break;
+    }
+    if (stop_after > 0) {
+        memcpy(h_out, hm, sizeof(double) * N);
+        free(hm); free(x); free_system(&S);
+        return status;
     }
     if (status == ORC_OK) {
         boundary_inflow(P, hm, S.K, dt, P->t, P->inflow);
@@ -769,6 +787,25 @@ static int picard_step(orc_problem *P, double dt, const double *guess, int max_p
 int orc_step(orc_problem *P, double dt, const double *guess, orc_step_stats *st)
 {
     return picard_step(P, dt, guess, P->opt.max_picard, st);
+}
+
+/* The Picard iterate h^m of a step of size dt from the state hn at the
+ * current time (the iterates of orc_step, for inspection): m >= 1 Picard
+ * iterations from h^(0) = hn, fewer if the loop converges first.  The
+ * problem's state is left as it was. */
+int orc_picard_iterate(orc_problem *P, const double *hn, double dt, int m, double *out)
+{
+    if (m < 1 || !(dt > 0.0)) return ORC_ERR_ARG;
+    const size_t N = ncell(P);
+    double *saved = P->h;
+    double *start = (double *)malloc(sizeof(double) * N);
+    memcpy(start, hn, sizeof(double) * N);
+    P->h = start;
+    orc_step_stats st;
+    const int s = picard_loop(P, dt, NULL, m, &st, m, out);
+    P->h = saved;
+    free(start);
+    return s;
 }
 
 /* End of the forcing segment that contains t (infinity if none). */

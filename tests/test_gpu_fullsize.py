@@ -11,13 +11,18 @@ the oracle does in seconds:
 4. one GPU step of 60 s: its heads are a fixed point of the oracle's Picard
    map to within the Picard tolerance, and its water balance closes to the
    bound the chord scheme implies; the same with the PCG in FP32 under the
-   FP64 Picard loop (the benchmark's mixed-precision options).
+   FP64 Picard loop (the benchmark's mixed-precision options);
+5. one step of 60 s at the benchmark's FP64 options (PCG tolerance 1e-8 m)
+   against the oracle's own step, run here in its slab mode on every host
+   thread (block-Jacobi DIC over sub-domains of whole y-rows, the 'simple'
+   decomposition of Sec. 2.3; a few seconds): the same number of Picard
+   iterations and every active head within 1e-8 relative.
 """
 import numpy as np
 import pytest
 
 from paper_1809_10895_amd import workloads as W
-from tests.common import make_oracle, make_solver
+from tests.common import make_oracle, make_solver, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -126,3 +131,26 @@ def fixed_point_checks(w, P, S):
     assert abs(mb["error"]) <= bound
     # storage against the oracle's own sum of V theta~(h1)
     assert mb["storage"] == pytest.approx(P.storage(h1), rel=1e-12)
+
+
+def test_watershed_full_size_step_matches_oracle_at_bench_options(ws, orc):
+    """Both sides solve each Picard system to max |r / diag| <= 1e-8 m with
+    different preconditioners (z-line on the GPU, block DIC in the oracle), so
+    their heads differ by the solves' errors, a small multiple of 1e-8 m
+    (measured 4.5e-9 m, 2.1e-9 relative); the Picard loop and its count are
+    the same."""
+    w, _, _ = ws
+    S = make_solver(w, precond=1, tol_cg=1e-8)
+    s_g, st_g = S.step(w.dt)
+    assert s_g == 0, S.last_error()
+    P = make_oracle(orc, w, tol_cg=1e-8)
+    P.set_slabs(max(1, min(orc.threads(), w.ny)))
+    s_o, st_o = P.step(w.dt)
+    assert s_o == 0
+    assert st_g["picard_iters"] == st_o["picard_iters"], (st_g["delta"], st_o["delta"])
+    m = w.active_mask()
+    h_o, _ = P.get_state()
+    err = rel_err(host(S.get_state()[0]), h_o, m)
+    print("watershed step at tol_cg 1e-8: relative head difference %.3e" % err)
+    assert err <= 1e-8
+

@@ -5,26 +5,32 @@ In mixed precision the soil coefficients, the Picard residual b - A h^m and
 h stay FP64; the PCG solve of each increment runs on FP32 vectors and FP32
 copies of the operator and preconditioner.  Each Picard iteration then acts
 as one step of iterative refinement, so the converged state differs from the
-FP64 one only through where the Picard loop stops: both sides stop once
-max|h^{m+1} - h^m| <= tol_picard, and the remaining distance to the discrete
-solution is of the order of tol_picard times rho / (1 - rho) for the Picard
-contraction rate rho (at most ~0.5 on these workloads; the FP32 solve adds a
-relative error ~cg_rel_tol to increments already below tol_picard).  The
-bound used is therefore an absolute 10 * tol_picard on h after every step,
-Picard counts within one of the oracle's, and the water balance closed to
-the same level.
+FP64 one only through the error of the solves: every Picard iteration
+recomputes the residual in FP64 at the current iterate, so an FP32 solve's
+error is corrected by the next iteration, and the state where the loop stops
+carries only the error of the last solve.  That solve stops once
+max |r / diag| has fallen by cg_rel_tol (1e-6) from its start, i.e. it
+leaves a relative error of about cg_rel_tol times the condition of the
+Jacobi-scaled operator (order 10 here) on an increment that is itself near
+tol_picard: about 1e-6 * 10 * 1e-5 m = 1e-10 m, and the bar is 1e-9 m on
+every head after every step (measured: 4.8e-13 m on the column, 2.5e-11 m
+on the hillslope slice).  Picard counts may differ by one where a delta
+straddles tol_picard; the water balance closes to the same level.  With the
+benchmark's options (absolute PCG test at 1e-8 m, no relative test) the
+error of the last solve is that of the FP64 path at the same tolerance, and
+the bar is the FP64 one, 1e-8 relative.
 """
 import numpy as np
 import pytest
 
 from paper_1809_10895_amd import workloads as W
-from tests.common import make_oracle, make_solver
+from tests.common import make_oracle, make_solver, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL_PICARD = 1e-6
-H_TOL = 10 * TOL_PICARD          # metres, see the module docstring
+H_TOL = 1e-9                     # metres, see the module docstring
 MIXED = dict(precision=1, tol_cg=1e-11, cg_rel_tol=1e-6)
 
 
@@ -102,7 +108,8 @@ def test_mixed_hillslope_full_size_bench_configuration(orc):
     assert abs(st_g["picard_iters"] - st_o["picard_iters"]) <= 1
     m = w.active_mask()
     h_o, _ = P.get_state()
-    assert np.abs(host(S.get_state()[0])[m] - h_o[m]).max() <= H_TOL
+    # measured 6.4e-10 m, the same as the FP64 path at tol_cg 1e-8
+    assert rel_err(host(S.get_state()[0]), h_o, m) <= 1e-8
 
 
 def test_mixed_is_deterministic():

@@ -119,11 +119,16 @@ def lockstep_ebats(orc, w, tol_picard=1e-6, max_flips=3, **opts):
     (Sec. 2.3) from the oracle's Picard counts.  Every step must give the
     same Picard count (or the same rejection) and heads within 1e-8.  A
     step whose count differs is accepted only at a borderline stopping
-    decision: at the first iteration where the two sides part, one delta is
-    below tol_picard and the other above, both within 5 % of it (a Picard
-    iterate sitting on a kink of the coefficients, such as h = 0, turns
-    rounding-level differences into a few per cent of delta).  The GPU is then
-    re-started from the oracle's state; at most max_flips such steps."""
+    decision at the kink of the coefficients at h = 0: at the first
+    iteration k where the two sides part, one delta is below tol_picard and
+    the other above, both within 5 % of it, the earlier deltas agree to
+    1e-8, and the cell that carries the oracle's deciding delta (the largest
+    change from its iterate h^k to h^{k+1}) lies within 10 tol_picard of
+    h = 0 at h^n, h^k or h^{k+1}.  There the retention curve is not smooth:
+    the capacity jumps to S at saturation, and below it its slope grows
+    without bound (dC/dh ~ |h|^(n-2) for n < 2), so rounding-level
+    differences become a few per cent of delta.  The GPU is then re-started
+    from the oracle's state; at most max_flips such steps."""
     import torch
     assert not w.forcing
     o = dict(ebats=0, max_picard=8, tol_picard=tol_picard, **opts)
@@ -133,6 +138,7 @@ def lockstep_ebats(orc, w, tol_picard=1e-6, max_flips=3, **opts):
     t, dt, easy, flips, steps, rejected = 0.0, w.dt, 0, 0, 0, 0
     while t < w.t_end * (1 - 1e-15) - 1e-12:
         d = min(dt, w.t_end - t)
+        h_before, _ = P.get_state()
         s_o, st_o = P.step(d)
         s_g, st_g = S.step(d)
         steps += 1
@@ -144,6 +150,12 @@ def lockstep_ebats(orc, w, tol_picard=1e-6, max_flips=3, **opts):
             assert all(abs(do[i] - dg[i]) <= 1e-8 * do[i] for i in range(k)), (steps, do, dg)
             assert abs(do[k] - tol_picard) <= 0.05 * tol_picard, (steps, k, do, dg)
             assert abs(dg[k] - tol_picard) <= 0.05 * tol_picard, (steps, k, do, dg)
+            h_k = h_before if k == 0 else P.picard_iterate(h_before, d, k)
+            h_k1 = P.picard_iterate(h_before, d, k + 1)
+            c = int(np.argmax(np.where(m, np.abs(h_k1 - h_k), -1.0)))
+            assert np.abs(h_k1[c] - h_k[c]) == do[k], (steps, k, c)
+            near = min(abs(h_before[c]), abs(h_k[c]), abs(h_k1[c]))
+            assert near <= 10 * tol_picard, (steps, k, c, h_before[c], h_k[c], h_k1[c])
             flips += 1
             assert flips <= max_flips, steps
             h_o, t_o = P.get_state()

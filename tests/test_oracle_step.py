@@ -262,3 +262,25 @@ def test_forcing_segments(orc):
     assert P.run(6000.0)[0] == 0
     expected = 500 * 2e-6 + 2000 * 5e-7
     assert P.mass_balance()["inflow"][orc.ZMAX] == pytest.approx(expected, rel=1e-12)
+
+
+def test_picard_iterates_reproduce_the_step(orc):
+    """The iterates exposed for inspection are the step's own: the last one is
+    the accepted state, and their successive differences are the deltas the
+    step reports."""
+    soil = SOILS["column100"]
+    P = column(orc, 100, 0.01, soil)
+    P.set_bc(orc.ZMAX, orc.DIRICHLET, -0.75)
+    P.set_bc(orc.ZMIN, orc.FREE_DRAINAGE)
+    P.set_options(tol_picard=1e-6, tol_cg=1e-13, ebats=0, dt0=10.0)
+    h0 = np.full(100, -10.0)
+    P.set_state(h0)
+    s, st = P.step(10.0)
+    assert s == 0 and st["picard_iters"] >= 3
+    h1, _ = P.get_state()
+    P.set_state(h0)
+    its = [h0] + [P.picard_iterate(h0, 10.0, m) for m in range(1, st["picard_iters"] + 1)]
+    assert np.array_equal(its[-1], h1)
+    for m in range(st["picard_iters"]):
+        assert np.abs(its[m + 1] - its[m]).max() == st["delta"][m]
+    assert np.array_equal(P.get_state()[0], h0)          # state untouched
