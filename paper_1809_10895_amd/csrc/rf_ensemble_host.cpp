@@ -383,7 +383,10 @@ static rf_status ens_run(rf_ens *e, double t_end, rf_ens_summary *out)
 // the GPU after other GPU work in the same process, with no fault reported,
 // and that cause has not been shown.  Until it is, rf_ens_run and
 // rf_ens_autotune refuse to launch it.
-static const bool kEnsRunEnabled = false;
+#ifndef RF_ENS_RUN_ENABLED
+#define RF_ENS_RUN_ENABLED 0   /* 1 only in the CPU emulation build of the tests */
+#endif
+static const bool kEnsRunEnabled = RF_ENS_RUN_ENABLED != 0;
 static const char *kEnsRunOff =
     "the column-ensemble run kernel is switched off: its launches did not return on the GPU "
     "and the cause has not been shown";

@@ -42,7 +42,8 @@ __device__ __forceinline__ double dpp(double x, double old)
     const long long xi = __double_as_longlong(x), oi = __double_as_longlong(old);
     const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)xi, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(xi >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                            (unsigned int)lo));
 }
 
 // Value of lane L (wave-uniform result).
@@ -58,7 +59,8 @@ __device__ __forceinline__ double lane_value(double x)
     const long long xi = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)xi, L);
     const int hi = __builtin_amdgcn_readlane((int)(xi >> 32), L);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                            (unsigned int)lo));
 }
 
 // x of lane i - 1 (lane 0 gets `edge`) and of lane i + 1 (lane 63 gets `edge`).

@@ -1,0 +1,125 @@
+"""The library's HIP sources run on the CPU: tests/simt compiles the kernels
+and host code of the 3-D solver and of the column ensemble as host C++ on a
+SIMT emulator (one fiber per lane, wavefront operations as lane
+rendezvous) under AddressSanitizer and UndefinedBehaviorSanitizer, and
+these tests compare what that build computes with the oracle.
+
+For the ensemble this is the parity evidence that the GPU cannot give while
+its launches stay switched off: the same inputs as the ensemble's GPU tests
+(ragged lengths at every boundary of the blocked layout under EBATS, a
+column that fails beside columns that finish, modified Picard, a run split
+in two launches) give per-column accepted, rejected and Picard counts equal
+to the oracle's, heads within 1e-8, and no sanitizer report."""
+import os
+import shutil
+
+import numpy as np
+import pytest
+
+import oracle as orc_mod
+from paper_1809_10895_amd import workloads as W
+from tests.common import make_oracle, rel_err
+from tests.simt import build as simt_build
+from tests.simt import cases
+from tests.test_zz_gpu_ensemble import EDGE_LENGTHS, oracle_column, small_ensemble
+
+pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+
+
+@pytest.fixture(scope="module")
+def exe():
+    return simt_build.build()
+
+
+def _ens(exe, tmp_path, w, t_ends, **opts):
+    path = os.path.join(str(tmp_path), "ens.txt")
+    cases.ens_case(path, w, t_ends, **opts)
+    return cases.run(exe, "ens", path, timeout=600)
+
+
+def _check_columns(w, out, oracle_runs):
+    off = w.offsets
+    for c in range(w.ncol):
+        s, rs, h_o, mb = oracle_runs(c)
+        r = out["cols"][c]
+        assert (r["accepted"], r["rejected"], r["picard_total"]) == \
+            (rs["accepted"], rs["rejected"], rs["picard_total"]), (c, r, rs)
+        assert (r["status"] == 0) == (s == 0), (c, r["status"], s)
+        h = out["h"][off[c]:off[c] + w.lengths[c]]
+        assert np.abs(h - h_o).max() <= 1e-8 * max(np.abs(h_o).max(), 1.0), c
+        if mb is not None:
+            assert r["storage"] == pytest.approx(mb["storage"], rel=1e-10), c
+            assert r["inflow_top"] == pytest.approx(mb["inflow"][W.ZMAX], rel=1e-8, abs=1e-15), c
+            assert r["inflow_bottom"] == pytest.approx(mb["inflow"][W.ZMIN], rel=1e-8,
+                                                       abs=1e-15), c
+
+
+def test_solver_emulated_matches_oracle(exe, tmp_path):
+    """Two fixed 600 s steps of a masked 10 x 6 x 20 watershed, with the
+    tiled and the column stencil kernels: the emulated library takes the
+    oracle's Picard iterations and reaches its heads."""
+    w = W.watershed(nx=10, ny=6, nz=20, kmin=10)
+    w.h0 = np.where(w.active_mask(), -1.5, 0.0)
+    P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
+    its = [P.step(600.0)[1]["picard_iters"] for _ in range(2)]
+    h_o, _ = P.get_state()
+    for stencil in (1, 0):            # RF_STENCIL_TILES, RF_STENCIL_COLUMNS
+        path = os.path.join(str(tmp_path), "solver%d.txt" % stencil)
+        cases.solver_case(path, w, 2, 600.0, stencil=stencil)
+        out = cases.run(exe, "solver", path, timeout=600)
+        assert [s["status"] for s in out["steps"]] == [0, 0]
+        assert [s["picard_iters"] for s in out["steps"]] == its
+        assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-10
+
+
+def test_ensemble_ragged_lengths_under_ebats(exe, tmp_path):
+    w = small_ensemble(EDGE_LENGTHS)
+    out = _ens(exe, tmp_path, w, [w.t_end])
+    assert out["runs"][0]["status"] == 0 and out["runs"][0]["failed"] == 0
+    _check_columns(w, out, lambda c: oracle_column(orc_mod, w, c, w.t_end))
+
+
+def test_ensemble_failed_column_is_isolated(exe, tmp_path):
+    w = small_ensemble([120, 200, 90], seed=7, t_end=300.0)
+    w.soil[1, 2:5] = [0.5, 3.0, 1e-4]
+    w.ebats = False
+    out = _ens(exe, tmp_path, w, [w.t_end])
+    assert out["runs"][0]["status"] == -5 and out["runs"][0]["failed"] == 1
+    _check_columns(w, out, lambda c: oracle_column(orc_mod, w, c, w.t_end))
+    assert [r["status"] for r in out["cols"]] == [0, -5, 0]
+
+
+def test_ensemble_modified_picard(exe, tmp_path):
+    w = small_ensemble([40, 64, 65, 200], seed=4)
+    out = _ens(exe, tmp_path, w, [w.t_end], picard_variant=1)
+    assert out["runs"][0]["status"] == 0
+    _check_columns(w, out, lambda c: oracle_column(orc_mod, w, c, w.t_end, picard_variant=1))
+
+
+def test_ensemble_second_launch_continues(exe, tmp_path):
+    """Two launches (to t/2, then t) end where the oracle does when it runs
+    each column in the same two pieces."""
+    w = small_ensemble([80, 160, 320], seed=8)
+    t1 = 0.5 * w.t_end
+    out = _ens(exe, tmp_path, w, [t1, w.t_end])
+    assert [r["status"] for r in out["runs"]] == [0, 0]
+
+    def two_pieces(c):
+        L, soil, h0 = w.column(c)
+        P = orc_mod.Problem(1, 1, L, 1.0, 1.0, w.dz)
+        P.set_soil(np.array([soil]))
+        for face, kind, value in w.bcs:
+            P.set_bc(face, kind, value)
+        P.set_options(tol_picard=1e-6, max_picard=50, dt0=w.dt, dt_max=w.dt_max,
+                      ebats=int(w.ebats), tol_cg=1e-13, max_cg=1000)
+        P.set_state(h0)
+        tot = dict(accepted=0, rejected=0, picard_total=0)
+        for t in (t1, w.t_end):
+            s, rs = P.run(t)
+            assert s == 0
+            for k in tot:
+                tot[k] += rs[k]
+        h, _ = P.get_state()
+        return 0, tot, h, None
+
+    _check_columns(w, out, two_pieces)
