@@ -66,8 +66,46 @@ __device__ __forceinline__ float dpp_quad_xor2(float x)
 // CIN: stored input channels (8 or 32); COB: output blocks of 16 channels (1
 // or 2).  EPI_RELU: out = bf16(relu(acc + bias)); EPI_MASK: out = bf16(acc)
 // where mask > 0, else 0 (gradient through a ReLU).
+//
+// The patch is held in LDS as planes of one 16-byte channel chunk over the
+// z-run of a column ([column][chunk][z]), so the sixteen lanes that read one
+// MFMA operand row (sixteen consecutive cells of one chunk) read 256
+// consecutive bytes: no bank conflicts.  (Channels-last order would put them
+// 64 bytes apart, a four-way conflict on every operand read.)  Staging issues
+// all of a thread's global loads before its first LDS write, so the block
+// waits for one memory round trip instead of one per chunk.
 constexpr int PX = 4, PY = 2, TX = PX + 2, TY = PY + 2, TZ = 64 + 2;
 constexpr int kTileThreads = 64 * PX * PY;
+
+// Patch staging: element e of the patch (chunk fastest, then z, then
+// column, i.e. the order of global memory) -> its 16 bytes, zero outside the
+// grid.  PLANES: LDS index in [column][chunk][z] order, else e itself.
+template <int CH, bool PLANES>
+__device__ __forceinline__ void stage_patch(const NetGeo &g, const bf16 *__restrict__ in, int px0,
+                                            int py0, int z0, bf16x8 *sT)
+{
+    constexpr int NST = TX * TY * TZ * CH;
+    constexpr int PER = (NST + kTileThreads - 1) / kTileThreads;
+    bf16x8 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int e = threadIdx.x + u * kTileThreads;
+        const int part = e % CH, cz = e / CH;
+        const int zl = cz % TZ, cl = cz / TZ;
+        const int i = px0 - 1 + cl % TX, j = py0 - 1 + cl / TX, k = z0 - 1 + zl;
+        const bool ok = e < NST && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const long cell = (long)k + (long)g.nz * ((long)i + (long)g.nx * j);
+        v[u] = ok ? *reinterpret_cast<const bf16x8 *>(in + cell * (8 * CH) + 8 * part) : zero8();
+    }
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int e = threadIdx.x + u * kTileThreads;
+        if (e >= NST) break;
+        const int part = e % CH, cz = e / CH;
+        const int zl = cz % TZ, cl = cz / TZ;
+        sT[PLANES ? (cl * CH + part) * TZ + zl : e] = v[u];
+    }
+}
 
 template <int CIN, int COB, int EPI>
 __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__restrict__ in,
@@ -86,15 +124,21 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
     const int pxy = blockIdx.x / g.zt;
     const int px0 = (pxy % pxn) * PX, py0 = (pxy / pxn) * PY, z0 = zti * 64;
     const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
-    for (int e = threadIdx.x; e < NPK; e += kTileThreads) sW[e] = wv[e];
-    for (int e = threadIdx.x; e < TX * TY * TZ * CH; e += kTileThreads) {
-        const int part = e % CH, cz = e / CH;
-        const int zl = cz % TZ, cl = cz / TZ;
-        const int i = px0 - 1 + cl % TX, j = py0 - 1 + cl / TX, k = z0 - 1 + zl;
-        const bool ok = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
-        const long cell = (long)k + (long)g.nz * ((long)i + (long)g.nx * j);
-        sT[e] = ok ? *reinterpret_cast<const bf16x8 *>(in + cell * CIN + 8 * part) : zero8();
+    {
+        constexpr int PW = (NPK + kTileThreads - 1) / kTileThreads;
+        bf16x8 w[PW];
+#pragma unroll
+        for (int u = 0; u < PW; u++) {
+            const int e = threadIdx.x + u * kTileThreads;
+            w[u] = e < NPK ? wv[e] : zero8();
+        }
+#pragma unroll
+        for (int u = 0; u < PW; u++) {
+            const int e = threadIdx.x + u * kTileThreads;
+            if (e < NPK) sW[e] = w[u];
+        }
     }
+    stage_patch<CH, true>(g, in, px0, py0, z0, sT);
     (void)pyn;
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -123,7 +167,7 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const int zl = 16 * t + n + 1 + dk;
-            B[t] = tok ? sT[(cl * TZ + zl) * CH + part] : zero8();
+            B[t] = tok ? sT[(cl * CH + part) * TZ + zl] : zero8();
         }
 #pragma unroll
         for (int t = 0; t < 4; t++)
@@ -183,14 +227,7 @@ __global__ void __launch_bounds__(kTileThreads) k_conv_out(NetGeo g, const bf16 
     // channels 8q..8q+7 of output channel 0 at tap s
     const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
     for (int e = threadIdx.x; e < kTaps * CH; e += kTileThreads) sW[e] = wv[(e / CH) * 64 + 16 * (e % CH)];
-    for (int e = threadIdx.x; e < TX * TY * TZ * CH; e += kTileThreads) {
-        const int part = e % CH, cz = e / CH;
-        const int zl = cz % TZ, cl = cz / TZ;
-        const int i = px0 - 1 + cl % TX, j = py0 - 1 + cl / TX, k = z0 - 1 + zl;
-        const bool ok = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
-        const long cell = (long)k + (long)g.nz * ((long)i + (long)g.nx * j);
-        sT[e] = ok ? *reinterpret_cast<const bf16x8 *>(in + cell * CIN + 8 * part) : zero8();
-    }
+    stage_patch<CH, false>(g, in, px0, py0, z0, sT);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;

@@ -801,7 +801,7 @@ static rf_status enqueue_pairs(rf_ctx *c, StepRec &r, int m, int n)
     for (int i = 0; i < n; i++) {
         const int j = r.pairs_enq[mi]++;
         TIMED(c, r, K_SPMV, m, j, launch_spmv(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
-        TIMED(c, r, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, c->stream));
+        TIMED(c, r, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
     }
     return RF_OK;
 }
@@ -829,7 +829,7 @@ static rf_status enqueue_iteration(rf_ctx *c, StepRec &r, int m)
                                              c->opt.picard_variant, c->stream));
     const bool refactor = (m == 0) || c->opt.zline_refactor == RF_REFACTOR_EVERY;
     TIMED(c, r, K_RESID, m, -1,
-          launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), refactor, c->stream));
+          launch_resid(G, A, c->opt.precond, m, nullptr, mixed(c), refactor, cg_tol(c), c->stream));
     rf_status s = enqueue_pairs(c, r, m, std::max(1, c->pred_cg[mi]));
     if (s) return s;
     return enqueue_apply(c, r, m);
@@ -1218,7 +1218,7 @@ rf_status rf_assemble(rf_ctx *c, const double *hm_dev, double dt, double *diag_d
     HIPCHK(c, launch_step_begin(c->G, c->S, bc, c->A, hm_dev, 0.0, -1, c->stream));
     HIPCHK(c, launch_coeff(c->G, c->S, c->A, 0, dt, c->opt.chord_eps, c->opt.picard_variant,
                            c->stream));
-    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, true, c->stream));
+    HIPCHK(c, launch_resid(c->G, c->A, c->opt.precond, 0, rhs_dev, false, true, cg_tol(c), c->stream));
     if (diag_dev) HIPCHK(c, launch_copy_active(c->G, c->A, c->A.diag, diag_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->assembled = true;

@@ -156,13 +156,15 @@ struct CgTol {
 };
 
 // refactor: compute (and store) the z-line factors of this iteration's matrix;
-// otherwise the stored ones are used.
+// otherwise the stored ones are used.  The residual and update launchers add,
+// when consumers read folded partials, a one-block fold that also takes the
+// next spmv kernel's exit decision with the tolerances t.
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        bool mixed, bool refactor, hipStream_t s);
+                        bool mixed, bool refactor, const CgTol &t, hipStream_t s);
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
                        const CgTol &t, hipStream_t s);
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
-                         hipStream_t s);
+                         const CgTol &t, hipStream_t s);
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s);
 // track: also dh = h^{n+1} - h^n.  serial: the host's tag of the step,

@@ -934,9 +934,10 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
 // wave reads K and h^m of its share of the tile's slots and Dd, bst of its
 // own columns (masked by their active lengths), stages K and h^m in LDS, and
 // forms each of its TY interior columns with resid_column, whose arithmetic
-// is that of k_resid.  The step flags and the active lengths are read
-// together first, so that a launch past the end of the step stops after one
-// round trip and no lane above its column's top loads anything.  Three
+// is that of k_resid.  The step flags are read first, alone (scalar loads),
+// so that each block of a launch past the end of the step ends after that
+// one round trip, with no vector load in flight; then the active lengths,
+// so that no lane above its column's top loads anything.  Three
 // blocks fit a CU (LDS and the register bound), which hides the latency of
 // each block's two round trips better than fewer blocks walking several
 // tiles (measured).  Writes the (r.z, max|r/diag|) block partials of nblk_t
@@ -952,10 +953,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
     __shared__ double sK[Tl::NS][kWave];
     __shared__ int sKt[Tl::NS];
     const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
+    if (stop) return;
     RF_WAVE_IDS;
     TileCols<TY> tc;
     tc.fetch(g, a.ktop, blockIdx.x, w);
-    if (stop) return;
     double K[Tl::PER], h[Tl::PER], Dp[TY], bp[TY], tzs[TY], rds[TY];
 #pragma unroll
     for (int u = 0; u < Tl::PER; u++) {
@@ -1217,10 +1218,11 @@ __device__ __forceinline__ bool spmv_decide(Scalars *s, int j, const double (&to
 // and its one-column halo are read once into LDS as p_new = z + beta p_old
 // and K, every wave reading a share of the slots with the loads of all its
 // slots in flight together.  The step flags, the iteration count, the rho
-// slots, the solve's tolerance, the active lengths and this thread's share of
-// the last update's partials are read in one round trip first, so that a
-// launch past the end of the solve stops there and no lane above its column's
-// top loads anything.  Wave w forms q = A p for its TY interior columns from
+// slots and the solve's tolerance are read first, alone (scalar loads): each
+// block of a launch past the end of the solve (marked finished by the fold
+// after the last update) ends after that one round trip, with no vector load
+// in flight.  Then the active lengths and this thread's share of the last
+// update's partials, so that no lane above its column's top loads anything.  Wave w forms q = A p for its TY interior columns from
 // LDS, with the arithmetic per cell of k_spmv.  Three blocks fit a CU.
 // Writes p, q and the block partials of p.q (nblk_t blocks).
 template <int PRECOND, typename T, int TY>
@@ -1238,12 +1240,12 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     __shared__ int sKt[Tl::NS];
     const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
+    if (stop) return;
     RF_WAVE_IDS;
     TileCols<TY> tc;
     tc.fetch(g, a.ktop, blockIdx.x, w);
     double pv[2];
     gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
-    if (stop) return;
     const bool first = (j == 0);
     T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY];
 #pragma unroll
@@ -1844,6 +1846,28 @@ __global__ void __launch_bounds__(kThreads) k_fold(double *P, int nblk, int out)
         for (int i = 0; i < NV; i++) P[(size_t)out * NV + i] = tot[i];
 }
 
+// The fold of the (r.z, max|r/diag|) partials of a residual or update kernel
+// (into the slot `out` the next spmv kernel reads) that also takes that spmv
+// kernel's exit decision for PCG iteration j = iters (spmv_decide, with the
+// same inputs, so the spmv kernel's own decision repeats it).  A solve that
+// has converged is then marked finished before the spmv launch after its last
+// iteration starts, and that launch stops at its first read of the flags
+// instead of loading its tile.  Nothing is decided when the flags already
+// stop the solve (a producer that returned early leaves them as they were).
+__global__ void __launch_bounds__(kThreads) k_fold_decide(Arrays a, int nblk, int out, double tol_cg,
+                                                          double rel, int max_cg)
+{
+    double tot[2];
+    reduce_partials<2, 2u>(a.pr, nblk, tot);
+    if (threadIdx.x == 0) {
+        a.pr[(size_t)out * 2] = tot[0];
+        a.pr[(size_t)out * 2 + 1] = tot[1];
+        Scalars *s = a.sc;
+        if (!(s->done | s->fail | s->stall | s->picard_done))
+            (void)spmv_decide(s, s->iters, tot, s->tol_eff, tol_cg, rel, max_cg);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1904,6 +1928,27 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
         return launch_fold(g, P, nv, mask, s, g.nblk_t);                                \
     } while (0)
 
+// Folds the (r.z, max|r/diag|) partials of nprod blocks with the next spmv
+// kernel's exit decision (k_fold_decide) when consumers read a folded total;
+// otherwise the spmv kernel combines the partials and decides itself.
+static hipError_t launch_fold_decide(const Geo &g, const Arrays &a, int nprod, const CgTol &t,
+                                     hipStream_t s)
+{
+    if (g.np != 1 || g.foff == 0) return hipSuccess;
+    RF_LAUNCH_N(1, k_fold_decide, a, nprod, g.foff, t.tol_cg, t.rel, t.max_cg);
+}
+
+// A kernel writing (r.z, max|r/diag|) partials into a.pr from nb blocks, and
+// their fold with the decision; RF_LAUNCH_DECIDE_TILED for a tiled kernel.
+#define RF_LAUNCH_DECIDE(nb, kern, ...)                                                 \
+    do {                                                                                \
+        const int nb_ = (nb);                                                           \
+        const hipError_t e_ = [&]() { RF_LAUNCH_N(nb_, kern, __VA_ARGS__); }();           \
+        if (e_ != hipSuccess) return e_;                                                \
+        return launch_fold_decide(g, a, nb_, t, s);                                     \
+    } while (0)
+#define RF_LAUNCH_DECIDE_TILED(kern, ...) RF_LAUNCH_DECIDE(g.nblk_t, kern, __VA_ARGS__)
+
 hipError_t launch_check_finite(const Geo &g, const Arrays &a, const double *h, hipStream_t s)
 {
     RF_LAUNCH_FOLD(a.ps, 1, 0u, k_check_finite, g, a, h);
@@ -1941,39 +1986,39 @@ static CgVec<double> dvec(const Arrays &a)
 }
 
 hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, double *bout,
-                        bool mixed, bool refactor, hipStream_t s)
+                        bool mixed, bool refactor, const CgTol &t, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
     const int rf = refactor ? 1 : 0;
     if (g.tiled && g.tile_y == 2) {
         if (mixed && zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float, 2>), g, a, a.f, m, bout, rf);
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_ZLINE, float, 2>), g, a, a.f, m, bout, rf);
         if (mixed)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float, 2>), g, a, a.f, m,
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_JACOBI, float, 2>), g, a, a.f, m,
                             bout, rf);
         if (zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double, 2>), g, a, dvec(a), m,
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_ZLINE, double, 2>), g, a, dvec(a), m,
                             bout, rf);
-        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double, 2>), g, a, dvec(a), m,
+        RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_JACOBI, double, 2>), g, a, dvec(a), m,
                         bout, rf);
     }
     if (g.tiled) {
         if (mixed && zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, float, 4>), g, a, a.f, m, bout, rf);
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_ZLINE, float, 4>), g, a, a.f, m, bout, rf);
         if (mixed)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, float, 4>), g, a, a.f, m,
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_JACOBI, float, 4>), g, a, a.f, m,
                             bout, rf);
         if (zl)
-            RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_ZLINE, double, 4>), g, a, dvec(a), m,
+            RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_ZLINE, double, 4>), g, a, dvec(a), m,
                             bout, rf);
-        RF_LAUNCH_TILED(a.pr, 2, 2u, (k_resid_tile<RF_PRECOND_JACOBI, double, 4>), g, a, dvec(a), m,
+        RF_LAUNCH_DECIDE_TILED((k_resid_tile<RF_PRECOND_JACOBI, double, 4>), g, a, dvec(a), m,
                         bout, rf);
     }
     if (mixed && zl)
-        RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
-    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout, rf);
-    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m, bout, rf);
-    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_resid<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m, bout, rf);
+        RF_LAUNCH_DECIDE(g.nblk, (k_resid<RF_PRECOND_ZLINE, float>), g, a, a.f, m, bout, rf);
+    if (mixed) RF_LAUNCH_DECIDE(g.nblk, (k_resid<RF_PRECOND_JACOBI, float>), g, a, a.f, m, bout, rf);
+    if (zl) RF_LAUNCH_DECIDE(g.nblk, (k_resid<RF_PRECOND_ZLINE, double>), g, a, dvec(a), m, bout, rf);
+    RF_LAUNCH_DECIDE(g.nblk, (k_resid<RF_PRECOND_JACOBI, double>), g, a, dvec(a), m, bout, rf);
 }
 
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
@@ -2020,13 +2065,13 @@ hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, i
 }
 
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
-                         hipStream_t s)
+                         const CgTol &t, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
-    if (mixed && zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_ZLINE, float>), g, a, a.f, parity);
-    if (mixed) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_JACOBI, float>), g, a, a.f, parity);
-    if (zl) RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity);
-    RF_LAUNCH_FOLD(a.pr, 2, 2u, (k_update<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity);
+    if (mixed && zl) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, float>), g, a, a.f, parity);
+    if (mixed) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, float>), g, a, a.f, parity);
+    if (zl) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity);
+    RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity);
 }
 
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
