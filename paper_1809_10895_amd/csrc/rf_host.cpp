@@ -67,6 +67,7 @@ struct rf_ctx {
     double dx = 0, dy = 0, dz = 0;
     double gvec[3] = {0, 0, 1};
     std::vector<int32_t> ktop;
+    std::vector<int32_t> chunk;            // active-cell runs, 4 ints each (Arrays::chunk)
     long active = 0;
 
     int model = RF_VGM;
@@ -282,6 +283,7 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
     }
     a.layer = c->layer.empty() ? nullptr : (uint8_t *)take(N);
     a.ktop = (int32_t *)take(ncol * sizeof(int32_t));
+    a.chunk = (const int4 *)take(std::max<size_t>(c->chunk.size(), 4) * sizeof(int32_t));
     const size_t nb1 = max_partial_blocks(c) + 1;
     a.pr = (double *)take(nb1 * 2 * sizeof(double));
     a.pq = (double *)take(nb1 * sizeof(double));
@@ -299,6 +301,52 @@ static size_t layout(const rf_ctx *c, char *base, Arrays *A)
 
 // Launch shapes of the grid (see Geo).  Partial arrays are sized for one
 // column per wave, so changing the shape never changes the workspace layout.
+// The runs of kWave consecutive active cells (in column order, columns of
+// no active cell skipped) that the per-cell kernels give one wavefront each:
+// for run q, its first cell (column, k) and the lanes where it enters each
+// of the next three columns, l1 <= l2 <= l3 (65 when the run ends first);
+// lanes from l3 on walk the active lengths themselves.
+static void build_chunks(rf_ctx *c)
+{
+    const size_t ncol = c->ktop.size();
+    const long nchunk = (c->active + kWave - 1) / kWave;
+    c->chunk.assign((size_t)nchunk * 4, 0);
+    size_t col = 0;
+    int k = 0;
+    for (long q = 0; q < nchunk; q++) {
+        while (col < ncol && k >= c->ktop[col]) {
+            k = 0;
+            col++;
+        }
+        int l[3];
+        int lane = c->ktop[col] - k;             // where the run leaves column col
+        size_t nc = col;
+        for (int t = 0; t < 3; t++) {
+            l[t] = std::min(lane, kWave + 1);
+            nc++;
+            if (lane <= kWave) lane += (nc < ncol) ? c->ktop[nc] : kWave + 1;
+        }
+        int32_t *r = &c->chunk[(size_t)q * 4];
+        r[0] = (int32_t)col;
+        r[1] = k;
+        r[2] = l[0] | (l[1] << 8) | (l[2] << 16);
+        r[3] = 0;
+        // advance kWave active cells
+        int left = kWave;
+        while (left > 0 && col < ncol) {
+            const int room = c->ktop[col] - k;
+            if (room > left) {
+                k += left;
+                left = 0;
+            } else {
+                left -= room;
+                col++;
+                k = 0;
+            }
+        }
+    }
+}
+
 static void set_shapes(rf_ctx *c)
 {
     Geo &G = c->G;
@@ -555,9 +603,12 @@ rf_status rf_setup_grid(rf_ctx *c, int nx, int ny, int nz, double dx, double dy,
         c->ktop[i] = kt;
         c->active += kt;
     }
+    build_chunks(c);
     Geo &G = c->G;
     G.nx = nx; G.ny = ny; G.nz = nz;
     G.ncol = (int)ncol;
+    G.nact = c->active;
+    G.nchunk = (int)(c->chunk.size() / 4);
     set_shapes(c);
     G.V = dx * dy * dz;
     G.A[0] = dy * dz; G.A[1] = dx * dz; G.A[2] = dx * dy;
@@ -726,6 +777,9 @@ rf_status rf::ctx_bind(rf_ctx *c, void *dev_ptr, size_t bytes)
     c->ws_bytes = bytes;
     HIPCHK(c, hipMemcpyAsync(c->A.ktop, c->ktop.data(), c->ktop.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
+    if (!c->chunk.empty())
+        HIPCHK(c, hipMemcpyAsync((void *)c->A.chunk, c->chunk.data(), c->chunk.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_zero(c->A.sc, sizeof(Scalars), c->stream));
     rf_status s = upload_soil(c);
     if (s) return s;

@@ -48,6 +48,8 @@ struct Geo {
     int tile_y;             // interior columns of a tile along y (2 or 4)
     int ntx;                // tiles along x
     int nblk_t;             // tiled kernels: blocks (one tile each)
+    int nchunk;             // runs of kWave consecutive active cells (column order)
+    long nact;              // active cells
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z
     double Tk[3];           // A / distance between centres, per unit K
@@ -110,6 +112,10 @@ struct Arrays {
     double *rdp;              // z-line: reciprocal pivots
     uint8_t *layer;           // may be null
     int32_t *ktop;
+    const int4 *chunk;        // per run q of kWave active cells (cells kWave q .. in column
+                              // order): x = column of its first cell, y = that cell's k,
+                              // z = lane bounds l1 | l2 << 8 | l3 << 16 where the run moves
+                              // to columns x+1, x+2, x+3 (65: not within the run)
     double *pr;               // block partials of (r.z, max|r/diag|)  [(nblk + 1) * 2]
     double *pq;               // block partials of p.q                 [nblk + 1]
     double *pd;               // block partials of (max|e|, non-finite) [(nblk + 1) * 2]

@@ -303,6 +303,58 @@ __device__ __forceinline__ void stage_layers(const Arrays &a, int nlayer, Layer 
 // Cell neighbourhood inside a column chunk.  Direction d: 0 -x, 1 +x, 2 -y,
 // 3 +y, 4 -z, 5 +z.  nb[d]: neighbour active; bnd[d]: the face is on the
 // domain boundary (the +z boundary is the top of the column's active run).
+// The cell of one lane in run q of kWave consecutive active cells (see
+// Arrays::chunk; rec is the run's record, read once per wavefront): column,
+// k, whether it exists (runs past the last active cell are short) and
+// whether it is its column's top cell.  Lanes past the third column of the
+// run walk the active lengths (columns shorter than a run only).
+struct RunCell {
+    int col, k;
+    bool act, top;
+    size_t i;       // cell index (0 for a lane without a cell)
+};
+
+__device__ __forceinline__ RunCell run_cell(const Geo &g, const int32_t *__restrict__ ktop,
+                                            const int4 &rec, int q, int lane)
+{
+    const int l1 = rec.z & 255, l2 = (rec.z >> 8) & 255, l3 = (rec.z >> 16) & 255;
+    RunCell r;
+    r.act = (long)q * kWave + lane < g.nact;
+    if (lane < l1) {
+        r.col = rec.x;
+        r.k = rec.y + lane;
+        r.top = lane == l1 - 1;
+    } else if (lane < l2) {
+        r.col = rec.x + 1;
+        r.k = lane - l1;
+        r.top = lane == l2 - 1;
+    } else if (lane < l3) {
+        r.col = rec.x + 2;
+        r.k = lane - l2;
+        r.top = lane == l3 - 1;
+    } else {
+        int col = rec.x + 3, k = lane - l3, kt = 0;
+        if (r.act) {
+            kt = ktop[col];
+            while (k >= kt) {
+                k -= kt;
+                col++;
+                kt = ktop[col];
+            }
+        }
+        r.col = col;
+        r.k = k;
+        r.top = k == kt - 1;
+    }
+    if (!r.act) {
+        r.col = 0;
+        r.k = 0;
+        r.top = false;
+    }
+    r.i = (size_t)r.col * g.nz + r.k;
+    return r;
+}
+
 struct Cell {
     size_t idx;
     size_t off[6];
@@ -532,13 +584,14 @@ __device__ __forceinline__ void coeff_terms(const FaceTab *sBT, const double *sK
     }
 }
 
-// The soil model is a template parameter.  Short columns: one column per
-// wave at a time, its loads issued together, a branch-free soil evaluation
-// for van Genuchten-Mualem.  At most 128 VGPRs (four waves per SIMD): two
-// 512-thread blocks per CU, so a grid of two blocks per CU runs in one
-// round.  Two interleaved columns per wave took 150 VGPRs, one block per CU
-// and two rounds.
-template <int MODEL>
+// The soil model is a template parameter.  A wavefront evaluates runs of
+// kWave consecutive active cells (Arrays::chunk), so no lane works on a cell
+// above its column's top, whatever the active lengths; the loads of a run are
+// issued together, and van Genuchten-Mualem is evaluated branch-free.  At
+// most 128 VGPRs (four waves per SIMD, two 512-thread blocks per CU): a
+// second run's loads in flight during the evaluation spilled registers and
+// measured slower.
+template <int MODEL, bool FLAT>
 __global__ void __launch_bounds__(kThreads, 4) k_coeff(Geo g, Soil so, Arrays a, int m, double dt,
                                                     double chord_eps, int variant)
 {
@@ -551,73 +604,33 @@ __global__ void __launch_bounds__(kThreads, 4) k_coeff(Geo g, Soil so, Arrays a,
     stage_layers(a, so.nlayer, sL);
     const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     const double vdt = g.V / dt;
-    int cb, ce;
-    block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
-    if (g.nz <= kWave) {
-        // G columns at a time: every load of the group first, then G
-        // independent soil evaluations per lane
-        constexpr int G = 1;
-        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G) {
-            ColSlot cs[G];
-            int lay[G];
-            double ks[G], hm[G], hn[G], thn[G], th[G], C[G], K[G];
-#pragma unroll
-            for (int u = 0; u < G; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-#pragma unroll
-            for (int u = 0; u < G; u++) {
-                const size_t i = cs[u].i;
-                lay[u] = a.layer ? a.layer[i] : 0;
-                ks[u] = a.Ks[i];
-                hm[u] = hmv[i];
-                hn[u] = a.hn[i];
-                thn[u] = a.thn[i];
-            }
-#pragma unroll
-            for (int u = 0; u < G; u++) {
-                if (MODEL == RF_VGM) {
-                    soil_eval_vgm_flat(hm[u], sL[lay[u]], ks[u], th[u], C[u], K[u]);
-                } else {
-                    soil_eval(MODEL, hm[u], sL[lay[u]], ks[u], th[u], C[u], K[u]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < G; u++) {
-                if (!cs[u].act) continue;
-                const int ci = cs[u].col % g.nx, cj = cs[u].col / g.nx;
-                const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, lane == 0,
-                                     lane == cs[u].kt - 1};
-                double D, b;
-                coeff_terms(sBT, sKR, lay[u], bnd, hm[u], hn[u], thn[u], ks[u], th[u],
-                            C[u], K[u], vdt, chord_eps, variant, D, b);
-                const size_t i = cs[u].i;
-                a.K[i] = K[u];
-                a.Dd[i] = D;
-                a.bst[i] = b;
-            }
-        }
-        return;
-    }
-    for (int col = cb + w; col < ce; col += kWavesPerBlock) {
-        const int kt = a.ktop[col];
-        for (int k0 = 0; k0 < kt; k0 += kWave) {
-            const int k = k0 + lane;
-            if (k >= kt) continue;
-            Cell c;
-            cell_setup(g, a.ktop, col, kt, k, c);
-            const size_t idx = c.idx;
-            const int lay = a.layer ? a.layer[idx] : 0;
-            const double ks = a.Ks[idx];
-            const double hm = hmv[idx], hn = a.hn[idx];
-            double th, C, K;
+    // one run of kWave active cells per wavefront at a time
+    const int qs = gridDim.x * kWavesPerBlock;
+    int q = blockIdx.x * kWavesPerBlock + w;
+    int4 rec_next = (q < g.nchunk) ? a.chunk[q] : int4{0, 0, 0, 0};
+    for (; q < g.nchunk; q += qs) {
+        // the next run's record is read while this run is evaluated
+        const int4 rec = rec_next;
+        if (q + qs < g.nchunk) rec_next = a.chunk[q + qs];
+        const RunCell rc = run_cell(g, a.ktop, rec, q, lane);
+        const size_t i = rc.i;
+        const int lay = a.layer ? a.layer[i] : 0;
+        const double ks = a.Ks[i], hm = hmv[i], hn = a.hn[i], thn = a.thn[i];
+        double th, C, K;
+        if (FLAT) {
+            soil_eval_vgm_flat(hm, sL[lay], ks, th, C, K);
+        } else {
             soil_eval(MODEL, hm, sL[lay], ks, th, C, K);
-            double D, b;
-            coeff_terms(sBT, sKR, lay, c.bnd, hm, hn, a.thn[idx], ks, th, C, K, vdt,
-                        chord_eps, variant, D, b);
-            a.K[idx] = K;
-            a.Dd[idx] = D;
-            a.bst[idx] = b;
         }
+        if (!rc.act) continue;
+        const int ci = rc.col % g.nx, cj = rc.col / g.nx;
+        const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, rc.k == 0, rc.top};
+        double D, b;
+        coeff_terms(sBT, sKR, lay, bnd, hm, hn, thn, ks, th, C, K, vdt, chord_eps, variant, D, b);
+        a.K[i] = K;
+        a.Dd[i] = D;
+        a.bst[i] = b;
     }
 }
 
@@ -1636,7 +1649,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
 // TRACK: also dh = h^{n+1} - h^n for the extrapolated first iterate.
 // Block partials (ps): [0] storage sum V theta~(h); [1+f] inflow rate through
 // face f with h = h^{m+1} and K = K(h^m) (the converged system).
-template <bool TRACK>
+template <bool TRACK, int MODEL, bool FLAT>
 __global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a, int serial)
 {
     Scalars *s = a.sc;
@@ -1648,80 +1661,35 @@ __global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a
     stage_layers(a, so.nlayer, sL);
     const int mf = s->picard_m;
     const double *hf = ((mf + 1) & 1) ? a.hb1 : a.hb0;
-    int cb, ce;
-    block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (g.nz <= kWave) {
-        constexpr int G2 = 1;
-        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            ColSlot cs[G2];
-            double hu[G2], Ku[G2], ksu[G2], ho[G2];
-            int lu[G2];
+    // one run of kWave active cells per wavefront at a time
+    const int qs = gridDim.x * kWavesPerBlock;
+    int q = blockIdx.x * kWavesPerBlock + w;
+    int4 rec_next = (q < g.nchunk) ? a.chunk[q] : int4{0, 0, 0, 0};
+    for (; q < g.nchunk; q += qs) {
+        // the next run's record is read while this run is evaluated
+        const int4 rec = rec_next;
+        if (q + qs < g.nchunk) rec_next = a.chunk[q + qs];
+        const RunCell rc = run_cell(g, a.ktop, rec, q, lane);
+        const size_t i = rc.i;
+        const double h = hf[i], K = a.K[i], ks = a.Ks[i];
+        const int lay = a.layer ? a.layer[i] : 0;
+        double ho = 0.0;
+        if (TRACK) ho = a.hn[i];
+        const double th = FLAT ? soil_theta_vgm_flat(h, sL[lay]) : soil_theta(MODEL, h, sL[lay]);
+        if (!rc.act) continue;
+        const int ci = rc.col % g.nx, cj = rc.col / g.nx;
+        const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, rc.k == 0, rc.top};
+        if (TRACK) a.dh[i] = h - ho;
+        a.hn[i] = h;
+        a.thn[i] = th;
+        v[0] += g.V * th;
 #pragma unroll
-            for (int u = 0; u < G2; u++) cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-#pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const size_t i = cs[u].i;
-                hu[u] = hf[i];
-                Ku[u] = a.K[i];
-                ksu[u] = a.Ks[i];
-                lu[u] = a.layer ? a.layer[i] : 0;
-                if (TRACK) ho[u] = a.hn[i];
-            }
-            // theta~ of the group before the per-column branches (branch-free
-            // for van Genuchten-Mualem); one column at a time, as in k_coeff,
-            // keeps the kernel within 128 VGPRs
-            double thu[G2];
-            if (so.model == RF_VGM) {
-#pragma unroll
-                for (int u = 0; u < G2; u++) thu[u] = soil_theta_vgm_flat(hu[u], sL[lu[u]]);
-            } else {
-#pragma unroll
-                for (int u = 0; u < G2; u++) thu[u] = soil_theta(so.model, hu[u], sL[lu[u]]);
-            }
-#pragma unroll
-            for (int u = 0; u < G2; u++) {
-                if (!cs[u].act) continue;
-                const size_t i = cs[u].i;
-                const int ci = cs[u].col % g.nx, cj = cs[u].col / g.nx;
-                const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, lane == 0,
-                                     lane == cs[u].kt - 1};
-                if (TRACK) a.dh[i] = hu[u] - ho[u];
-                a.hn[i] = hu[u];
-                const double th = thu[u];
-                a.thn[i] = th;
-                v[0] += g.V * th;
-#pragma unroll
-                for (int d = 0; d < 6; d++) {
-                    if (!bnd[d]) continue;
-                    const double Kb = ksu[u] * sKR[d * RF_MAX_LAYERS + lu[u]];
-                    v[1 + d] += (sBT[d].cKb - sBT[d].cD * hu[u]) * Kb + sBT[d].cK * Ku[u] + sBT[d].c0;
-                }
-            }
-        }
-    } else
-    for (int col = cb + w; col < ce; col += kWavesPerBlock) {
-        const int kt = a.ktop[col];
-        for (int k0 = 0; k0 < kt; k0 += kWave) {
-            const int k = k0 + lane;
-            if (k >= kt) continue;
-            Cell c;
-            cell_setup(g, a.ktop, col, kt, k, c);
-            const size_t idx = c.idx;
-            const int lay = a.layer ? a.layer[idx] : 0;
-            const double h = hf[idx];
-            if (TRACK) a.dh[idx] = h - a.hn[idx];
-            a.hn[idx] = h;
-            const double th = soil_theta(so.model, h, sL[lay]);
-            a.thn[idx] = th;
-            v[0] += g.V * th;
-#pragma unroll
-            for (int d = 0; d < 6; d++) {
-                if (!c.bnd[d]) continue;
-                const double Kb = a.Ks[idx] * sKR[d * RF_MAX_LAYERS + lay];
-                v[1 + d] += (sBT[d].cKb - sBT[d].cD * h) * Kb + sBT[d].cK * a.K[idx] + sBT[d].c0;
-            }
+        for (int d = 0; d < 6; d++) {
+            if (!bnd[d]) continue;
+            const double Kb = ks * sKR[d * RF_MAX_LAYERS + lay];
+            v[1 + d] += (sBT[d].cKb - sBT[d].cD * h) * Kb + sBT[d].cK * K + sBT[d].c0;
         }
     }
     block_partial<7, 0u>(v, a.ps);
@@ -1975,8 +1943,11 @@ hipError_t launch_decide(const Geo &g, const Arrays &a, int m, double tol_picard
 hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, double dt,
                         double chord_eps, int variant, hipStream_t s)
 {
-    if (so.model == RF_GARDNER) RF_LAUNCH((k_coeff<RF_GARDNER>), g, so, a, m, dt, chord_eps, variant);
-    RF_LAUNCH((k_coeff<RF_VGM>), g, so, a, m, dt, chord_eps, variant);
+    if (so.model == RF_GARDNER)
+        RF_LAUNCH((k_coeff<RF_GARDNER, false>), g, so, a, m, dt, chord_eps, variant);
+    // branch-free van Genuchten-Mualem on columns of at most one wave
+    if (g.nz <= kWave) RF_LAUNCH((k_coeff<RF_VGM, true>), g, so, a, m, dt, chord_eps, variant);
+    RF_LAUNCH((k_coeff<RF_VGM, false>), g, so, a, m, dt, chord_eps, variant);
 }
 
 // The PCG arrays of the FP64 solve: the workspace arrays themselves.
@@ -2087,8 +2058,15 @@ hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, cons
 hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, int serial,
                          hipStream_t s)
 {
-    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<true>, g, so, a, serial);
-    RF_LAUNCH_FOLD(a.ps, 7, 0u, k_accept<false>, g, so, a, serial);
+    // van Genuchten-Mualem branch-free on columns of at most one wave (the
+    // arithmetic the solver has always used there), branching on taller ones
+    const bool vgm = so.model == RF_VGM, flat = vgm && g.nz <= kWave;
+    if (track && flat) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_VGM, true>), g, so, a, serial);
+    if (track && vgm) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_VGM, false>), g, so, a, serial);
+    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_GARDNER, false>), g, so, a, serial);
+    if (flat) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_VGM, true>), g, so, a, serial);
+    if (vgm) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_VGM, false>), g, so, a, serial);
+    RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_GARDNER, false>), g, so, a, serial);
 }
 
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,

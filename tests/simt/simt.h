@@ -32,6 +32,10 @@
 #define __shared__ static
 #define __align__(n) __attribute__((aligned(n)))
 
+struct __attribute__((aligned(16))) int4 {
+    int x, y, z, w;
+};
+
 struct dim3 {
     unsigned x, y, z;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
