@@ -79,11 +79,13 @@ constexpr int kTileThreads = 64 * PX * PY;
 
 // Patch staging: element e of the patch (chunk fastest, then z, then
 // column, i.e. the order of global memory) -> its 16 bytes, zero outside the
-// grid.  PLANES: LDS index in [column][chunk][z] order, else e itself.
-template <int CH, bool PLANES>
+// grid; ZT cells of z per tile plus the border (TZ = ZT + 2).  PLANES: LDS
+// index in [column][chunk][z] order, else e itself.
+template <int CH, bool PLANES, int ZT = 64>
 __device__ __forceinline__ void stage_patch(const NetGeo &g, const bf16 *__restrict__ in, int px0,
                                             int py0, int z0, bf16x8 *sT)
 {
+    constexpr int TZ = ZT + 2;
     constexpr int NST = TX * TY * TZ * CH;
     constexpr int PER = (NST + kTileThreads - 1) / kTileThreads;
     bf16x8 v[PER];
@@ -153,8 +155,9 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
     for (int b = 0; b < COB; b++)
 #pragma unroll
         for (int t = 0; t < 4; t++) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < STEPS; s++) {
-        bf16x8 A[COB];
+    // the operands of step s + 1 are read from LDS while the MFMAs of step s
+    // run (two register sets in turn)
+    auto load = [&](int s, bf16x8 (&A)[COB], bf16x8 (&B)[4]) {
 #pragma unroll
         for (int b = 0; b < COB; b++) A[b] = sW[(s * COB + b) * 64 + lane];
         const int tap = (CIN == 32) ? s : 4 * s + q;
@@ -163,17 +166,28 @@ __global__ void __launch_bounds__(kTileThreads) k_conv(NetGeo g, const bf16 *__r
         const int di = tt / 9 - 1, dj = (tt / 3) % 3 - 1, dk = tt % 3 - 1;
         const int cl = (cx + 1 + di) + TX * (cy + 1 + dj);
         const int part = (CIN == 32) ? q : 0;
-        bf16x8 B[4];
 #pragma unroll
         for (int t = 0; t < 4; t++) {
             const int zl = 16 * t + n + 1 + dk;
             B[t] = tok ? sT[(cl * CH + part) * TZ + zl] : zero8();
         }
+    };
+    auto mfma = [&](const bf16x8 (&A)[COB], const bf16x8 (&B)[4]) {
 #pragma unroll
         for (int t = 0; t < 4; t++)
 #pragma unroll
             for (int b = 0; b < COB; b++)
                 acc[b][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[b], B[t], acc[b][t], 0, 0, 0);
+    };
+    bf16x8 A0[COB], B0[4], A1[COB], B1[4];
+    load(0, A0, B0);
+    for (int s = 0; s < STEPS; s += 2) {
+        if (s + 1 < STEPS) load(s + 1, A1, B1);
+        mfma(A0, B0);
+        if (s + 1 < STEPS) {
+            if (s + 2 < STEPS) load(s + 2, A0, B0);
+            mfma(A1, B1);
+        }
     }
     // lane holds rows 4q..4q+3 (output channels) of column n (cell)
 #pragma unroll
@@ -204,30 +218,35 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // The output layer (32 channels -> 1) is a matrix-vector product per cell: on
 // the 16 x 16 MFMA tile it would fill one output row of sixteen.  Here it
 // runs on the VALU with packed BF16 dot products (v_dot2_f32_bf16, FP32
-// accumulation), from the same LDS patch as k_conv: four adjacent lanes share
-// a cell, lane q taking channels 8q..8q+7, so that a wavefront's LDS reads
-// are consecutive 16-byte chunks (no bank conflicts) and its weight reads are
-// four-way broadcasts; the four partial sums of a cell are added with two
-// quad DPP exchanges.  A wavefront covers its column's 64 cells in four
-// passes of 16.  outf = sum + bias (FP32).
+// accumulation), from an LDS patch like k_conv's but of kOutZ cells of z (a
+// smaller patch, so that two blocks fit a CU and one block's staging overlaps
+// another's arithmetic): four adjacent lanes share a cell, lane q taking
+// channels 8q..8q+7, so that a wavefront's LDS reads are consecutive 16-byte
+// chunks (no bank conflicts) and its weight reads are four-way broadcasts;
+// the four partial sums of a cell are added with two quad DPP exchanges.  A
+// wavefront covers its column's kOutZ cells in passes of 16.
+// outf = sum + bias (FP32).
+constexpr int kOutZ = 32;
+
 __global__ void __launch_bounds__(kTileThreads) k_conv_out(NetGeo g, const bf16 *__restrict__ in,
                                                            const bf16 *__restrict__ wp,
                                                            const float *__restrict__ bias,
                                                            float *__restrict__ outf)
 {
-    constexpr int CIN = kHid, CH = CIN / 8;
+    constexpr int CIN = kHid, CH = CIN / 8, TZO = kOutZ + 2;
     static_assert(CH == 4, "one lane per 16-byte chunk of a cell, four per cell");
     __shared__ bf16x8 sW[kTaps * CH];
-    __shared__ bf16x8 sT[TX * TY * TZ * CH];
+    __shared__ bf16x8 sT[TX * TY * TZO * CH];
     const int pxn = (g.nx + PX - 1) / PX;
-    const int zti = blockIdx.x % g.zt;
-    const int pxy = blockIdx.x / g.zt;
-    const int px0 = (pxy % pxn) * PX, py0 = (pxy / pxn) * PY, z0 = zti * 64;
+    const int zto = (g.nz + kOutZ - 1) / kOutZ;
+    const int zti = blockIdx.x % zto;
+    const int pxy = blockIdx.x / zto;
+    const int px0 = (pxy % pxn) * PX, py0 = (pxy / pxn) * PY, z0 = zti * kOutZ;
     // packed forward weights, one output block: step s, lane 16 q holds
     // channels 8q..8q+7 of output channel 0 at tap s
     const bf16x8 *wv = reinterpret_cast<const bf16x8 *>(wp);
     for (int e = threadIdx.x; e < kTaps * CH; e += kTileThreads) sW[e] = wv[(e / CH) * 64 + 16 * (e % CH)];
-    stage_patch<CH, false>(g, in, px0, py0, z0, sT);
+    stage_patch<CH, false, kOutZ>(g, in, px0, py0, z0, sT);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -237,14 +256,14 @@ __global__ void __launch_bounds__(kTileThreads) k_conv_out(NetGeo g, const bf16 
     const int q = lane & 3, cc = lane >> 2;
     const float b0 = bias[0];
 #pragma unroll
-    for (int pass = 0; pass < 4; pass++) {
+    for (int pass = 0; pass < kOutZ / 16; pass++) {
         const int kl = 16 * pass + cc;              // cell of the column's z-run
         float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int tap = 0; tap < kTaps; tap++) {
             const int di = tap / 9 - 1, dj = (tap / 3) % 3 - 1, dk = tap % 3 - 1;
             const int cl = (cx + 1 + di) + TX * (cy + 1 + dj);
-            const bf16x8 x = sT[(cl * TZ + kl + 1 + dk) * CH + q];
+            const bf16x8 x = sT[(cl * TZO + kl + 1 + dk) * CH + q];
             const bf16x8 w = sW[tap * CH + q];
 #pragma unroll
             for (int e = 0; e < 8; e += 2)
@@ -494,10 +513,16 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[e] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
 }
 
-// One block per patch of PX x PY columns and 64 cells of z.
+// One block per patch of PX x PY columns and 64 cells of z (kOutZ for the
+// output layer).
 int conv_grid(const NetGeo &g)
 {
     return ((g.nx + PX - 1) / PX) * ((g.ny + PY - 1) / PY) * g.zt;
+}
+
+int conv_out_grid(const NetGeo &g)
+{
+    return ((g.nx + PX - 1) / PX) * ((g.ny + PY - 1) / PY) * ((g.nz + kOutZ - 1) / kOutZ);
 }
 
 }  // namespace
@@ -536,7 +561,8 @@ hipError_t net_forward(const NetGeo &g, const NetArrays &a, hipStream_t s)
                        a.p + param_b(1), a.act[1], nullptr);
     hipLaunchKernelGGL((k_conv<32, 2, EPI_RELU>), grid, block, 0, s, g, a.act[1], a.wf[2],
                        a.p + param_b(2), a.act[2], nullptr);
-    hipLaunchKernelGGL(k_conv_out, grid, block, 0, s, g, a.act[2], a.wf[3], a.p + param_b(3), a.y);
+    hipLaunchKernelGGL(k_conv_out, dim3(conv_out_grid(g)), block, 0, s, g, a.act[2], a.wf[3],
+                       a.p + param_b(3), a.y);
     return hipGetLastError();
 }
 

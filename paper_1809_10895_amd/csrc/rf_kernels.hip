@@ -1673,14 +1673,17 @@ __global__ void __launch_bounds__(kThreads, 4) k_accept(Geo g, Soil so, Arrays a
         if (q + qs < g.nchunk) rec_next = a.chunk[q + qs];
         const RunCell rc = run_cell(g, a.ktop, rec, q, lane);
         const size_t i = rc.i;
-        const double h = hf[i], K = a.K[i], ks = a.Ks[i];
+        const int ci = rc.col % g.nx, cj = rc.col / g.nx;
+        const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, rc.k == 0, rc.top};
+        // K and Ks enter only the inflow through domain faces
+        const bool edge = bnd[0] || bnd[1] || bnd[2] || bnd[3] || bnd[4] || bnd[5];
+        const double h = hf[i];
+        const double K = edge ? a.K[i] : 0.0, ks = edge ? a.Ks[i] : 0.0;
         const int lay = a.layer ? a.layer[i] : 0;
         double ho = 0.0;
         if (TRACK) ho = a.hn[i];
         const double th = FLAT ? soil_theta_vgm_flat(h, sL[lay]) : soil_theta(MODEL, h, sL[lay]);
         if (!rc.act) continue;
-        const int ci = rc.col % g.nx, cj = rc.col / g.nx;
-        const bool bnd[6] = {ci == 0, ci == g.nx - 1, cj == 0, cj == g.ny - 1, rc.k == 0, rc.top};
         if (TRACK) a.dh[i] = h - ho;
         a.hn[i] = h;
         a.thn[i] = th;
