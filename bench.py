@@ -40,20 +40,22 @@ FP64_VECTOR_TFLOPS = 78.6
 # neighbour values are reuse, not extra traffic).  Kernel -> (jacobi, zline).
 ALGO_BYTES = {
     "fp64": {
-        "spmv": (56, 48),      # read r, diag (z), p_old, K, Dd; write p, q
-        "update": (56, 80),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z)
+        # read r, diag (z), p_old, K, Dd, e; write p, q, e (the last update's
+        # e += alpha p rides on the spmv kernel, which reads p_old anyway)
+        "spmv": (72, 64),
+        "update": (32, 48),    # read r, q, diag (Jacobi) / r, q, rdp, tz (z-line); write r (+ z)
         "coeff": (56, 56),     # read h^m, h^n, theta^n, Ks; write K, Dd, bst
         "resid": (56, 80),     # read K, h^m, Dd, bst; write r, e, diag (+ tz, rdp, z)
-        "apply_h": (24, 24),   # read e, h^m; write h^m
+        "apply_h": (32, 32),   # read e, p (the last alpha p), h^m; write h^m
         "accept": (24, 24),    # read h^m; write h^n, theta^n
     },
     # PCG vectors and the operator / preconditioner copies in FP32
     "mixed": {
-        "spmv": (28, 24),      # read r, diag (z), p_old, K, Dd (4 B); write p, q (4 B)
-        "update": (28, 40),    # read e, p, r, q, diag (+ rdp, tz); write e, r (+ z), 4 B each
+        "spmv": (36, 32),      # as above, 4 B each
+        "update": (16, 24),    # read r, q, diag / r, q, rdp, tz; write r (+ z), 4 B each
         "coeff": (56, 56),     # FP64 as above
         "resid": (52, 64),     # read K, h^m, Dd, bst (8 B); write r, e, diag, K, Dd (+ tz, rdp, z) (4 B)
-        "apply_h": (20, 20),   # read e (4 B), h^m; write h^m
+        "apply_h": (24, 24),   # read e, p (4 B), h^m; write h^m
         "accept": (24, 24),
     },
 }

@@ -855,7 +855,9 @@ static rf_status enqueue_pairs(rf_ctx *c, StepRec &r, int m, int n)
     for (int i = 0; i < n; i++) {
         const int j = r.pairs_enq[mi]++;
         TIMED(c, r, K_SPMV, m, j, launch_spmv(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
-        TIMED(c, r, K_UPDATE, m, j, launch_update(c->G, A, pc, mixed(c), j & 1, cg_tol(c), c->stream));
+        const bool current = (m == 0) || c->opt.zline_refactor == RF_REFACTOR_EVERY;
+        TIMED(c, r, K_UPDATE, m, j,
+              launch_update(c->G, A, pc, mixed(c), j & 1, current, cg_tol(c), c->stream));
     }
     return RF_OK;
 }

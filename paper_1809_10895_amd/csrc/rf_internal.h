@@ -72,7 +72,11 @@ struct Scalars {
     double rho[2];    // r.z of iteration j kept in slot j & 1
     double resmax;    // max |r / diag| seen by the last direction update
     double pq;
+    double alpha;     // alpha of the last direction update; the next spmv kernel (or, after
+                      // the solve's last update, k_apply_h) adds alpha p to e
     int iters;        // PCG updates completed (written by the update kernel)
+    int plast;        // direction buffer the last spmv kernel that went on wrote (0: p0, 1: p1;
+                      // the host's parity of an iteration need not follow the device's count)
     int jcur;         // index of the direction update in flight (spmv kernel)
     int done;         // PCG finished (converged, hit max_cg or failed)
     int fail;         // 1 breakdown (p.q <= 0), 2 max_cg reached, 3 non-finite
@@ -169,8 +173,10 @@ hipError_t launch_resid(const Geo &g, const Arrays &a, int precond, int m, doubl
                         bool mixed, bool refactor, const CgTol &t, hipStream_t s);
 hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
                        const CgTol &t, hipStream_t s);
+// factors_current: the z-line factors are this Picard iteration's (the
+// diagonal is then rebuilt from them instead of read).
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
-                         const CgTol &t, hipStream_t s);
+                         bool factors_current, const CgTol &t, hipStream_t s);
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s);
 // track: also dh = h^{n+1} - h^n.  serial: the host's tag of the step,

@@ -1078,10 +1078,12 @@ template <int PRECOND, typename T, int G>
 struct SpmvGroup {
     ColSlot cs[G];
     bool nb[G][4];
-    T K[G], D[G], z[G], p[G], Kn[G][4], zn[G][4], pn[G][4];
+    T K[G], D[G], z[G], p[G], e[G], Kn[G][4], zn[G][4], pn[G][4];
 
+    // with_e: also the PCG iterate e at the columns' cells (to add alpha p_old)
     __device__ __forceinline__ void load(const Geo &g, const Arrays &a, const CgVec<T> &cv,
-                                         const T *__restrict__ p_in, int c0, int ce, int lane)
+                                         const T *__restrict__ p_in, int c0, int ce, bool with_e,
+                                         int lane)
     {
         size_t in[G][4];
 #pragma unroll
@@ -1096,6 +1098,7 @@ struct SpmvGroup {
             D[u] = cv.Dd[i];
             z[u] = (PRECOND == RF_PRECOND_JACOBI) ? cv.r[i] / cv.diag[i] : cv.z[i];
             p[u] = p_in[i];
+            e[u] = with_e ? cv.e[i] : T(0);
 #pragma unroll
             for (int d = 0; d < 4; d++) {
                 const size_t jn = in[u][d];
@@ -1111,7 +1114,9 @@ struct SpmvGroup {
 // (r.z, max|r/diag|) partials of the last update and takes the same exit
 // decision (spmv_continue); otherwise p = z + beta p_old (z = M^-1 r) at the
 // cell and its neighbours, q = A p with A = Dd + sum_f T_f (I - shift_f)
-// rebuilt from (K, Dd); writes p, q and the block partials of p.q.  Vector
+// rebuilt from (K, Dd), and the last update's step on the iterate, e +=
+// alpha_{j-1} p_old (p_old is read anyway; the solve's last such step is
+// k_apply_h's); writes p, q, e and the block partials of p.q.  Vector
 // arithmetic in T, reductions and the scalars rho, beta in FP64.  The
 // direction buffers alternate: parity 0 reads p0 and writes p1.
 template <int PRECOND, typename T>
@@ -1121,6 +1126,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
     Scalars *s = a.sc;
     if (s->done || s->fail || s->stall || s->picard_done) return;
     const int j = s->iters;
+    const T alpha_prev = (T)s->alpha;     // alpha_{j-1}: e += alpha_{j-1} p_{j-1} here
     const T *__restrict__ p_in = parity ? cv.p1 : cv.p0;
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
     const bool first = (j == 0);
@@ -1142,11 +1148,12 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
         // combined (2 % on this kernel; with FP32's two columns it was slower)
         constexpr bool kAhead = std::is_same<T, double>::value;
         SpmvGroup<PRECOND, T, G2> gr;
-        if (kAhead && cb + w < ce) gr.load(g, a, cv, p_in, cb + w, ce, lane);
+        if (kAhead && cb + w < ce) gr.load(g, a, cv, p_in, cb + w, ce, !first, lane);
         if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
+        if (lead_thread()) s->plast = parity ? 0 : 1;
         const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            if (!kAhead || c0 != cb + w) gr.load(g, a, cv, p_in, c0, ce, lane);
+            if (!kAhead || c0 != cb + w) gr.load(g, a, cv, p_in, c0, ce, !first, lane);
             T pp[G2], pn[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
@@ -1169,6 +1176,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
                 if (lane + 1 < kt) q += tz2 * (Kp + Ku) * (pp[u] - pup);
                 p_out[gr.cs[u].i] = pp[u];
                 cv.q[gr.cs[u].i] = q;
+                if (!first) cv.e[gr.cs[u].i] = gr.e[u] + alpha_prev * gr.p[u];
                 v[0] += (double)pp[u] * (double)q;
             }
         }
@@ -1176,6 +1184,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
         return;
     }
     if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
+    if (lead_thread()) s->plast = parity ? 0 : 1;
     const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
         const int kt = a.ktop[col];
@@ -1186,6 +1195,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
             cell_setup(g, a.ktop, col, kt, k, c);
             const T Kp = cv.K[c.idx];
             const T pp = pnew_at<PRECOND, T>(cv, c.idx, beta, first, p_in);
+            if (!first) cv.e[c.idx] += alpha_prev * p_in[c.idx];
             T q = cv.Dd[c.idx] * pp;
 #pragma unroll
             for (int d = 0; d < 6; d++) {
@@ -1235,9 +1245,11 @@ __device__ __forceinline__ bool spmv_decide(Scalars *s, int j, const double (&to
 // block of a launch past the end of the solve (marked finished by the fold
 // after the last update) ends after that one round trip, with no vector load
 // in flight.  Then the active lengths and this thread's share of the last
-// update's partials, so that no lane above its column's top loads anything.  Wave w forms q = A p for its TY interior columns from
-// LDS, with the arithmetic per cell of k_spmv.  Three blocks fit a CU.
-// Writes p, q and the block partials of p.q (nblk_t blocks).
+// update's partials, so that no lane above its column's top loads anything.
+// Wave w forms q = A p for its TY interior columns from LDS, and e +=
+// alpha_{j-1} p_old at them, with the arithmetic per cell of k_spmv.  Three
+// blocks fit a CU.  Writes p, q, e and the block partials of p.q (nblk_t
+// blocks).
 template <int PRECOND, typename T, int TY>
 __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVec<T> cv, int parity,
                                                            double tol_cg, double rel, int max_cg)
@@ -1248,6 +1260,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     const int j = s->iters;
     const double rho_slot[2] = {s->rho[0], s->rho[1]};
     const double tol_prev = s->tol_eff;
+    const T alpha_prev = (T)s->alpha;     // alpha_{j-1}: e += alpha_{j-1} p_{j-1} here
     __shared__ T sP[Tl::NS][kWave];
     __shared__ T sK[Tl::NS][kWave];
     __shared__ int sKt[Tl::NS];
@@ -1260,7 +1273,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     double pv[2];
     gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
     const bool first = (j == 0);
-    T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY];
+    T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY], eo[TY], pw[TY];
 #pragma unroll
     for (int u = 0; u < Tl::PER; u++) {
         z[u] = T(0);
@@ -1275,12 +1288,20 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     }
 #pragma unroll
     for (int t = 0; t < TY; t++) {
-        Dd[t] = T(0);
-        if (lane < tc.okt[t]) Dd[t] = cv.Dd[(size_t)tc.oc[t] * g.nz + lane];
+        Dd[t] = eo[t] = pw[t] = T(0);
+        if (lane < tc.okt[t]) {
+            const size_t i = (size_t)tc.oc[t] * g.nz + lane;
+            Dd[t] = cv.Dd[i];
+            if (!first) {
+                eo[t] = cv.e[i];
+                pw[t] = p_in[i];
+            }
+        }
     }
     double tot[2];
     combine_partials<2, 2u>(pv, tot);
     if (!spmv_decide(s, j, tot, tol_prev, tol_cg, rel, max_cg)) return;
+    if (lead_thread()) s->plast = parity ? 0 : 1;
     const T beta = first ? T(0) : (T)(tot[0] / rho_slot[(j + 1) & 1]);
 #pragma unroll
     for (int u = 0; u < Tl::PER; u++) {
@@ -1317,6 +1338,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
             const size_t i = (size_t)tc.oc[t] * g.nz + lane;
             p_out[i] = pp;
             cv.q[i] = q;
+            if (!first) cv.e[i] = eo[t] + alpha_prev * pw[t];
             v[0] += (double)pp * (double)q;
         }
     }
@@ -1348,6 +1370,7 @@ __device__ __forceinline__ bool update_alpha(const Geo &g, const Arrays &a, Scal
     alpha = s->rho[j & 1] / pq;
     if (lead_thread()) {
         s->pq = pq;
+        s->alpha = alpha;
         s->iters = j + 1;
     }
     return true;
@@ -1372,6 +1395,7 @@ __device__ __forceinline__ bool update_decide(Scalars *s, int j, double pq, doub
     alpha = rho_j / pq;
     if (lead_thread()) {
         s->pq = pq;
+        s->alpha = alpha;
         s->iters = j + 1;
     }
     return true;
@@ -1396,48 +1420,64 @@ struct GroupCols {
 };
 
 // Values of G columns of one wave read by the update kernel, loaded by the
-// lanes below each column's active length only.
+// lanes below each column's active length only: r, q, the z-line factors
+// (z-line) and the diagonal, unless it is rebuilt from the factors (rebuild:
+// the factors are this iteration's).
 template <int PRECOND, typename T, int G>
 struct UpdGroupM {
     int col[G], kt[G];
-    T p[G], r[G], q[G], d[G], e[G], rd[G], t[G];
+    T r[G], q[G], d[G], rd[G], t[G];
 
-    __device__ __forceinline__ void load(const Geo &g, const CgVec<T> &cv, const T *__restrict__ pv,
-                                         const GroupCols<G> &gc, int lane)
+    __device__ __forceinline__ void load(const Geo &g, const CgVec<T> &cv, const GroupCols<G> &gc,
+                                         bool rebuild, int lane)
     {
 #pragma unroll
         for (int u = 0; u < G; u++) {
             col[u] = gc.col[u];
             kt[u] = gc.kt[u];
-            p[u] = r[u] = q[u] = e[u] = rd[u] = t[u] = T(0);
+            r[u] = q[u] = rd[u] = t[u] = T(0);
             d[u] = T(1);
             if (lane < kt[u]) {
                 const size_t i = (size_t)col[u] * g.nz + lane;
-                p[u] = pv[i];
                 r[u] = cv.r[i];
                 q[u] = cv.q[i];
-                d[u] = cv.diag[i];
-                e[u] = cv.e[i];
                 if (PRECOND == RF_PRECOND_ZLINE) {
                     rd[u] = cv.rdp[i];
                     t[u] = cv.tz[i];
                 }
+                if (PRECOND != RF_PRECOND_ZLINE || !rebuild) d[u] = cv.diag[i];
             }
         }
     }
 };
 
-// alpha = rho_j / p.q (every block combines the p.q partials); block
-// partials of (r.z, max|r/diag|).  p is the direction the spmv kernel of the
-// same parity wrote.  Short columns: the loads of a wave's first group of
-// columns are issued before the partials are combined, so the two are in
-// flight together, and each further group is loaded while the one before
-// it is computed.
-template <int PRECOND, typename T>
-__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity)
+// The diagonal of a column cell from its z-line factors: with pivots d_k =
+// a_k - t_{k-1}^2 / d_{k-1} (rdp = 1/d), a_k = 1/rdp_k + t_{k-1}^2 rdp_{k-1}
+// (both terms positive, no cancellation).  rd, t: this lane's rdp and t
+// (zero above the column's top); the cell below's come from lane k-1.
+template <typename T>
+__device__ __forceinline__ T zline_diag(T rd, T t)
 {
+    const T rb = from_below<T>(rd, T(0)), tb = from_below<T>(t, T(0));
+    return T(1) / rd + tb * tb * rb;
+}
+
+// alpha = rho_j / p.q (every block combines the p.q partials; kept in the
+// scalars for e += alpha p, which the next spmv kernel applies since it reads
+// p anyway, or k_apply_h after the solve's last update); r -= alpha q, z =
+// M^-1 r; block partials of (r.z, max|r/diag|).  With the z-line
+// preconditioner factored from this iteration's matrix (rebuild), diag is
+// rebuilt from the column's pivots (zline_diag), so the kernel reads r, q,
+// rdp, tz and writes r, z.  Short columns: the loads
+// of a wave's first group of columns are issued before the partials are
+// combined, so the two are in flight together, and each further group is
+// loaded while the one before it is computed.
+template <int PRECOND, typename T>
+__global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity,
+                                                     int rebuild)
+{
+    (void)parity;
     Scalars *s = a.sc;
-    const T *__restrict__ p = parity ? cv.p0 : cv.p1;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
@@ -1461,12 +1501,11 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
         gather_partials<1, 0u>(a.pq + g.foff, g.np, pv);
         if (stop) return;
         UpdGroupM<PRECOND, T, G> ga, gb;
-        ga.load(g, cv, p, ka, lane);
+        ga.load(g, cv, ka, rebuild, lane);
         double tot[1];
         combine_partials<1, 0u>(pv, tot);
         if (!update_decide(s, j, tot[0], rho_slot[j & 1], alpha_d)) return;
         const T alpha = (T)alpha_d;
-        T *__restrict__ ev = cv.e;
         T *__restrict__ rv = cv.r;
         T *__restrict__ zv = cv.z;
         auto work = [&](const UpdGroupM<PRECOND, T, G> &gr) {
@@ -1475,13 +1514,14 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                 const bool act = lane < gr.kt[u];
                 const size_t i = (size_t)(gr.col[u] >= 0 ? gr.col[u] : 0) * g.nz + lane;
                 const T r = act ? gr.r[u] - alpha * gr.q[u] : T(0);
+                const T dg = (PRECOND == RF_PRECOND_ZLINE && rebuild)
+                                 ? zline_diag<T>(act ? gr.rd[u] : T(1), gr.t[u]) : gr.d[u];
                 if (act) {
-                    ev[i] = gr.e[u] + alpha * gr.p[u];
                     rv[i] = r;
-                    v[1] = fmax(v[1], (double)fabs(r / gr.d[u]));
+                    v[1] = fmax(v[1], (double)fabs(r / dg));
                 }
                 if (PRECOND == RF_PRECOND_JACOBI) {
-                    if (act) v[0] += (double)r * (double)(r / gr.d[u]);
+                    if (act) v[0] += (double)r * (double)(r / dg);
                 } else {
                     const T zk = zline_solve_short<T>(r, act ? gr.rd[u] : T(0), act ? gr.t[u] : T(0), lane);
                     if (act) {
@@ -1494,13 +1534,13 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
         for (int c0 = cb + w; c0 < ce; c0 += 2 * step) {
             const bool more = c0 + step < ce;
             if (more) {
-                gb.load(g, cv, p, kb, lane);
+                gb.load(g, cv, kb, rebuild, lane);
                 ka.fetch(a.ktop, c0 + 2 * step, ce);
             }
             work(ga);
             if (!more) break;
             if (c0 + 2 * step < ce) {
-                ga.load(g, cv, p, ka, lane);
+                ga.load(g, cv, ka, rebuild, lane);
                 kb.fetch(a.ktop, c0 + 3 * step, ce);
             }
             work(gb);
@@ -1519,7 +1559,6 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
             const int k = k0 + lane;
             if (k >= kt) continue;
             const size_t i = base + k;
-            cv.e[i] += alpha * p[i];
             const T r = cv.r[i] - alpha * cv.q[i];
             cv.r[i] = r;
             const T dg = cv.diag[i];
@@ -1538,18 +1577,21 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
 }
 
 // ---------------------------------------------------------------------------
-// Picard update: h^{m+1} = h^m + e
+// Picard update: h^{m+1} = h^m + e + alpha_{J-1} p_{J-1}
 // ---------------------------------------------------------------------------
 
 // Enqueued after a chunk of PCG iterations.  Every block combines the last
 // (r.z, max|r/diag|) partials and decides, as the next direction update
 // would, whether the solve has finished.  If not, the step stalls until the
-// host enqueues more iterations; if so, hb[(m+1)&1] = hb[m&1] + e and block
-// partials of (max|e|, non-finite count).  The increment e is in the
-// precision T of the solve; h stays FP64.
+// host enqueues more iterations; if so, the increment is e plus the last
+// update's step alpha_{J-1} p_{J-1} (J updates done; every earlier step was
+// added by the spmv kernel after it), hb[(m+1)&1] = hb[m&1] + that, and block
+// partials of (max|increment|, non-finite count).  The increment is formed in
+// the precision T of the solve; h stays FP64.  p0, p1: the direction buffers.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *e_in, int m,
-                                                      double tol_cg, double rel, int max_cg)
+__global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *e_in, const T *p0,
+                                                      const T *p1, int m, double tol_cg, double rel,
+                                                      int max_cg)
 {
     Scalars *s = a.sc;
     // the step flags, the solve's state, the first group's active lengths and
@@ -1560,9 +1602,14 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
     const int j = s->iters;
     const int sdone = s->done;
     const double tol_prev = s->tol_eff;
+    const T alpha_last = (T)s->alpha;
+    const int plast = s->plast;
     const double *__restrict__ hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     double *__restrict__ hnext = (m & 1) ? a.hb0 : a.hb1;
     const T *__restrict__ ev = e_in;
+    // p_{J-1}: the buffer the last spmv kernel that went on wrote (none when J = 0)
+    const T *__restrict__ pl = plast ? p1 : p0;
+    const bool step_left = j > 0;
     int cb, ce;
     block_columns(g, g.cpb, cb, ce);
     RF_WAVE_IDS;
@@ -1579,7 +1626,8 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
             hv[u] = 0.0;
             if (lane < kc.kt[u]) {
                 const size_t i = (size_t)kc.col[u] * g.nz + lane;
-                e[u] = (double)ev[i];
+                const T et = step_left ? ev[i] + alpha_last * pl[i] : ev[i];
+                e[u] = (double)et;
                 hv[u] = hmv[i];
             }
         }
@@ -1629,7 +1677,8 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
                 const int k = k0 + lane;
                 if (k >= kt) continue;
                 const size_t i = (size_t)col * g.nz + k;
-                const double e = (double)ev[i];
+                const T et = step_left ? ev[i] + alpha_last * pl[i] : ev[i];
+                const double e = (double)et;
                 const double h = hmv[i] + e;
                 hnext[i] = h;
                 v[0] = fmax(v[0], fabs(e));
@@ -2039,23 +2088,25 @@ hipError_t launch_spmv(const Geo &g, const Arrays &a, int precond, bool mixed, i
 }
 
 hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed, int parity,
-                         const CgTol &t, hipStream_t s)
+                         bool factors_current, const CgTol &t, hipStream_t s)
 {
     const bool zl = precond == RF_PRECOND_ZLINE;
-    if (mixed && zl) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, float>), g, a, a.f, parity);
-    if (mixed) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, float>), g, a, a.f, parity);
-    if (zl) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity);
-    RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity);
+    const int rb = factors_current ? 1 : 0;
+    if (mixed && zl)
+        RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, float>), g, a, a.f, parity, rb);
+    if (mixed) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, float>), g, a, a.f, parity, rb);
+    if (zl) RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_ZLINE, double>), g, a, dvec(a), parity, rb);
+    RF_LAUNCH_DECIDE(g.nblk, (k_update<RF_PRECOND_JACOBI, double>), g, a, dvec(a), parity, rb);
 }
 
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s)
 {
     if (mixed)
-        RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<float>, g, a, (const float *)a.f.e, m, t.tol_cg, t.rel,
-                       t.max_cg);
-    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<double>, g, a, (const double *)a.e, m, t.tol_cg, t.rel,
-                   t.max_cg);
+        RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<float>, g, a, (const float *)a.f.e,
+                       (const float *)a.f.p0, (const float *)a.f.p1, m, t.tol_cg, t.rel, t.max_cg);
+    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<double>, g, a, (const double *)a.e, (const double *)a.p0,
+                   (const double *)a.p1, m, t.tol_cg, t.rel, t.max_cg);
 }
 
 hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, int serial,

@@ -160,6 +160,7 @@ static int run_solver()
     o.stencil = ri();
     o.tile_rows = ri();
     o.cols_per_wave = ri();
+    o.cg_rel_tol = rd();
     CHK(rf_set_options(c, &o));
     const int nsteps = ri();
     const double dt = rd();
@@ -183,6 +184,9 @@ static int run_solver()
             const int s = rf_step(c, dt, nullptr, &st);
             printf("step %d %d %d", s, st.picard_iters, st.cg_iters_total);
             for (int m = 0; m < st.picard_iters && m < RF_MAX_PICARD_LOG; m++) printf(" %.17g", st.delta[m]);
+            printf("\n");
+            printf("cg");
+            for (int m = 0; m < st.picard_iters && m < RF_MAX_PICARD_LOG; m++) printf(" %d", st.cg_iters[m]);
             printf("\n");
             if (s) break;
         }

@@ -72,6 +72,27 @@ def test_solver_emulated_matches_oracle(exe, tmp_path):
         assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-10
 
 
+def test_solver_emulated_resumed_solve_mixed(exe, tmp_path):
+    """The 1-D column (long-column kernels) in mixed precision with a relative
+    PCG exit and the Jacobi preconditioner: the second step's first solve
+    needs more PCG iterations than the first step's last one, so it stalls
+    and the host enqueues more, and re-enqueues the later Picard iterations
+    with direction-buffer parities that no longer follow the device's count.
+    The step must still end where the oracle's does (a regression: the last
+    iterate step once read the wrong direction buffer there)."""
+    w = W.column100()
+    n = 3
+    path = os.path.join(str(tmp_path), "col.txt")
+    cases.solver_case(path, w, n, w.dt, precond=0, precision=1, tol_cg=1e-11, cg_rel_tol=1e-6)
+    out = cases.run(exe, "solver", path, timeout=600)
+    P = make_oracle(orc_mod, w, dt0=w.dt, ebats=0)
+    its = [P.step(w.dt)[1]["picard_iters"] for _ in range(n)]
+    h_o, _ = P.get_state()
+    got = [s["picard_iters"] for s in out["steps"]]
+    assert all(abs(a - b) <= 1 for a, b in zip(got, its)), (got, its)
+    assert np.abs(out["h"] - h_o).max() <= 1e-9
+
+
 def test_ensemble_ragged_lengths_under_ebats(exe, tmp_path):
     w = small_ensemble(EDGE_LENGTHS)
     out = _ens(exe, tmp_path, w, [w.t_end])
