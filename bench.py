@@ -45,7 +45,9 @@ ALGO_BYTES = {
         "spmv": (72, 64),
         "update": (32, 48),    # read r, q, diag (Jacobi) / r, q, rdp, tz (z-line); write r (+ z)
         "coeff": (56, 56),     # read h^m, h^n, theta^n, Ks; write K, Dd, bst
-        "resid": (56, 80),     # read K, h^m, Dd, bst; write r, e, diag (+ tz, rdp, z)
+        # read K, h^m, Dd, bst; write r, diag (Jacobi) / r, tz, rdp, z (z-line,
+        # diag rebuilt later from the factors)
+        "resid": (48, 64),
         "apply_h": (32, 32),   # read e, p (the last alpha p), h^m; write h^m
         "accept": (24, 24),    # read h^m; write h^n, theta^n
     },
@@ -54,7 +56,7 @@ ALGO_BYTES = {
         "spmv": (36, 32),      # as above, 4 B each
         "update": (16, 24),    # read r, q, diag / r, q, rdp, tz; write r (+ z), 4 B each
         "coeff": (56, 56),     # FP64 as above
-        "resid": (52, 64),     # read K, h^m, Dd, bst (8 B); write r, e, diag, K, Dd (+ tz, rdp, z) (4 B)
+        "resid": (48, 56),     # read K, h^m, Dd, bst (8 B); write r, diag / r, tz, rdp, z, and K, Dd (4 B)
         "apply_h": (24, 24),   # read e, p (4 B), h^m; write h^m
         "accept": (24, 24),
     },

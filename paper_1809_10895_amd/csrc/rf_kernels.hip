@@ -104,13 +104,30 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double *out)
 
 // First half of reduce_partials: this thread's share of the nblk block
 // partials (blocks threadIdx.x, + kThreads, ...), so that their loads can be
-// issued early and combined later with combine_partials.
+// issued early and combined later with combine_partials.  The loads of eight
+// partials are issued before any is added (one round trip per eight instead
+// of one per partial, which is what a one-block fold over thousands of
+// partials waits on); they are added in block order, as one at a time.
 template <int NV, unsigned MAXMASK>
 __device__ __forceinline__ void gather_partials(const double *P, int nblk, double (&v)[NV])
 {
+    constexpr int U = 8;
 #pragma unroll
     for (int i = 0; i < NV; i++) v[i] = 0.0;   // identity of sums and of max over |x|
-    for (int b = threadIdx.x; b < nblk; b += kThreads)
+    int b = threadIdx.x;
+    for (; b + (U - 1) * kThreads < nblk; b += U * kThreads) {
+        double x[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int i = 0; i < NV; i++) x[u][i] = P[(size_t)(b + u * kThreads) * NV + i];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int i = 0; i < NV; i++)
+                v[i] = ((MAXMASK >> i) & 1u) ? fmax(v[i], x[u][i]) : v[i] + x[u][i];
+    }
+    for (; b < nblk; b += kThreads)
 #pragma unroll
         for (int i = 0; i < NV; i++) {
             const double x = P[(size_t)b * NV + i];
@@ -683,9 +700,12 @@ __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 // ---------------------------------------------------------------------------
 
 // One column of at most 64 cells (lane = k): the interior faces, the
-// residual r = b - A h^m of the increment system, diag, e = 0, the z-line
-// factors (refactor) and z = M^-1 r, and the block-partial contributions
-// v = (r.z, max|r/diag|).  Kp, hp, Dp, bp: K, h^m, Dd, bst of the lane's
+// residual r = b - A h^m of the increment system, diag (stored only where a
+// later kernel reads it: Jacobi, factors kept from an earlier iteration, or
+// the assembly for the caller; the update kernel otherwise rebuilds it from
+// this iteration's factors), the z-line factors (refactor) and z = M^-1 r,
+// and the block-partial contributions v = (r.z, max|r/diag|).  The PCG
+// iterate e needs no clearing: the first spmv kernel to add to it writes it.  Kp, hp, Dp, bp: K, h^m, Dd, bst of the lane's
 // cell; Kn, hn, nb: the lateral neighbours (-x, +x, -y, +y) and whether they
 // are active; tzs, rds: the stored z-line factors (used when !refactor).
 // Lanes at or above the active length kt only take part in the scans.
@@ -727,11 +747,11 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
     }
     const double r = act ? b - Ap : 0.0;
     const T rs = (T)r, ds = (T)diag;
+    const bool keep_diag = PRECOND == RF_PRECOND_JACOBI || !refactor || bout != nullptr;
     if (act) {
         if (bout) bout[i] = b;
         cv.r[i] = rs;
-        cv.e[i] = T(0);
-        cv.diag[i] = ds;
+        if (keep_diag) cv.diag[i] = ds;
         if (kCopyKD) {
             cv.K[i] = (T)Kp;
             cv.Dd[i] = (T)Dp;
@@ -785,10 +805,12 @@ __device__ __forceinline__ void resid_reset_scalars(Scalars *s, int m)
 
 // Adds the interior faces: diag = Dd + sum T_f, b = bst + sum A_f K_f g.n_f
 // with K_f = (K_P + K_N)/2 and T_f = A_f K_f / d_f; r = b - A h^m (the
-// right-hand side of the increment system A e = r, e0 = 0); e = 0.
-// Jacobi: z = r / diag.  z-line: t_k (vertical couplings) and reciprocal
-// pivots of each column (refactor = 1), or those stored by the step's first
-// Picard iteration (refactor = 0), and z = M^-1 r with them.  Block partials of (r.z, max|r/diag|).
+// right-hand side of the increment system A e = r, e0 = 0; e itself is
+// written by the first spmv kernel that adds to it).  Jacobi: z = r / diag.
+// z-line: t_k (vertical couplings) and reciprocal pivots of each column
+// (refactor = 1), or those stored by the step's first Picard iteration
+// (refactor = 0), and z = M^-1 r with them.  Block partials of (r.z,
+// max|r/diag|).
 // Everything is computed in FP64; the PCG arrays v receive it in the
 // precision T of the solve (FP32 copies of K and Dd as well when T is float).
 template <int PRECOND, typename T>
@@ -873,7 +895,6 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
                 r = b - Ap;
                 if (bout) bout[c.idx] = b;
                 cv.r[c.idx] = (T)r;
-                cv.e[c.idx] = T(0);
                 cv.diag[c.idx] = (T)diag;
                 if (kCopyKD) {
                     cv.K[c.idx] = (T)Kp;
@@ -1080,7 +1101,8 @@ struct SpmvGroup {
     bool nb[G][4];
     T K[G], D[G], z[G], p[G], e[G], Kn[G][4], zn[G][4], pn[G][4];
 
-    // with_e: also the PCG iterate e at the columns' cells (to add alpha p_old)
+    // with_e: also the PCG iterate e at the columns' cells (to add alpha p_old;
+    // before the second step e is 0 and is not read)
     __device__ __forceinline__ void load(const Geo &g, const Arrays &a, const CgVec<T> &cv,
                                          const T *__restrict__ p_in, int c0, int ce, bool with_e,
                                          int lane)
@@ -1148,12 +1170,12 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
         // combined (2 % on this kernel; with FP32's two columns it was slower)
         constexpr bool kAhead = std::is_same<T, double>::value;
         SpmvGroup<PRECOND, T, G2> gr;
-        if (kAhead && cb + w < ce) gr.load(g, a, cv, p_in, cb + w, ce, !first, lane);
+        if (kAhead && cb + w < ce) gr.load(g, a, cv, p_in, cb + w, ce, j >= 2, lane);
         if (!spmv_continue(g, a, s, j, tol_cg, rel, max_cg, rho)) return;
         if (lead_thread()) s->plast = parity ? 0 : 1;
         const T beta = first ? T(0) : (T)(rho / s->rho[(j + 1) & 1]);
         for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            if (!kAhead || c0 != cb + w) gr.load(g, a, cv, p_in, c0, ce, !first, lane);
+            if (!kAhead || c0 != cb + w) gr.load(g, a, cv, p_in, c0, ce, j >= 2, lane);
             T pp[G2], pn[G2][4];
 #pragma unroll
             for (int u = 0; u < G2; u++) {
@@ -1195,7 +1217,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
             cell_setup(g, a.ktop, col, kt, k, c);
             const T Kp = cv.K[c.idx];
             const T pp = pnew_at<PRECOND, T>(cv, c.idx, beta, first, p_in);
-            if (!first) cv.e[c.idx] += alpha_prev * p_in[c.idx];
+            if (j == 1) cv.e[c.idx] = alpha_prev * p_in[c.idx];      // e was 0
+            else if (j >= 2) cv.e[c.idx] += alpha_prev * p_in[c.idx];
             T q = cv.Dd[c.idx] * pp;
 #pragma unroll
             for (int d = 0; d < 6; d++) {
@@ -1292,10 +1315,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
         if (lane < tc.okt[t]) {
             const size_t i = (size_t)tc.oc[t] * g.nz + lane;
             Dd[t] = cv.Dd[i];
-            if (!first) {
-                eo[t] = cv.e[i];
-                pw[t] = p_in[i];
-            }
+            if (!first) pw[t] = p_in[i];
+            if (j >= 2) eo[t] = cv.e[i];        // (e is 0 before the first step)
         }
     }
     double tot[2];
@@ -1585,7 +1606,8 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
 // would, whether the solve has finished.  If not, the step stalls until the
 // host enqueues more iterations; if so, the increment is e plus the last
 // update's step alpha_{J-1} p_{J-1} (J updates done; every earlier step was
-// added by the spmv kernel after it), hb[(m+1)&1] = hb[m&1] + that, and block
+// added by the spmv kernel after it, and e holds them from J = 2 on; 0 for
+// J = 0), hb[(m+1)&1] = hb[m&1] + that, and block
 // partials of (max|increment|, non-finite count).  The increment is formed in
 // the precision T of the solve; h stays FP64.  p0, p1: the direction buffers.
 template <typename T>
@@ -1626,7 +1648,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
             hv[u] = 0.0;
             if (lane < kc.kt[u]) {
                 const size_t i = (size_t)kc.col[u] * g.nz + lane;
-                const T et = step_left ? ev[i] + alpha_last * pl[i] : ev[i];
+                const T et = (j >= 2) ? ev[i] + alpha_last * pl[i] : step_left ? alpha_last * pl[i] : T(0);
                 e[u] = (double)et;
                 hv[u] = hmv[i];
             }
@@ -1677,7 +1699,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_h(Geo g, Arrays a, const T *
                 const int k = k0 + lane;
                 if (k >= kt) continue;
                 const size_t i = (size_t)col * g.nz + k;
-                const T et = step_left ? ev[i] + alpha_last * pl[i] : ev[i];
+                const T et = (j >= 2) ? ev[i] + alpha_last * pl[i] : step_left ? alpha_last * pl[i] : T(0);
                 const double e = (double)et;
                 const double h = hmv[i] + e;
                 hnext[i] = h;
