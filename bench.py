@@ -185,6 +185,30 @@ def cpu_baseline(w, seconds, serial_steps):
     return out if "value" in out else None
 
 
+def host_stream_copy(threads, mib=512, reps=5):
+    """Host memory bandwidth: a copy of `mib` MiB between two NumPy arrays in
+    `threads` slices on as many threads (NumPy releases the GIL in copyto),
+    best of `reps`; bytes counted as read + write."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    n = mib * (1 << 20) // 8
+    src = np.ones(n)
+    dst = np.zeros(n)
+    edges = [n * i // threads for i in range(threads + 1)]
+
+    def part(i):
+        np.copyto(dst[edges[i]:edges[i + 1]], src[edges[i]:edges[i + 1]])
+
+    best = float("inf")
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(part, range(threads)))                     # first touch
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(part, range(threads)))
+            best = min(best, time.perf_counter() - t0)
+    return 2.0 * n * 8 / best / 1e9
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("rf_kernels.hip", "rf_internal.h"):
@@ -480,6 +504,19 @@ def main():
     add_copy_reference(main_r["roofline"])
     progress("cpu baseline")
     cpu = cpu_baseline(w, args.cpu_seconds, args.cpu_serial_steps)
+    if cpu is not None and cpu.get("cores", 1) > 1:
+        # the host's own bandwidth, and what share of it the oracle's rate
+        # would be if it moved the GPU path's algorithmic bytes per cell-step
+        pc = 1 if args.precond == "zline" else 0
+        ab = ALGO_BYTES[args.precision]
+        pic, cgp = main_r["picard_per_step"], main_r["cg_per_picard"]
+        per_cell_step = (pic * cgp * (ab["spmv"][pc] + ab["update"][pc])
+                         + pic * (ab["coeff"][pc] + ab["resid"][pc] + ab["apply_h"][pc])
+                         + ab["accept"][pc])
+        bw = host_stream_copy(cpu["cores"])
+        cpu["host_stream_copy_GBps"] = round(bw, 1)
+        cpu["gpu_path_bytes_per_cell_step"] = round(per_cell_step, 1)
+        cpu["stream_fraction"] = round(cpu["value"] * per_cell_step / 1e9 / bw, 4)
     out = {
         "metric": "cell-steps/s at Picard tol 1e-6", "value": main_r["value"], "unit": "cell-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -44,3 +44,5 @@ def test_one_json_line_with_the_contract_fields():
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
     assert cpu["one_thread"]["cores"] == 1 and cpu["one_thread"]["value"] > 0
     assert cpu["host"]["os_cpu_count"] >= 1
+    if cpu["cores"] > 1:
+        assert cpu["host_stream_copy_GBps"] > 0 and 0 < cpu["stream_fraction"] < 1
