@@ -36,7 +36,8 @@ def solver_case(path, w, nsteps, dt, tol_picard=1e-6, tol_cg=1e-13, max_picard=1
 
 def ens_case(path, w, t_ends, tol_picard=1e-6, max_picard=50, chord_eps=1e-9, dt_min=1e-6,
              inc_after=10, few_iters=3, max_iters=8, factor=1.3, precision=0, picard_variant=0,
-             model=0, max_steps=10 ** 8, max_seconds=1e6, waves_per_block=4, blocks_per_cu=0):
+             model=0, max_steps=10 ** 8, max_seconds=1e6, waves_per_block=4, blocks_per_cu=0,
+             run_steps=()):
     bc = {4: (0, 0.0), 5: (0, 0.0)}
     for face, kind, value in w.bcs:
         bc[face] = (kind, value)
@@ -48,6 +49,7 @@ def ens_case(path, w, t_ends, tol_picard=1e-6, max_picard=50, chord_eps=1e-9, dt
     lines.append("%d %r" % (max_steps, max_seconds))
     lines.append("%d %d" % (waves_per_block, blocks_per_cu))
     lines.append("%d %s" % (len(t_ends), _fmt(t_ends)))
+    lines.append("%d %s" % (len(run_steps), _fmt(run_steps)))   # per-run step budgets
     lines.append(_fmt(w.h0))
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -87,6 +87,8 @@ static int run_ens()
     CHK(rf_ens_set_tile(e, &tile));
     const int nrun = ri();
     auto t_end = rv<double>(nrun);
+    const int nlim = ri();                      // per-run step budgets (0: the one above)
+    auto run_steps = rv<double>(nlim);
     long ncell = 0;
     CHK(rf_ens_cells(e, &ncell));
     auto h0 = rv<double>(ncell);
@@ -98,6 +100,7 @@ static int run_ens()
     memcpy(hd, h0.data(), ncell * sizeof(double));
     CHK(rf_ens_set_state(e, hd, 0.0));
     for (int r = 0; r < nrun; r++) {
+        if (r < nlim && run_steps[r] > 0) CHK(rf_ens_set_limits(e, (long)run_steps[r], max_seconds));
         rf_ens_summary sm;
         const int s = rf_ens_run(e, t_end[r], &sm);
         printf("run %d %ld %ld %ld %ld %d %.17g %.17g\n", s, sm.accepted, sm.rejected, sm.picard_total,

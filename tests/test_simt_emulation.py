@@ -7,9 +7,11 @@ these tests compare what that build computes with the oracle.
 For the ensemble this is the parity evidence that the GPU cannot give while
 its launches stay switched off: the same inputs as the ensemble's GPU tests
 (ragged lengths at every boundary of the blocked layout under EBATS, a
-column that fails beside columns that finish, modified Picard, a run split
-in two launches) give per-column accepted, rejected and Picard counts equal
-to the oracle's, heads within 1e-8, and no sanitizer report."""
+column that fails beside columns that finish, modified Picard, Gardner soils
+with a flux top, FP32 solves, a run split in two launches, a step budget
+then a resume) give per-column accepted, rejected and Picard counts equal to
+the oracle's, heads within 1e-8 (FP32 solves: 1e-5 m), and no sanitizer
+report."""
 import os
 import shutil
 
@@ -144,3 +146,62 @@ def test_ensemble_second_launch_continues(exe, tmp_path):
         return 0, tot, h, None
 
     _check_columns(w, out, two_pieces)
+
+
+def test_ensemble_gardner_flux_top(exe, tmp_path):
+    """Gardner soils (App. A) with a flux top and a Dirichlet base under
+    EBATS: the oracle's heads per column."""
+    wg = small_ensemble([50, 129], seed=6)
+    wg.soil[:, 2] = [0.5, 3.0]
+    wg.bcs = [(W.ZMAX, W.FLUX, 5e-7), (W.ZMIN, W.DIRICHLET, 0.0)]
+    wg.h0 = -np.concatenate([np.linspace(0.0, 0.5, 50), np.linspace(0.0, 1.29, 129)])
+    out = _ens(exe, tmp_path, wg, [wg.t_end], model=1)
+    assert out["runs"][0]["status"] == 0
+    for c in range(2):
+        L, soil, h0 = wg.column(c)
+        P = orc_mod.Problem(1, 1, L, 1.0, 1.0, wg.dz)
+        P.set_soil(np.array([soil]), model=1)
+        W.configure_ensemble(wg, P)
+        P.set_options(tol_picard=1e-6, max_picard=50, dt0=wg.dt, dt_max=wg.dt_max, ebats=1,
+                      tol_cg=1e-13, max_cg=1000)
+        P.set_state(h0)
+        s, rs = P.run(wg.t_end)
+        assert s == 0
+        h_o, _ = P.get_state()
+        r = out["cols"][c]
+        assert (r["accepted"], r["rejected"], r["picard_total"]) == \
+            (rs["accepted"], rs["rejected"], rs["picard_total"]), (c, r, rs)
+        o = wg.offsets[c]
+        assert np.abs(out["h"][o:o + L] - h_o).max() <= 1e-8 * max(np.abs(h_o).max(), 1.0)
+
+
+def test_ensemble_mixed_precision(exe, tmp_path):
+    """FP32 tridiagonal solves under FP64 Picard refinement, fixed steps:
+    heads within 10 tol_picard of the FP64 oracle, Picard totals within the
+    step count, storages to 1e-6."""
+    w = small_ensemble([50, 64, 65, 150, 300, 448], seed=11, t_end=300.0, ks_max=-6.0)
+    w.ebats = False
+    out = _ens(exe, tmp_path, w, [w.t_end], precision=1)
+    assert out["runs"][0]["status"] == 0
+    for c in range(w.ncol):
+        so, rs, h_o, mb = oracle_column(orc_mod, w, c, w.t_end)
+        assert so == 0
+        L, o = w.lengths[c], w.offsets[c]
+        r = out["cols"][c]
+        assert np.abs(out["h"][o:o + L] - h_o).max() <= 1e-5, c
+        assert abs(r["picard_total"] - rs["picard_total"]) <= rs["accepted"], c
+        assert r["storage"] == pytest.approx(mb["storage"], rel=1e-6)
+
+
+def test_ensemble_step_budget_then_resume(exe, tmp_path):
+    """A run stopped by a budget of 7 steps per column, then resumed, ends
+    bit for bit where one uninterrupted run ends, with the same counts."""
+    w = small_ensemble([80, 160, 320], seed=8)
+    whole = _ens(exe, tmp_path, w, [w.t_end])
+    split = _ens(exe, tmp_path, w, [w.t_end, w.t_end], run_steps=(7, 10 ** 8))
+    assert split["runs"][0]["status"] == -5 and split["runs"][0]["failed"] == 0
+    assert split["runs"][0]["t_min"] < w.t_end
+    assert split["runs"][1]["status"] == 0
+    assert np.array_equal(whole["h"], split["h"])
+    assert [(r["accepted"], r["picard_total"]) for r in whole["cols"]] == \
+        [(r["accepted"], r["picard_total"]) for r in split["cols"]]
