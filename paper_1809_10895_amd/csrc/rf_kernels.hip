@@ -695,6 +695,34 @@ __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
     return scan_affine_down<T>(t * rd, wk, T(0), lane);
 }
 
+// The same for two columns at once, one per half-wave, two cells per lane
+// (cells k0 = 2 (lane & 31) and k0 + 1): r, rdp and t of the lane's two
+// cells (zero above the column's top); returns their z.  Each lane composes
+// the affine maps of its two cells, the composites are scanned over the
+// half, and the lane's cells are finished from its neighbour lane's prefix.
+template <typename T>
+__device__ __forceinline__ void zline_solve_pair(const T (&r)[2], const T (&rd)[2], const T (&t)[2],
+                                                 int lane, T (&z)[2])
+{
+    const bool first = (lane & 31) == 0, last = (lane & 31) == 31;
+    // forward sweep w_k = (r_k + t_{k-1} w_{k-1}) rdp_k
+    const T A0 = from_below<T>(t[1], T(0)) * rd[0], B0 = r[0] * rd[0];
+    const T A1 = t[0] * rd[1], B1 = r[1] * rd[1];
+    T fa = A1 * A0, fc = A1 * B0 + B1;
+    scan_affine_up_half<T>(fa, fc);
+    T wb = from_below<T>(fc, T(0));
+    if (first) wb = T(0);
+    const T w0 = A0 * wb + B0, w1 = A1 * w0 + B1;
+    // backward sweep z_k = w_k + t_k rdp_k z_{k+1}
+    const T C0 = t[0] * rd[0], C1 = t[1] * rd[1];
+    T bb = C0 * C1, bc = C0 * w1 + w0;
+    scan_affine_down_half<T>(bb, bc, lane);
+    T za = from_above<T>(bc, T(0));
+    if (last) za = T(0);
+    z[1] = C1 * za + w1;
+    z[0] = C0 * z[1] + w0;
+}
+
 // ---------------------------------------------------------------------------
 // Residual of the Picard system and PCG start
 // ---------------------------------------------------------------------------
@@ -783,6 +811,123 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
             }
             cv.z[i] = zs;
             v[0] += (double)rs * (double)zs;
+        }
+    }
+}
+
+// Two columns of at most 64 cells at once, one per half-wave, two cells per
+// lane: cells k0 = 2 (lane & 31) and k0 + 1 of this half's column (active
+// length kt, first cell i0 = its index of k0).  Per cell, the arithmetic of
+// resid_column; the z-line pivots and sweeps first compose each lane's two
+// cells and then scan over the 32 lanes of the half (half the scan steps per
+// cell, and no chaining across four rows).  Kp, hp, Dp, bp, tzs, rds: the two
+// cells' values; Kn, hn, nb: their lateral neighbours.
+template <int PRECOND, typename T>
+__device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, double *bout,
+                                           int refactor, int kt, size_t i0, int k0, int lane,
+                                           const double (&Kp)[2], const double (&hp)[2],
+                                           const double (&Dp)[2], const double (&bp)[2],
+                                           const double (&Kn)[2][4], const double (&hn)[2][4],
+                                           const bool (&nb)[2][4], const double (&tzs)[2],
+                                           const double (&rds)[2], double (&v)[2])
+{
+    constexpr bool kCopyKD = !std::is_same<T, double>::value;
+    const double gz[2] = {gdot(g, 4), gdot(g, 5)};
+    // below the first cell lies the lower lane's second, above the second
+    // cell the upper lane's first (masked by k > 0 and k + 1 < kt)
+    const double Kd[2] = {from_below(Kp[1], 0.0), Kp[0]}, hd[2] = {from_below(hp[1], 0.0), hp[0]};
+    const double Ku[2] = {Kp[1], from_above(Kp[0], 0.0)}, hu[2] = {hp[1], from_above(hp[0], 0.0)};
+    const bool keep_diag = PRECOND == RF_PRECOND_JACOBI || !refactor || bout != nullptr;
+    double diag[2], r[2], tup[2];
+    T rs[2];
+    bool act[2];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        const int k = k0 + c;
+        act[c] = k < kt;
+        double dg = act[c] ? Dp[c] : 1.0, Ap = Dp[c] * hp[c], b = bp[c], tu = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            if (!nb[c][d]) continue;
+            const double Kf = 0.5 * (Kp[c] + Kn[c][d]);
+            const double Tf = g.Tk[d >> 1] * Kf;
+            dg += Tf;
+            Ap += Tf * (hp[c] - hn[c][d]);
+            b += g.A[d >> 1] * Kf * gdot(g, d);
+        }
+        if (act[c] && k > 0) {
+            const double Kf = 0.5 * (Kp[c] + Kd[c]);
+            const double Tf = g.Tk[2] * Kf;
+            dg += Tf;
+            Ap += Tf * (hp[c] - hd[c]);
+            b += g.A[2] * Kf * gz[0];
+        }
+        if (act[c] && k + 1 < kt) {
+            const double Kf = 0.5 * (Kp[c] + Ku[c]);
+            tu = g.Tk[2] * Kf;
+            dg += tu;
+            Ap += tu * (hp[c] - hu[c]);
+            b += g.A[2] * Kf * gz[1];
+        }
+        diag[c] = dg;
+        tup[c] = tu;
+        r[c] = act[c] ? b - Ap : 0.0;
+        rs[c] = (T)r[c];
+        if (act[c]) {
+            const size_t i = i0 + c;
+            if (bout) bout[i] = b;
+            cv.r[i] = rs[c];
+            if (keep_diag) cv.diag[i] = (T)dg;
+            if (kCopyKD) {
+                cv.K[i] = (T)Kp[c];
+                cv.Dd[i] = (T)Dp[c];
+            }
+            v[1] = fmax(v[1], fabs(r[c] / dg));
+            if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs[c] * (double)(rs[c] / (T)dg);
+        }
+    }
+    if (PRECOND == RF_PRECOND_ZLINE) {
+        double tzv[2], rdp[2];
+        if (refactor) {
+            // leading minors P_k = diag_k P_{k-1} - t_{k-1}^2 P_{k-2}: the lane's
+            // two-cell matrix, scanned over the half, then the lower lane's
+            // prefix (P_{k0-1}, P_{k0-2}) carried through the lane's cells
+            const double tb = from_below(tup[1], 0.0);
+            const double q0 = act[0] ? tb * tb : 0.0, q1 = act[1] ? tup[0] * tup[0] : 0.0;
+            double m00 = diag[1] * diag[0] - q1, m01 = -(diag[1] * q0), m10 = diag[0], m11 = -q0;
+            rescale4(m00, m01, m10, m11);
+            scan_matrix_up_half(m00, m01, m10, m11);
+            double u0 = from_below(m00, 1.0), u1 = from_below(m10, 0.0);
+            if ((lane & 31) == 0) {
+                u0 = 1.0;
+                u1 = 0.0;
+            }
+            const double P0 = diag[0] * u0 - q0 * u1;
+            const double P1 = diag[1] * P0 - q1 * u0;
+            rdp[0] = act[0] ? u0 / P0 : 0.0;
+            rdp[1] = act[1] ? P0 / P1 : 0.0;
+            tzv[0] = tup[0];
+            tzv[1] = tup[1];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                tzv[c] = act[c] ? tzs[c] : 0.0;
+                rdp[c] = act[c] ? rds[c] : 0.0;
+            }
+        }
+        double z[2];
+        zline_solve_pair<double>(r, rdp, tzv, lane, z);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            if (!act[c]) continue;
+            const size_t i = i0 + c;
+            const T zs = (T)z[c];
+            if (refactor) {
+                cv.tz[i] = (T)tup[c];
+                cv.rdp[i] = (T)rdp[c];
+            }
+            cv.z[i] = zs;
+            v[0] += (double)rs[c] * (double)zs;
         }
     }
 }
@@ -967,8 +1112,9 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
 // at most one wave; the tile layout of Tile<TY>, one tile per block).  Every
 // wave reads K and h^m of its share of the tile's slots and Dd, bst of its
 // own columns (masked by their active lengths), stages K and h^m in LDS, and
-// forms each of its TY interior columns with resid_column, whose arithmetic
-// is that of k_resid.  The step flags are read first, alone (scalar loads),
+// forms its TY interior columns two at a time with resid_pair (one column
+// per half-wave, two cells per lane), whose arithmetic per cell is that of
+// k_resid.  The step flags are read first, alone (scalar loads),
 // so that each block of a launch past the end of the step ends after that
 // one round trip, with no vector load in flight; then the active lengths,
 // so that no lane above its column's top loads anything.  Three
@@ -991,7 +1137,11 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
     RF_WAVE_IDS;
     TileCols<TY> tc;
     tc.fetch(g, a.ktop, blockIdx.x, w);
-    double K[Tl::PER], h[Tl::PER], Dp[TY], bp[TY], tzs[TY], rds[TY];
+    static_assert(TY % 2 == 0, "columns are formed in pairs");
+    constexpr int NP = TY / 2;
+    // the lane's two cells in column h = lane >> 5 of each pair of own columns
+    const int half = lane >> 5, k0 = 2 * (lane & 31);
+    double K[Tl::PER], h[Tl::PER], Dp[NP][2], bp[NP][2], tzs[NP][2], rds[NP][2];
 #pragma unroll
     for (int u = 0; u < Tl::PER; u++) {
         K[u] = 0.0;
@@ -1002,19 +1152,27 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
             h[u] = hmv[i];
         }
     }
+    int okt[NP];
+    size_t i0[NP];
 #pragma unroll
-    for (int t = 0; t < TY; t++) {
-        Dp[t] = 0.0;
-        bp[t] = 0.0;
-        tzs[t] = 0.0;
-        rds[t] = 0.0;
-        if (lane < tc.okt[t]) {
-            const size_t i = (size_t)tc.oc[t] * g.nz + lane;
-            Dp[t] = a.Dd[i];
-            bp[t] = a.bst[i];
-            if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
-                tzs[t] = (double)cv.tz[i];
-                rds[t] = (double)cv.rdp[i];
+    for (int p = 0; p < NP; p++) {
+        const int oc = half ? tc.oc[2 * p + 1] : tc.oc[2 * p];
+        okt[p] = half ? tc.okt[2 * p + 1] : tc.okt[2 * p];
+        i0[p] = (size_t)(oc >= 0 ? oc : 0) * g.nz + k0;
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            Dp[p][c] = 0.0;
+            bp[p][c] = 0.0;
+            tzs[p][c] = 0.0;
+            rds[p][c] = 0.0;
+            if (k0 + c < okt[p]) {
+                const size_t i = i0[p] + c;
+                Dp[p][c] = a.Dd[i];
+                bp[p][c] = a.bst[i];
+                if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
+                    tzs[p][c] = (double)cv.tz[i];
+                    rds[p][c] = (double)cv.rdp[i];
+                }
             }
         }
     }
@@ -1031,22 +1189,29 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
     __syncthreads();
     double v[2] = {0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < TY; t++) {
-        const int c = Tl::own(w, t);
-        const int nbs[4] = {c - 1, c + 1, c - Tl::SX, c + Tl::SX};   // -x, +x, -y, +y
-        const bool act = lane < tc.okt[t];
-        const double Kp = act ? sK[c][lane] : 0.0, hp = act ? sH[c][lane] : 0.0;
-        double Kn[4], hn[4];
-        bool nb[4];
+    for (int p = 0; p < NP; p++) {
+        const int c0 = Tl::own(w, 2 * p + half);
+        const int nbs[4] = {c0 - 1, c0 + 1, c0 - Tl::SX, c0 + Tl::SX};   // -x, +x, -y, +y
+        int ktn[4];
 #pragma unroll
-        for (int d = 0; d < 4; d++) {
-            nb[d] = act && lane < sKt[nbs[d]];
-            Kn[d] = nb[d] ? sK[nbs[d]][lane] : 0.0;
-            hn[d] = nb[d] ? sH[nbs[d]][lane] : 0.0;
+        for (int d = 0; d < 4; d++) ktn[d] = sKt[nbs[d]];
+        double Kp[2], hp[2], Kn[2][4], hn[2][4];
+        bool nb[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int k = k0 + c;
+            const bool act = k < okt[p];
+            Kp[c] = act ? sK[c0][k] : 0.0;
+            hp[c] = act ? sH[c0][k] : 0.0;
+#pragma unroll
+            for (int d = 0; d < 4; d++) {
+                nb[c][d] = act && k < ktn[d];
+                Kn[c][d] = nb[c][d] ? sK[nbs[d]][k] : 0.0;
+                hn[c][d] = nb[c][d] ? sH[nbs[d]][k] : 0.0;
+            }
         }
-        const size_t i = (size_t)(tc.oc[t] >= 0 ? tc.oc[t] : 0) * g.nz + lane;
-        resid_column<PRECOND, T>(g, cv, bout, refactor, act, tc.okt[t], i, lane, Kp, hp, Dp[t],
-                                 bp[t], Kn, hn, nb, tzs[t], rds[t], v);
+        resid_pair<PRECOND, T>(g, cv, bout, refactor, okt[p], i0[p], k0, lane, Kp, hp, Dp[p],
+                               bp[p], Kn, hn, nb, tzs[p], rds[p], v);
     }
     block_partial<2, 2u>(v, a.pr);
     if (lead_thread()) resid_reset_scalars(s, m);
@@ -1440,59 +1605,55 @@ struct GroupCols {
     }
 };
 
-// Values of G columns of one wave read by the update kernel, loaded by the
-// lanes below each column's active length only: r, q, the z-line factors
-// (z-line) and the diagonal, unless it is rebuilt from the factors (rebuild:
-// the factors are this iteration's).
-template <int PRECOND, typename T, int G>
-struct UpdGroupM {
-    int col[G], kt[G];
-    T r[G], q[G], d[G], rd[G], t[G];
+// Values the update kernel reads for a group of two columns, one per
+// half-wave, two cells per lane (cells k0 = 2 (lane & 31) and k0 + 1),
+// loaded by the lanes below each column's active length only: r, q, the
+// z-line factors (z-line) and the diagonal, unless it is rebuilt from the
+// factors (rebuild: the factors are this iteration's).
+template <int PRECOND, typename T>
+struct UpdPair {
+    int kt;
+    size_t i0;
+    T r[2], q[2], d[2], rd[2], t[2];
 
-    __device__ __forceinline__ void load(const Geo &g, const CgVec<T> &cv, const GroupCols<G> &gc,
+    __device__ __forceinline__ void load(const Geo &g, const CgVec<T> &cv, const GroupCols<2> &gc,
                                          bool rebuild, int lane)
     {
+        const int half = lane >> 5, k0 = 2 * (lane & 31);
+        const int col = half ? gc.col[1] : gc.col[0];
+        kt = half ? gc.kt[1] : gc.kt[0];
+        i0 = (size_t)(col >= 0 ? col : 0) * g.nz + k0;
 #pragma unroll
-        for (int u = 0; u < G; u++) {
-            col[u] = gc.col[u];
-            kt[u] = gc.kt[u];
-            r[u] = q[u] = rd[u] = t[u] = T(0);
-            d[u] = T(1);
-            if (lane < kt[u]) {
-                const size_t i = (size_t)col[u] * g.nz + lane;
-                r[u] = cv.r[i];
-                q[u] = cv.q[i];
+        for (int c = 0; c < 2; c++) {
+            r[c] = q[c] = rd[c] = t[c] = T(0);
+            d[c] = T(1);
+            if (k0 + c < kt) {
+                const size_t i = i0 + c;
+                r[c] = cv.r[i];
+                q[c] = cv.q[i];
                 if (PRECOND == RF_PRECOND_ZLINE) {
-                    rd[u] = cv.rdp[i];
-                    t[u] = cv.tz[i];
+                    rd[c] = cv.rdp[i];
+                    t[c] = cv.tz[i];
                 }
-                if (PRECOND != RF_PRECOND_ZLINE || !rebuild) d[u] = cv.diag[i];
+                if (PRECOND != RF_PRECOND_ZLINE || !rebuild) d[c] = cv.diag[i];
             }
         }
     }
 };
-
-// The diagonal of a column cell from its z-line factors: with pivots d_k =
-// a_k - t_{k-1}^2 / d_{k-1} (rdp = 1/d), a_k = 1/rdp_k + t_{k-1}^2 rdp_{k-1}
-// (both terms positive, no cancellation).  rd, t: this lane's rdp and t
-// (zero above the column's top); the cell below's come from lane k-1.
-template <typename T>
-__device__ __forceinline__ T zline_diag(T rd, T t)
-{
-    const T rb = from_below<T>(rd, T(0)), tb = from_below<T>(t, T(0));
-    return T(1) / rd + tb * tb * rb;
-}
 
 // alpha = rho_j / p.q (every block combines the p.q partials; kept in the
 // scalars for e += alpha p, which the next spmv kernel applies since it reads
 // p anyway, or k_apply_h after the solve's last update); r -= alpha q, z =
 // M^-1 r; block partials of (r.z, max|r/diag|).  With the z-line
 // preconditioner factored from this iteration's matrix (rebuild), diag is
-// rebuilt from the column's pivots (zline_diag), so the kernel reads r, q,
-// rdp, tz and writes r, z.  Short columns: the loads
-// of a wave's first group of columns are issued before the partials are
-// combined, so the two are in flight together, and each further group is
-// loaded while the one before it is computed.
+// rebuilt from the column's pivots d_k = a_k - t_{k-1}^2 / d_{k-1} (rdp =
+// 1/d): a_k = 1/rdp_k + t_{k-1}^2 rdp_{k-1}, both terms positive, no
+// cancellation; so the kernel reads r, q, rdp, tz and writes r, z.  Short
+// columns: two at a time, one per half-wave, two cells per lane
+// (zline_solve_pair); the loads of a wave's first group of columns are
+// issued before the partials are combined, so the two are in flight
+// together, and each further group is loaded while the one before it is
+// computed.
 template <int PRECOND, typename T>
 __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> cv, int parity,
                                                      int rebuild)
@@ -1521,7 +1682,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
         double pv[1];
         gather_partials<1, 0u>(a.pq + g.foff, g.np, pv);
         if (stop) return;
-        UpdGroupM<PRECOND, T, G> ga, gb;
+        UpdPair<PRECOND, T> ga, gb;
         ga.load(g, cv, ka, rebuild, lane);
         double tot[1];
         combine_partials<1, 0u>(pv, tot);
@@ -1529,26 +1690,41 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
         const T alpha = (T)alpha_d;
         T *__restrict__ rv = cv.r;
         T *__restrict__ zv = cv.z;
-        auto work = [&](const UpdGroupM<PRECOND, T, G> &gr) {
+        const int k0 = 2 * (lane & 31);
+        auto work = [&](const UpdPair<PRECOND, T> &gr) {
+            bool act[2];
+            T r[2], dg[2], rd[2], t[2];
 #pragma unroll
-            for (int u = 0; u < G; u++) {
-                const bool act = lane < gr.kt[u];
-                const size_t i = (size_t)(gr.col[u] >= 0 ? gr.col[u] : 0) * g.nz + lane;
-                const T r = act ? gr.r[u] - alpha * gr.q[u] : T(0);
-                const T dg = (PRECOND == RF_PRECOND_ZLINE && rebuild)
-                                 ? zline_diag<T>(act ? gr.rd[u] : T(1), gr.t[u]) : gr.d[u];
-                if (act) {
-                    rv[i] = r;
-                    v[1] = fmax(v[1], (double)fabs(r / dg));
-                }
-                if (PRECOND == RF_PRECOND_JACOBI) {
-                    if (act) v[0] += (double)r * (double)(r / dg);
-                } else {
-                    const T zk = zline_solve_short<T>(r, act ? gr.rd[u] : T(0), act ? gr.t[u] : T(0), lane);
-                    if (act) {
-                        zv[i] = zk;
-                        v[0] += (double)r * (double)zk;
-                    }
+            for (int c = 0; c < 2; c++) {
+                act[c] = k0 + c < gr.kt;
+                r[c] = act[c] ? gr.r[c] - alpha * gr.q[c] : T(0);
+                rd[c] = act[c] ? gr.rd[c] : T(0);
+                t[c] = act[c] ? gr.t[c] : T(0);
+                dg[c] = gr.d[c];
+            }
+            if (PRECOND == RF_PRECOND_ZLINE && rebuild) {
+                // a_k = 1/rdp_k + t_{k-1}^2 rdp_{k-1}; the first cell's lower
+                // neighbour is the lower lane's second cell
+                const T r0 = act[0] ? gr.rd[0] : T(1), r1 = act[1] ? gr.rd[1] : T(1);
+                const T rb = from_below<T>(r1, T(0)), tb = from_below<T>(gr.t[1], T(0));
+                dg[0] = T(1) / r0 + tb * tb * rb;
+                dg[1] = T(1) / r1 + gr.t[0] * gr.t[0] * r0;
+            }
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                if (!act[c]) continue;
+                rv[gr.i0 + c] = r[c];
+                v[1] = fmax(v[1], (double)fabs(r[c] / dg[c]));
+                if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)r[c] * (double)(r[c] / dg[c]);
+            }
+            if (PRECOND == RF_PRECOND_ZLINE) {
+                T z[2];
+                zline_solve_pair<T>(r, rd, t, lane, z);
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    if (!act[c]) continue;
+                    zv[gr.i0 + c] = z[c];
+                    v[0] += (double)r[c] * (double)z[c];
                 }
             }
         };

@@ -26,6 +26,7 @@ enum : int {
     kDppRowShr = 0x110,   // + k: lane i of a row reads lane i - k of the same row
     kDppWaveShl1 = 0x130, // lane i reads lane i + 1 (lane 63: no source)
     kDppWaveShr1 = 0x138, // lane i reads lane i - 1 (lane 0: no source)
+    kDppRowBcast15 = 0x142, // every lane of row r >= 1 reads lane 16 r - 1
 };
 
 // x moved by the DPP pattern CTRL; lanes without a source lane get `old`.
@@ -42,6 +43,25 @@ __device__ __forceinline__ double dpp(double x, double old)
     const long long xi = __double_as_longlong(x), oi = __double_as_longlong(old);
     const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)xi, CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(xi >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                            (unsigned int)lo));
+}
+
+// The same in the rows named by ROWS (bit r: row r) only; the other rows get
+// `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows(float x, float old)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL,
+                                                      ROWS, 0xF, false));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double x, double old)
+{
+    const long long xi = __double_as_longlong(x), oi = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)xi, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(xi >> 32), CTRL, ROWS, 0xF, false);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
                                             (unsigned int)lo));
 }
@@ -116,21 +136,25 @@ __device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
     return b * cin + c;
 }
 
+// Exponent e of a finite x with |x| in [2^(e-1), 2^e) (v_frexp_exp_i32_f64;
+// 0 for x = 0).
+__device__ __forceinline__ int frexp_exponent(double x) { return __builtin_amdgcn_frexp_exp(x); }
+
 // Scales (m00, m01, m10, m11) by the power of two that brings the largest
 // magnitude into [1, 2) (exact; zero stays zero).
 __device__ __forceinline__ void rescale4(double &m00, double &m01, double &m10, double &m11)
 {
     const double sc = fmax(fmax(fabs(m00), fabs(m01)), fmax(fabs(m10), fabs(m11)));
-    const int ex = (sc > 0.0) ? ilogb(sc) : 0;
-    m00 = ldexp(m00, -ex); m01 = ldexp(m01, -ex); m10 = ldexp(m10, -ex); m11 = ldexp(m11, -ex);
+    const int ex = 1 - frexp_exponent(sc);
+    m00 = ldexp(m00, ex); m01 = ldexp(m01, ex); m10 = ldexp(m10, ex); m11 = ldexp(m11, ex);
 }
 
 __device__ __forceinline__ void rescale2(double &v0, double &v1)
 {
     const double sc = fmax(fabs(v0), fabs(v1));
-    const int ex = (sc > 0.0) ? ilogb(sc) : 0;
-    v0 = ldexp(v0, -ex);
-    v1 = ldexp(v1, -ex);
+    const int ex = 1 - frexp_exponent(sc);
+    v0 = ldexp(v0, ex);
+    v1 = ldexp(v1, ex);
 }
 
 // Pivots of a column tridiagonal T (diagonal diag_k, off-diagonal t_{k-1}
@@ -176,6 +200,86 @@ __device__ __forceinline__ double scan_pivots(double diag, double tprev2, double
     const double v0 = (row == 0) ? r0[0] : (row == 1) ? r0[1] : (row == 2) ? r0[2] : r0[3];
     const double v1 = (row == 0) ? r1[0] : (row == 1) ? r1[1] : (row == 2) ? r1[2] : r1[3];
     return (m00 * v0 + m01 * v1) / (m10 * v0 + m11 * v1);
+}
+
+// ---------------------------------------------------------------------------
+// Two columns per wave: column h in lanes 32h .. 32h + 31, each lane carrying
+// the composite of its consecutive cells.  The scans below run over the 32
+// lanes of each half: four doubling steps inside each 16-lane row, then the
+// second row of each half composes with its first row's total (row_bcast:15
+// into rows 1 and 3 for the upward scans; lanes 16 and 48 read back into rows
+// 0 and 2 for the downward one).
+// ---------------------------------------------------------------------------
+
+// Inclusive upward scan of affine maps x -> a x + c within each half:
+// (a, c) of lane l becomes the composite of the maps of lanes 32h .. l, the
+// later lanes applied last.
+template <typename T>
+__device__ __forceinline__ void scan_affine_up_half(T &a, T &c)
+{
+#define RF_UP_STEP(K)                                          \
+    {                                                          \
+        const T ao = dpp<kDppRowShr + (K)>(a, T(1));           \
+        const T co = dpp<kDppRowShr + (K)>(c, T(0));           \
+        c = a * co + c;                                        \
+        a = a * ao;                                            \
+    }
+    RF_UP_STEP(1) RF_UP_STEP(2) RF_UP_STEP(4) RF_UP_STEP(8)
+#undef RF_UP_STEP
+    const T ao = dpp_rows<kDppRowBcast15, 0xA>(a, T(1));
+    const T co = dpp_rows<kDppRowBcast15, 0xA>(c, T(0));
+    c = a * co + c;
+    a = a * ao;
+}
+
+// Inclusive downward scan of maps x -> b x + c within each half: (b, c) of
+// lane l becomes the composite of the maps of lanes l .. 32h + 31, the lower
+// lanes applied last.
+template <typename T>
+__device__ __forceinline__ void scan_affine_down_half(T &b, T &c, int lane)
+{
+#define RF_DOWN_STEP(K)                                        \
+    {                                                          \
+        const T bo = dpp<kDppRowShl + (K)>(b, T(1));           \
+        const T co = dpp<kDppRowShl + (K)>(c, T(0));           \
+        c = b * co + c;                                        \
+        b = b * bo;                                            \
+    }
+    RF_DOWN_STEP(1) RF_DOWN_STEP(2) RF_DOWN_STEP(4) RF_DOWN_STEP(8)
+#undef RF_DOWN_STEP
+    const T b16 = lane_value<16>(b), c16 = lane_value<16>(c);
+    const T b48 = lane_value<48>(b), c48 = lane_value<48>(c);
+    const int row = lane >> 4;
+    const T bo = (row == 0) ? b16 : (row == 2) ? b48 : T(1);
+    const T co = (row == 0) ? c16 : (row == 2) ? c48 : T(0);
+    c = b * co + c;
+    b = b * bo;
+}
+
+// Inclusive upward scan of 2x2 matrices within each half: m of lane l
+// becomes the product of the matrices of lanes 32h .. l, the later lanes on
+// the left, rescaled by a power of two after every step (only ratios of its
+// entries are used).
+__device__ __forceinline__ void scan_matrix_up_half(double &m00, double &m01, double &m10,
+                                                    double &m11)
+{
+#define RF_MAT_STEP(CTRL, ROWS)                                                 \
+    {                                                                           \
+        const double o00 = dpp_rows<CTRL, ROWS>(m00, 1.0);                      \
+        const double o01 = dpp_rows<CTRL, ROWS>(m01, 0.0);                      \
+        const double o10 = dpp_rows<CTRL, ROWS>(m10, 0.0);                      \
+        const double o11 = dpp_rows<CTRL, ROWS>(m11, 1.0);                      \
+        const double n00 = m00 * o00 + m01 * o10;                               \
+        const double n01 = m00 * o01 + m01 * o11;                               \
+        const double n10 = m10 * o00 + m11 * o10;                               \
+        const double n11 = m10 * o01 + m11 * o11;                               \
+        m00 = n00; m01 = n01; m10 = n10; m11 = n11;                             \
+        rescale4(m00, m01, m10, m11);                                           \
+    }
+    RF_MAT_STEP(kDppRowShr + 1, 0xF) RF_MAT_STEP(kDppRowShr + 2, 0xF)
+    RF_MAT_STEP(kDppRowShr + 4, 0xF) RF_MAT_STEP(kDppRowShr + 8, 0xF)
+    RF_MAT_STEP(kDppRowBcast15, 0xA)
+#undef RF_MAT_STEP
 }
 
 }  // namespace rf

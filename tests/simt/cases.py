@@ -14,7 +14,7 @@ def _fmt(xs):
 
 def solver_case(path, w, nsteps, dt, tol_picard=1e-6, tol_cg=1e-13, max_picard=100, max_cg=20000,
                 precond=1, ebats=0, dt0=None, dt_max=3600.0, precision=0, stencil=2, tile_rows=0,
-                cols_per_wave=0, use_static=0, cg_rel_tol=0.0):
+                cols_per_wave=0, use_static=0, cg_rel_tol=0.0, zline_refactor=0):
     lines = ["%d %d %d %r %r %r" % (w.nx, w.ny, w.nz, w.dx, w.dy, w.dz)]
     lines.append("1 " + _fmt(w.ktop) if w.ktop is not None else "0")
     g = w.grad_elev if w.grad_elev is not None else (0.0, 0.0, 1.0)
@@ -24,9 +24,9 @@ def solver_case(path, w, nsteps, dt, tol_picard=1e-6, tol_cg=1e-13, max_picard=1
     lines.append("1 " + _fmt(w.layer) if w.layer is not None else "0")
     lines.append("1 " + _fmt(w.lnks) if w.lnks is not None else "0")
     lines.append("%d %s" % (len(w.bcs), " ".join("%d %d %r" % (f, k, float(v)) for f, k, v in w.bcs)))
-    lines.append("%r %r %d %d %d %d %r %r %d %d %d %d %r" % (
+    lines.append("%r %r %d %d %d %d %r %r %d %d %d %d %r %d" % (
         tol_picard, tol_cg, max_picard, max_cg, precond, ebats, dt0 if dt0 else dt, dt_max, precision,
-        stencil, tile_rows, cols_per_wave, cg_rel_tol))
+        stencil, tile_rows, cols_per_wave, cg_rel_tol, zline_refactor))
     lines.append("%d %r" % (nsteps, dt))
     lines.append(_fmt(w.h0))
     lines.append("%d" % use_static)

@@ -164,6 +164,7 @@ static int run_solver()
     o.tile_rows = ri();
     o.cols_per_wave = ri();
     o.cg_rel_tol = rd();
+    o.zline_refactor = ri();
     CHK(rf_set_options(c, &o));
     const int nsteps = ri();
     const double dt = rd();

@@ -158,12 +158,14 @@ void resolve_wave(Fiber *w, int n, unsigned b, int wi)
         case kReadLane: src = w[l].param; break;
         case kClock: break;
         case kDpp: {
-            const int c = w[l].param, r = l & 15;
+            const int c = w[l].param & 0xFFFF, rows = w[l].param >> 16, r = l & 15, row = l >> 4;
             if (c > 0x100 && c < 0x110) src = (r + (c - 0x100) < 16) ? l + (c - 0x100) : -1;       // row_shl
             else if (c > 0x110 && c < 0x120) src = (r - (c - 0x110) >= 0) ? l - (c - 0x110) : -1;  // row_shr
             else if (c == 0x130) src = (l + 1 < kWave) ? l + 1 : -1;                              // wave_shl1
             else if (c == 0x138) src = (l >= 1) ? l - 1 : -1;                                       // wave_shr1
+            else if (c == 0x142) src = (row >= 1) ? 16 * row - 1 : -1;                             // row_bcast15
             else fail("unsupported DPP control", b, wi);
+            if (!((rows >> row) & 1)) src = -1;                                                     // row masked off
             break;
         }
         default: fail("unknown cross-lane operation", b, wi);

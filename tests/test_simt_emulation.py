@@ -74,6 +74,35 @@ def test_solver_emulated_matches_oracle(exe, tmp_path):
         assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-10
 
 
+@pytest.mark.parametrize("precond,precision,refactor,tile_rows", [
+    (1, 1, 0, 2),     # z-line, FP32 PCG, tiles of 8 x 2
+    (0, 0, 0, 2),     # Jacobi
+    (1, 0, 1, 4),     # z-line factored once per step, tiles of 8 x 4
+])
+def test_solver_emulated_short_column_variants(exe, tmp_path, precond, precision, refactor,
+                                               tile_rows):
+    """The short-column kernels (two columns per wave, two cells per lane)
+    in their other instantiations: FP32 PCG vectors, the Jacobi
+    preconditioner, z-line factors kept from a step's first Picard iteration,
+    tiles of 8 x 4 columns.  Same Picard iterations as the oracle, heads to
+    1e-8 (FP32 solves: 10 tol_picard)."""
+    w = W.watershed(nx=10, ny=6, nz=20, kmin=10)
+    w.h0 = np.where(w.active_mask(), -1.5, 0.0)
+    P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
+    its = [P.step(600.0)[1]["picard_iters"] for _ in range(2)]
+    h_o, _ = P.get_state()
+    path = os.path.join(str(tmp_path), "short.txt")
+    cases.solver_case(path, w, 2, 600.0, stencil=1, precond=precond, precision=precision,
+                      zline_refactor=refactor, tile_rows=tile_rows)
+    out = cases.run(exe, "solver", path, timeout=600)
+    assert [s["status"] for s in out["steps"]] == [0, 0]
+    assert [s["picard_iters"] for s in out["steps"]] == its
+    if precision:
+        assert np.abs(out["h"] - h_o)[w.active_mask()].max() <= 1e-5
+    else:
+        assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-8
+
+
 def test_solver_emulated_resumed_solve_mixed(exe, tmp_path):
     """The 1-D column (long-column kernels) in mixed precision with a relative
     PCG exit and the Jacobi preconditioner: the second step's first solve
