@@ -690,7 +690,7 @@ __device__ __forceinline__ void zline_solve_long(const T *r, const T *rdp, const
 template <typename T>
 __device__ __forceinline__ T zline_solve_short(T r, T rd, T t, int lane)
 {
-    const T tp = from_below<T>(t, T(0));
+    const T tp = from_below0<T>(t);
     const T wk = scan_affine_up<T>(tp * rd, r * rd, T(0), lane);
     return scan_affine_down<T>(t * rd, wk, T(0), lane);
 }
@@ -706,18 +706,18 @@ __device__ __forceinline__ void zline_solve_pair(const T (&r)[2], const T (&rd)[
 {
     const bool first = (lane & 31) == 0, last = (lane & 31) == 31;
     // forward sweep w_k = (r_k + t_{k-1} w_{k-1}) rdp_k
-    const T A0 = from_below<T>(t[1], T(0)) * rd[0], B0 = r[0] * rd[0];
+    const T A0 = from_below0<T>(t[1]) * rd[0], B0 = r[0] * rd[0];
     const T A1 = t[0] * rd[1], B1 = r[1] * rd[1];
     T fa = A1 * A0, fc = A1 * B0 + B1;
     scan_affine_up_half<T>(fa, fc);
-    T wb = from_below<T>(fc, T(0));
+    T wb = from_below0<T>(fc);
     if (first) wb = T(0);
     const T w0 = A0 * wb + B0, w1 = A1 * w0 + B1;
     // backward sweep z_k = w_k + t_k rdp_k z_{k+1}
     const T C0 = t[0] * rd[0], C1 = t[1] * rd[1];
     T bb = C0 * C1, bc = C0 * w1 + w0;
     scan_affine_down_half<T>(bb, bc, lane);
-    T za = from_above<T>(bc, T(0));
+    T za = from_above0<T>(bc);
     if (last) za = T(0);
     z[1] = C1 * za + w1;
     z[0] = C0 * z[1] + w0;
@@ -747,8 +747,8 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
 {
     constexpr bool kCopyKD = !std::is_same<T, double>::value;
     const double gz[2] = {gdot(g, 4), gdot(g, 5)};
-    const double Kd = from_below(Kp, 0.0), hd = from_below(hp, 0.0);
-    const double Ku = from_above(Kp, 0.0), hu = from_above(hp, 0.0);
+    const double Kd = from_below0(Kp), hd = from_below0(hp);
+    const double Ku = from_above0(Kp), hu = from_above0(hp);
     double diag = act ? Dp : 1.0, Ap = Dp * hp, b = bp, tup = 0.0;
 #pragma unroll
     for (int d = 0; d < 4; d++) {
@@ -792,7 +792,7 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
         // of the step's first iteration
         double tzv, rdp;
         if (refactor) {
-            const double tprev = from_below(tup, 0.0);
+            const double tprev = from_below0(tup);
             const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
             tzv = tup;
             rdp = act ? 1.0 / dpiv : 0.0;
@@ -800,7 +800,7 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
             tzv = act ? tzs : 0.0;
             rdp = act ? rds : 0.0;
         }
-        const double tprev = from_below(tzv, 0.0);
+        const double tprev = from_below0(tzv);
         const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
         const double zk = scan_affine_down<double>(tzv * rdp, wk, 0.0, lane);
         if (act) {
@@ -835,8 +835,8 @@ __device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, dou
     const double gz[2] = {gdot(g, 4), gdot(g, 5)};
     // below the first cell lies the lower lane's second, above the second
     // cell the upper lane's first (masked by k > 0 and k + 1 < kt)
-    const double Kd[2] = {from_below(Kp[1], 0.0), Kp[0]}, hd[2] = {from_below(hp[1], 0.0), hp[0]};
-    const double Ku[2] = {Kp[1], from_above(Kp[0], 0.0)}, hu[2] = {hp[1], from_above(hp[0], 0.0)};
+    const double Kd[2] = {from_below0(Kp[1]), Kp[0]}, hd[2] = {from_below0(hp[1]), hp[0]};
+    const double Ku[2] = {Kp[1], from_above0(Kp[0])}, hu[2] = {hp[1], from_above0(hp[0])};
     const bool keep_diag = PRECOND == RF_PRECOND_JACOBI || !refactor || bout != nullptr;
     double diag[2], r[2], tup[2];
     T rs[2];
@@ -892,12 +892,12 @@ __device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, dou
             // leading minors P_k = diag_k P_{k-1} - t_{k-1}^2 P_{k-2}: the lane's
             // two-cell matrix, scanned over the half, then the lower lane's
             // prefix (P_{k0-1}, P_{k0-2}) carried through the lane's cells
-            const double tb = from_below(tup[1], 0.0);
+            const double tb = from_below0(tup[1]);
             const double q0 = act[0] ? tb * tb : 0.0, q1 = act[1] ? tup[0] * tup[0] : 0.0;
             double m00 = diag[1] * diag[0] - q1, m01 = -(diag[1] * q0), m10 = diag[0], m11 = -q0;
             rescale4(m00, m01, m10, m11);
             scan_matrix_up_half(m00, m01, m10, m11);
-            double u0 = from_below(m00, 1.0), u1 = from_below(m10, 0.0);
+            double u0 = from_below0(m00), u1 = from_below0(m10);
             if ((lane & 31) == 0) {
                 u0 = 1.0;
                 u1 = 0.0;
@@ -1352,8 +1352,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv(Geo g, Arrays a, CgVec<T> cv,
             for (int u = 0; u < G2; u++) {
                 const int kt = gr.cs[u].kt;
                 const T Kp = gr.K[u];
-                const T Kd = from_below(Kp, T(0)), pdn = from_below(pp[u], T(0));
-                const T Ku = from_above(Kp, T(0)), pup = from_above(pp[u], T(0));
+                const T Kd = from_below0(Kp), pdn = from_below0(pp[u]);
+                const T Ku = from_above0(Kp), pup = from_above0(pp[u]);
                 if (!gr.cs[u].act) continue;
                 T q = gr.D[u] * pp[u];
 #pragma unroll
@@ -1510,8 +1510,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
         const bool act = lane < tc.okt[t];
         const T pp = act ? sP[c][lane] : T(0);
         const T Kp = act ? sK[c][lane] : T(0);
-        const T Kd = from_below(Kp, T(0)), pdn = from_below(pp, T(0));
-        const T Ku = from_above(Kp, T(0)), pup = from_above(pp, T(0));
+        const T Kd = from_below0(Kp), pdn = from_below0(pp);
+        const T Ku = from_above0(Kp), pup = from_above0(pp);
         T q = Dd[t] * pp;
 #pragma unroll
         for (int d = 0; d < 4; d++) {
@@ -1706,7 +1706,7 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                 // a_k = 1/rdp_k + t_{k-1}^2 rdp_{k-1}; the first cell's lower
                 // neighbour is the lower lane's second cell
                 const T r0 = act[0] ? gr.rd[0] : T(1), r1 = act[1] ? gr.rd[1] : T(1);
-                const T rb = from_below<T>(r1, T(0)), tb = from_below<T>(gr.t[1], T(0));
+                const T rb = from_below0<T>(r1), tb = from_below0<T>(gr.t[1]);
                 dg[0] = T(1) / r0 + tb * tb * rb;
                 dg[1] = T(1) / r1 + gr.t[0] * gr.t[0] * r0;
             }

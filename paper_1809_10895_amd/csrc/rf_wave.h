@@ -47,6 +47,43 @@ __device__ __forceinline__ double dpp(double x, double old)
                                             (unsigned int)lo));
 }
 
+// x moved by CTRL; lanes without a source lane get 0 (the zero fill of DPP,
+// BOUND_CTRL = 1, so no register has to be set to the fill value first).
+template <int CTRL>
+__device__ __forceinline__ float dpp0(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp0(double x)
+{
+    const long long xi = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)xi, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(xi >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                            (unsigned int)lo));
+}
+
+// x moved by CTRL; lanes without a source lane get 1 (the low word of 1.0 is
+// the zero fill, only the high word is set first).
+template <int CTRL>
+__device__ __forceinline__ float dpp1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0x3F800000, __float_as_int(x), CTRL, 0xF, 0xF,
+                                                      false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp1(double x)
+{
+    const long long xi = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)xi, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0x3FF00000, (int)(xi >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                            (unsigned int)lo));
+}
+
 // The same in the rows named by ROWS (bit r: row r) only; the other rows get
 // `old`.
 template <int CTRL, int ROWS>
@@ -88,6 +125,11 @@ template <typename T>
 __device__ __forceinline__ T from_below(T x, T edge) { return dpp<kDppWaveShr1>(x, edge); }
 template <typename T>
 __device__ __forceinline__ T from_above(T x, T edge) { return dpp<kDppWaveShl1>(x, edge); }
+// The same with edge 0.
+template <typename T>
+__device__ __forceinline__ T from_below0(T x) { return dpp0<kDppWaveShr1>(x); }
+template <typename T>
+__device__ __forceinline__ T from_above0(T x) { return dpp0<kDppWaveShl1>(x); }
 
 // Inclusive upward scan of affine maps x_k = a_k x_{k-1} + c_k over the
 // wave (k = lane); returns x_k for x_{-1} = carry.  Inside each 16-lane row
@@ -99,8 +141,8 @@ __device__ __forceinline__ T scan_affine_up(T a, T c, T carry, int lane)
 {
 #define RF_UP_STEP(K)                                          \
     {                                                          \
-        const T ao = dpp<kDppRowShr + (K)>(a, T(1));           \
-        const T co = dpp<kDppRowShr + (K)>(c, T(0));           \
+        const T ao = dpp1<kDppRowShr + (K)>(a);                \
+        const T co = dpp0<kDppRowShr + (K)>(c);                \
         c = a * co + c;                                        \
         a = a * ao;                                            \
     }
@@ -121,8 +163,8 @@ __device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
 {
 #define RF_DOWN_STEP(K)                                        \
     {                                                          \
-        const T bo = dpp<kDppRowShl + (K)>(b, T(1));           \
-        const T co = dpp<kDppRowShl + (K)>(c, T(0));           \
+        const T bo = dpp1<kDppRowShl + (K)>(b);                \
+        const T co = dpp0<kDppRowShl + (K)>(c);                \
         c = b * co + c;                                        \
         b = b * bo;                                            \
     }
@@ -169,10 +211,10 @@ __device__ __forceinline__ double scan_pivots(double diag, double tprev2, double
     double m00 = diag, m01 = -tprev2, m10 = 1.0, m11 = 0.0;
 #define RF_PIV_STEP(K)                                                      \
     {                                                                       \
-        const double o00 = dpp<kDppRowShr + (K)>(m00, 1.0);                 \
-        const double o01 = dpp<kDppRowShr + (K)>(m01, 0.0);                 \
-        const double o10 = dpp<kDppRowShr + (K)>(m10, 0.0);                 \
-        const double o11 = dpp<kDppRowShr + (K)>(m11, 1.0);                 \
+        const double o00 = dpp1<kDppRowShr + (K)>(m00);                     \
+        const double o01 = dpp0<kDppRowShr + (K)>(m01);                     \
+        const double o10 = dpp0<kDppRowShr + (K)>(m10);                     \
+        const double o11 = dpp1<kDppRowShr + (K)>(m11);                     \
         const double n00 = m00 * o00 + m01 * o10;                           \
         const double n01 = m00 * o01 + m01 * o11;                           \
         const double n10 = m10 * o00 + m11 * o10;                           \
@@ -219,8 +261,8 @@ __device__ __forceinline__ void scan_affine_up_half(T &a, T &c)
 {
 #define RF_UP_STEP(K)                                          \
     {                                                          \
-        const T ao = dpp<kDppRowShr + (K)>(a, T(1));           \
-        const T co = dpp<kDppRowShr + (K)>(c, T(0));           \
+        const T ao = dpp1<kDppRowShr + (K)>(a);                \
+        const T co = dpp0<kDppRowShr + (K)>(c);                \
         c = a * co + c;                                        \
         a = a * ao;                                            \
     }
@@ -240,8 +282,8 @@ __device__ __forceinline__ void scan_affine_down_half(T &b, T &c, int lane)
 {
 #define RF_DOWN_STEP(K)                                        \
     {                                                          \
-        const T bo = dpp<kDppRowShl + (K)>(b, T(1));           \
-        const T co = dpp<kDppRowShl + (K)>(c, T(0));           \
+        const T bo = dpp1<kDppRowShl + (K)>(b);                \
+        const T co = dpp0<kDppRowShl + (K)>(c);                \
         c = b * co + c;                                        \
         b = b * bo;                                            \
     }
@@ -263,12 +305,8 @@ __device__ __forceinline__ void scan_affine_down_half(T &b, T &c, int lane)
 __device__ __forceinline__ void scan_matrix_up_half(double &m00, double &m01, double &m10,
                                                     double &m11)
 {
-#define RF_MAT_STEP(CTRL, ROWS)                                                 \
+#define RF_MAT_MUL                                                              \
     {                                                                           \
-        const double o00 = dpp_rows<CTRL, ROWS>(m00, 1.0);                      \
-        const double o01 = dpp_rows<CTRL, ROWS>(m01, 0.0);                      \
-        const double o10 = dpp_rows<CTRL, ROWS>(m10, 0.0);                      \
-        const double o11 = dpp_rows<CTRL, ROWS>(m11, 1.0);                      \
         const double n00 = m00 * o00 + m01 * o10;                               \
         const double n01 = m00 * o01 + m01 * o11;                               \
         const double n10 = m10 * o00 + m11 * o10;                               \
@@ -276,10 +314,24 @@ __device__ __forceinline__ void scan_matrix_up_half(double &m00, double &m01, do
         m00 = n00; m01 = n01; m10 = n10; m11 = n11;                             \
         rescale4(m00, m01, m10, m11);                                           \
     }
-    RF_MAT_STEP(kDppRowShr + 1, 0xF) RF_MAT_STEP(kDppRowShr + 2, 0xF)
-    RF_MAT_STEP(kDppRowShr + 4, 0xF) RF_MAT_STEP(kDppRowShr + 8, 0xF)
-    RF_MAT_STEP(kDppRowBcast15, 0xA)
+#define RF_MAT_STEP(K)                                                          \
+    {                                                                           \
+        const double o00 = dpp1<kDppRowShr + (K)>(m00);                         \
+        const double o01 = dpp0<kDppRowShr + (K)>(m01);                         \
+        const double o10 = dpp0<kDppRowShr + (K)>(m10);                         \
+        const double o11 = dpp1<kDppRowShr + (K)>(m11);                         \
+        RF_MAT_MUL                                                              \
+    }
+    RF_MAT_STEP(1) RF_MAT_STEP(2) RF_MAT_STEP(4) RF_MAT_STEP(8)
+    {
+        const double o00 = dpp_rows<kDppRowBcast15, 0xA>(m00, 1.0);
+        const double o01 = dpp_rows<kDppRowBcast15, 0xA>(m01, 0.0);
+        const double o10 = dpp_rows<kDppRowBcast15, 0xA>(m10, 0.0);
+        const double o11 = dpp_rows<kDppRowBcast15, 0xA>(m11, 1.0);
+        RF_MAT_MUL
+    }
 #undef RF_MAT_STEP
+#undef RF_MAT_MUL
 }
 
 }  // namespace rf

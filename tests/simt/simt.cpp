@@ -158,7 +158,7 @@ void resolve_wave(Fiber *w, int n, unsigned b, int wi)
         case kReadLane: src = w[l].param; break;
         case kClock: break;
         case kDpp: {
-            const int c = w[l].param & 0xFFFF, rows = w[l].param >> 16, r = l & 15, row = l >> 4;
+            const int c = w[l].param & 0xFFFF, rows = (w[l].param >> 16) & 0xF, r = l & 15, row = l >> 4;
             if (c > 0x100 && c < 0x110) src = (r + (c - 0x100) < 16) ? l + (c - 0x100) : -1;       // row_shl
             else if (c > 0x110 && c < 0x120) src = (r - (c - 0x110) >= 0) ? l - (c - 0x110) : -1;  // row_shr
             else if (c == 0x130) src = (l + 1 < kWave) ? l + 1 : -1;                              // wave_shl1
@@ -173,7 +173,10 @@ void resolve_wave(Fiber *w, int n, unsigned b, int wi)
         if (f0.kind == kClock) {
             w[l].out = g_ops * 100;   // 100 ticks per resolved operation
         } else if (f0.kind == kDpp) {
-            if (src < 0) {
+            const bool masked = !((((w[l].param >> 16) & 0xF) >> (l >> 4)) & 1);
+            if (src < 0 && !masked && (w[l].param >> 20) & 1) {
+                w[l].out = 0;                                                 // zero fill
+            } else if (src < 0) {
                 w[l].out = w[l].in >> 32;                                     // keeps old
             } else {
                 if (src >= n || w[src].state == kDone) fail("DPP reads a lane that has exited", b, wi);

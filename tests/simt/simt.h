@@ -106,14 +106,16 @@ inline int __builtin_amdgcn_readlane(int v, int l)
     return simt::from_bits<int>(simt::lane_op(simt::kReadLane, simt::to_bits(v), l, 64));
 }
 // DPP move (GFX9 controls row_shl/row_shr 1-15, wave_shl1, wave_shr1,
-// row_bcast15; all banks enabled): a lane whose source lies outside its row
-// (or the wave), or whose row is not in row_mask, keeps `old`
+// row_bcast15; all banks enabled): a lane whose row is not in row_mask keeps
+// `old`; a lane whose source lies outside its row (or the wave) keeps `old`,
+// or gets 0 with bound_ctrl (zero fill, only with all rows enabled)
 inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
                                        bool bound_ctrl)
 {
-    if (row_mask < 1 || row_mask > 0xF || bank_mask != 0xF || bound_ctrl) abort();
+    if (row_mask < 1 || row_mask > 0xF || bank_mask != 0xF || (bound_ctrl && row_mask != 0xF)) abort();
     const uint64_t packed = ((uint64_t)(uint32_t)old << 32) | (uint32_t)src;
-    return simt::from_bits<int>(simt::lane_op(simt::kDpp, packed, ctrl | (row_mask << 16), 64));
+    return simt::from_bits<int>(simt::lane_op(simt::kDpp, packed,
+                                              ctrl | (row_mask << 16) | ((int)bound_ctrl << 20), 64));
 }
 // exponent e with |x| in [2^(e-1), 2^e) (v_frexp_exp_i32_f64: 0 for 0, inf, NaN)
 inline int __builtin_amdgcn_frexp_exp(double x)
