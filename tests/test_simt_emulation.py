@@ -88,14 +88,15 @@ def test_solver_emulated_short_column_variants(exe, tmp_path, precond, precision
     1e-8 (FP32 solves: 10 tol_picard)."""
     w = W.watershed(nx=10, ny=6, nz=20, kmin=10)
     w.h0 = np.where(w.active_mask(), -1.5, 0.0)
+    n = 1 if precond == 0 else 2        # Jacobi takes many more PCG iterations
     P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
-    its = [P.step(600.0)[1]["picard_iters"] for _ in range(2)]
+    its = [P.step(600.0)[1]["picard_iters"] for _ in range(n)]
     h_o, _ = P.get_state()
     path = os.path.join(str(tmp_path), "short.txt")
-    cases.solver_case(path, w, 2, 600.0, stencil=1, precond=precond, precision=precision,
+    cases.solver_case(path, w, n, 600.0, stencil=1, precond=precond, precision=precision,
                       zline_refactor=refactor, tile_rows=tile_rows)
     out = cases.run(exe, "solver", path, timeout=600)
-    assert [s["status"] for s in out["steps"]] == [0, 0]
+    assert [s["status"] for s in out["steps"]] == [0] * n
     assert [s["picard_iters"] for s in out["steps"]] == its
     if precision:
         assert np.abs(out["h"] - h_o)[w.active_mask()].max() <= 1e-5
