@@ -815,6 +815,18 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
     }
 }
 
+// max(m, |a_c| / d_c) over the lane's active cells c (d_c > 0) with one
+// division: the larger of the cross products |a_0| d_1, |a_1| d_0 over d_0 d_1.
+template <typename T>
+__device__ __forceinline__ double max_ratio_pair(double m, T a0, T d0, bool act0, T a1, T d1,
+                                                 bool act1)
+{
+    const double x0 = fabs((double)a0), x1 = fabs((double)a1);
+    const double num = act0 ? (act1 ? fmax(x0 * (double)d1, x1 * (double)d0) : x0) : x1;
+    const double den = act0 ? (act1 ? (double)d0 * (double)d1 : (double)d0) : (double)d1;
+    return (act0 || act1) ? fmax(m, num / den) : m;
+}
+
 // Two columns of at most 64 cells at once, one per half-wave, two cells per
 // lane: cells k0 = 2 (lane & 31) and k0 + 1 of this half's column (active
 // length kt, first cell i0 = its index of k0).  Per cell, the arithmetic of
@@ -882,10 +894,10 @@ __device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, dou
                 cv.K[i] = (T)Kp[c];
                 cv.Dd[i] = (T)Dp[c];
             }
-            v[1] = fmax(v[1], fabs(r[c] / dg));
             if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs[c] * (double)(rs[c] / (T)dg);
         }
     }
+    v[1] = max_ratio_pair<double>(v[1], r[0], diag[0], act[0], r[1], diag[1], act[1]);
     if (PRECOND == RF_PRECOND_ZLINE) {
         double tzv[2], rdp[2];
         if (refactor) {
@@ -904,8 +916,10 @@ __device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, dou
             }
             const double P0 = diag[0] * u0 - q0 * u1;
             const double P1 = diag[1] * P0 - q1 * u0;
-            rdp[0] = act[0] ? u0 / P0 : 0.0;
-            rdp[1] = act[1] ? P0 / P1 : 0.0;
+            // 1/d_k = P_{k-1} / P_k for both cells from one division
+            const double inv = 1.0 / (P0 * P1);
+            rdp[0] = act[0] ? u0 * P1 * inv : 0.0;
+            rdp[1] = act[1] ? P0 * P0 * inv : 0.0;
             tzv[0] = tup[0];
             tzv[1] = tup[1];
         } else {
@@ -1707,16 +1721,17 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                 // neighbour is the lower lane's second cell
                 const T r0 = act[0] ? gr.rd[0] : T(1), r1 = act[1] ? gr.rd[1] : T(1);
                 const T rb = from_below0<T>(r1), tb = from_below0<T>(gr.t[1]);
-                dg[0] = T(1) / r0 + tb * tb * rb;
-                dg[1] = T(1) / r1 + gr.t[0] * gr.t[0] * r0;
+                const T inv = T(1) / (r0 * r1);   // 1/r0 = r1 inv, 1/r1 = r0 inv
+                dg[0] = r1 * inv + tb * tb * rb;
+                dg[1] = r0 * inv + gr.t[0] * gr.t[0] * r0;
             }
 #pragma unroll
             for (int c = 0; c < 2; c++) {
                 if (!act[c]) continue;
                 rv[gr.i0 + c] = r[c];
-                v[1] = fmax(v[1], (double)fabs(r[c] / dg[c]));
                 if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)r[c] * (double)(r[c] / dg[c]);
             }
+            v[1] = max_ratio_pair<T>(v[1], r[0], dg[0], act[0], r[1], dg[1], act[1]);
             if (PRECOND == RF_PRECOND_ZLINE) {
                 T z[2];
                 zline_solve_pair<T>(r, rd, t, lane, z);
