@@ -404,6 +404,16 @@ static void set_shapes(rf_ctx *c)
         G.np = G.nblk;
         G.foff = 0;
     }
+    // k_coeff and k_accept walk runs of active cells, FP64-ALU bound: where
+    // their partials are folded anyway (large grids), a grid of kRunsPerWave
+    // runs per wave pays each wave's start-up (the record and the soil table)
+    // over several runs; elsewhere they take the reducing kernels' grid,
+    // whose partials the host reads as written
+    G.nblk_r = G.nblk;
+    if (G.np == 1 && G.foff != 0) {
+        const long per = (long)kWavesPerBlock * kRunsPerWave;
+        G.nblk_r = (int)std::max<long>(8, std::min<long>(G.nblk, (G.nchunk + per - 1) / per));
+    }
 }
 
 

@@ -14,6 +14,7 @@ constexpr int kWave = 64;           // CDNA wavefront
 constexpr int kWavesPerBlock = 8;   // one column per wave at a time
 constexpr int kThreads = kWave * kWavesPerBlock;
 constexpr int kPartialsMax = 512;   // partials every block of a consumer kernel may combine
+constexpr int kRunsPerWave = 12;     // runs of active cells per wave of k_coeff / k_accept on large grids
 constexpr int kRedSlots = 8;        // values per block partial
 constexpr int kTileX = 8;           // tiled stencil kernels: interior columns of a tile along x
                                     // (one per wave); along y: Geo::tile_y (2 or 4)
@@ -49,6 +50,7 @@ struct Geo {
     int ntx;                // tiles along x
     int nblk_t;             // tiled kernels: blocks (one tile each)
     int nchunk;             // runs of kWave consecutive active cells (column order)
+    int nblk_r;             // blocks of the kernels over those runs (k_coeff, k_accept)
     long nact;              // active cells
     double V;               // cell volume
     double A[3];            // face areas normal to x, y, z

@@ -2153,6 +2153,15 @@ hipError_t launch_init_ks(const Geo &g, const Soil &so, const Arrays &a, hipStre
         return launch_fold(g, P, nv, mask, s);                                          \
     } while (0)
 
+// A kernel over runs of active cells (nblk_r blocks) and the fold of its
+// partials.
+#define RF_LAUNCH_FOLD_R(P, nv, mask, kern, ...)                                        \
+    do {                                                                                \
+        const hipError_t e_ = [&]() { RF_LAUNCH_N(g.nblk_r, kern, __VA_ARGS__); }();      \
+        if (e_ != hipSuccess) return e_;                                                \
+        return launch_fold(g, P, nv, mask, s, g.nblk_r);                                \
+    } while (0)
+
 // A tiled kernel (nblk_t blocks) and the fold of its partials.
 #define RF_LAUNCH_TILED(P, nv, mask, kern, ...)                                         \
     do {                                                                                \
@@ -2209,10 +2218,10 @@ hipError_t launch_coeff(const Geo &g, const Soil &so, const Arrays &a, int m, do
                         double chord_eps, int variant, hipStream_t s)
 {
     if (so.model == RF_GARDNER)
-        RF_LAUNCH((k_coeff<RF_GARDNER, false>), g, so, a, m, dt, chord_eps, variant);
+        RF_LAUNCH_N(g.nblk_r, (k_coeff<RF_GARDNER, false>), g, so, a, m, dt, chord_eps, variant);
     // branch-free van Genuchten-Mualem on columns of at most one wave
-    if (g.nz <= kWave) RF_LAUNCH((k_coeff<RF_VGM, true>), g, so, a, m, dt, chord_eps, variant);
-    RF_LAUNCH((k_coeff<RF_VGM, false>), g, so, a, m, dt, chord_eps, variant);
+    if (g.nz <= kWave) RF_LAUNCH_N(g.nblk_r, (k_coeff<RF_VGM, true>), g, so, a, m, dt, chord_eps, variant);
+    RF_LAUNCH_N(g.nblk_r, (k_coeff<RF_VGM, false>), g, so, a, m, dt, chord_eps, variant);
 }
 
 // The PCG arrays of the FP64 solve: the workspace arrays themselves.
@@ -2328,12 +2337,12 @@ hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool tra
     // van Genuchten-Mualem branch-free on columns of at most one wave (the
     // arithmetic the solver has always used there), branching on taller ones
     const bool vgm = so.model == RF_VGM, flat = vgm && g.nz <= kWave;
-    if (track && flat) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_VGM, true>), g, so, a, serial);
-    if (track && vgm) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_VGM, false>), g, so, a, serial);
-    if (track) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<true, RF_GARDNER, false>), g, so, a, serial);
-    if (flat) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_VGM, true>), g, so, a, serial);
-    if (vgm) RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_VGM, false>), g, so, a, serial);
-    RF_LAUNCH_FOLD(a.ps, 7, 0u, (k_accept<false, RF_GARDNER, false>), g, so, a, serial);
+    if (track && flat) RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<true, RF_VGM, true>), g, so, a, serial);
+    if (track && vgm) RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<true, RF_VGM, false>), g, so, a, serial);
+    if (track) RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<true, RF_GARDNER, false>), g, so, a, serial);
+    if (flat) RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<false, RF_VGM, true>), g, so, a, serial);
+    if (vgm) RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<false, RF_VGM, false>), g, so, a, serial);
+    RF_LAUNCH_FOLD_R(a.ps, 7, 0u, (k_accept<false, RF_GARDNER, false>), g, so, a, serial);
 }
 
 hipError_t launch_eval_soil(const Geo &g, const Soil &so, const Arrays &a, const double *h,
