@@ -55,9 +55,11 @@ def ens_case(path, w, t_ends, tol_picard=1e-6, max_picard=50, chord_eps=1e-9, dt
         f.write("\n".join(lines) + "\n")
 
 
-def run(exe, mode, path, timeout=900):
+def run(exe, mode, path, timeout=900, fill=0):
+    """Runs the driver on a case file; `fill` is the byte the driver writes
+    into every device buffer before the library sees it."""
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
-               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1", SIMT_FILL=str(fill))
     r = subprocess.run([exe, mode, path], capture_output=True, text=True, timeout=timeout, env=env)
     if r.returncode != 0:
         raise RuntimeError("driver exited with %d:\n%s\n%s" % (r.returncode, r.stdout[-3000:],

@@ -31,11 +31,15 @@ static std::vector<T> rv(size_t n)
     for (size_t i = 0; i < n; i++) v[i] = (T)rd();
     return v;
 }
+// Device buffers of the case: filled with the byte SIMT_FILL names (default
+// 0), so that a run can show whether anything reads memory it never wrote
+// (0xFF reads as NaN in every floating-point type).
 static void *aligned(size_t n)
 {
     void *p = nullptr;
     if (posix_memalign(&p, 256, n ? n : 256)) exit(3);
-    memset(p, 0, n);
+    const char *f = getenv("SIMT_FILL");
+    memset(p, f ? (int)strtol(f, nullptr, 0) : 0, n);
     return p;
 }
 #define CHK(x)                                                                  \
