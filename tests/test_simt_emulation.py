@@ -14,6 +14,7 @@ the oracle's, heads within 1e-8 (FP32 solves: 1e-5 m), and no sanitizer
 report."""
 import os
 import shutil
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -74,34 +75,41 @@ def test_solver_emulated_matches_oracle(exe, tmp_path):
         assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-10
 
 
-@pytest.mark.parametrize("precond,precision,refactor,tile_rows", [
-    (1, 1, 0, 2),     # z-line, FP32 PCG, tiles of 8 x 2
-    (0, 0, 0, 2),     # Jacobi
-    (1, 0, 1, 4),     # z-line factored once per step, tiles of 8 x 4
-])
-def test_solver_emulated_short_column_variants(exe, tmp_path, precond, precision, refactor,
-                                               tile_rows):
+def test_solver_emulated_short_column_variants(exe, tmp_path):
     """The short-column kernels (two columns per wave, two cells per lane)
     in their other instantiations: FP32 PCG vectors, the Jacobi
     preconditioner, z-line factors kept from a step's first Picard iteration,
     tiles of 8 x 4 columns.  Same Picard iterations as the oracle, heads to
-    1e-8 (FP32 solves: 10 tol_picard)."""
+    1e-8 (FP32 solves: 10 tol_picard).  The three cases run as concurrent
+    driver processes."""
     w = W.watershed(nx=10, ny=6, nz=20, kmin=10)
     w.h0 = np.where(w.active_mask(), -1.5, 0.0)
-    n = 1 if precond == 0 else 2        # Jacobi takes many more PCG iterations
+    variants = [  # precond, precision, zline_refactor, tile_rows, steps
+        (1, 1, 0, 2, 2),     # z-line, FP32 PCG, tiles of 8 x 2
+        (0, 0, 0, 2, 1),     # Jacobi (many more PCG iterations: one step)
+        (1, 0, 1, 4, 2),     # z-line factored once per step, tiles of 8 x 4
+    ]
+    paths = []
+    for i, (precond, precision, refactor, tile_rows, n) in enumerate(variants):
+        paths.append(os.path.join(str(tmp_path), "short%d.txt" % i))
+        cases.solver_case(paths[-1], w, n, 600.0, stencil=1, precond=precond, precision=precision,
+                          zline_refactor=refactor, tile_rows=tile_rows)
+    with ThreadPoolExecutor(len(paths)) as pool:
+        outs = list(pool.map(lambda p: cases.run(exe, "solver", p, timeout=600), paths))
     P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
-    its = [P.step(600.0)[1]["picard_iters"] for _ in range(n)]
-    h_o, _ = P.get_state()
-    path = os.path.join(str(tmp_path), "short.txt")
-    cases.solver_case(path, w, n, 600.0, stencil=1, precond=precond, precision=precision,
-                      zline_refactor=refactor, tile_rows=tile_rows)
-    out = cases.run(exe, "solver", path, timeout=600)
-    assert [s["status"] for s in out["steps"]] == [0] * n
-    assert [s["picard_iters"] for s in out["steps"]] == its
-    if precision:
-        assert np.abs(out["h"] - h_o)[w.active_mask()].max() <= 1e-5
-    else:
-        assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-8
+    its = [P.step(600.0)[1]["picard_iters"] for _ in range(2)]
+    h2, _ = P.get_state()
+    P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
+    P.step(600.0)
+    h1, _ = P.get_state()
+    for (precond, precision, refactor, tile_rows, n), out in zip(variants, outs):
+        h_o = h1 if n == 1 else h2
+        assert [s["status"] for s in out["steps"]] == [0] * n
+        assert [s["picard_iters"] for s in out["steps"]] == its[:n], (precond, precision, refactor)
+        if precision:
+            assert np.abs(out["h"] - h_o)[w.active_mask()].max() <= 1e-5
+        else:
+            assert rel_err(out["h"], h_o, w.active_mask()) <= 1e-8
 
 
 def test_solver_emulated_resumed_solve_mixed(exe, tmp_path):
@@ -244,14 +252,16 @@ def test_results_do_not_depend_on_prior_memory_contents(exe, tmp_path):
     has not written (stale contents left by earlier GPU work in a process
     cannot change a run)."""
     w = small_ensemble([1, 5, 63, 64, 65, 129], seed=3)
-    path = os.path.join(str(tmp_path), "ens.txt")
-    cases.ens_case(path, w, [w.t_end])
-    a, b = (cases.run(exe, "ens", path, timeout=600, fill=f) for f in (0, 0xFF))
-    assert a["runs"] == b["runs"] and a["cols"] == b["cols"]
-    assert np.array_equal(a["h"], b["h"])
-    g = W.watershed(nx=10, ny=6, nz=20, kmin=10)
+    ens_path = os.path.join(str(tmp_path), "ens.txt")
+    cases.ens_case(ens_path, w, [w.t_end])
+    g = W.watershed(nx=9, ny=3, nz=12, kmin=6)
     g.h0 = np.where(g.active_mask(), -1.5, 0.0)
-    path = os.path.join(str(tmp_path), "solver.txt")
-    cases.solver_case(path, g, 1, 600.0, stencil=1)
-    a, b = (cases.run(exe, "solver", path, timeout=600, fill=f) for f in (0, 0xFF))
-    assert a["steps"] == b["steps"] and np.array_equal(a["h"], b["h"])
+    sol_path = os.path.join(str(tmp_path), "solver.txt")
+    cases.solver_case(sol_path, g, 1, 600.0, stencil=1)
+    with ThreadPoolExecutor(4) as pool:   # four independent driver processes
+        ea, eb, sa, sb = pool.map(lambda a: cases.run(exe, a[0], a[1], timeout=600, fill=a[2]),
+                                  [("ens", ens_path, 0), ("ens", ens_path, 0xFF),
+                                   ("solver", sol_path, 0), ("solver", sol_path, 0xFF)])
+    assert ea["runs"] == eb["runs"] and ea["cols"] == eb["cols"]
+    assert np.array_equal(ea["h"], eb["h"])
+    assert sa["steps"] == sb["steps"] and np.array_equal(sa["h"], sb["h"])
