@@ -550,8 +550,11 @@ __global__ void __launch_bounds__(kThreads) k_decide(Geo g, Arrays a, int m, dou
 {
     Scalars *s = a.sc;
     if (s->fail || s->stall || s->picard_done) return;
+    // the nblk partials of k_apply_h as it wrote them (no fold kernel: this
+    // one-block kernel is their only reader; a max and a count combine alike
+    // in any order)
     double tot[2];
-    reduce_partials<2, 1u>(a.pd + 2 * g.foff, g.np, tot);
+    reduce_partials<2, 1u>(a.pd, g.nblk, tot);
     if (threadIdx.x == 0) {
         if (m - 1 < RF_MAX_PICARD_LOG) s->delta_log[m - 1] = tot[0];
         if (tot[1] > 0.0 || !isfinite(tot[0])) {
@@ -2324,11 +2327,12 @@ hipError_t launch_update(const Geo &g, const Arrays &a, int precond, bool mixed,
 hipError_t launch_apply_h(const Geo &g, const Arrays &a, int m, bool mixed, const CgTol &t,
                           hipStream_t s)
 {
+    // its partials are combined by k_decide itself
     if (mixed)
-        RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<float>, g, a, (const float *)a.f.e,
-                       (const float *)a.f.p0, (const float *)a.f.p1, m, t.tol_cg, t.rel, t.max_cg);
-    RF_LAUNCH_FOLD(a.pd, 2, 1u, k_apply_h<double>, g, a, (const double *)a.e, (const double *)a.p0,
-                   (const double *)a.p1, m, t.tol_cg, t.rel, t.max_cg);
+        RF_LAUNCH(k_apply_h<float>, g, a, (const float *)a.f.e, (const float *)a.f.p0,
+                  (const float *)a.f.p1, m, t.tol_cg, t.rel, t.max_cg);
+    RF_LAUNCH(k_apply_h<double>, g, a, (const double *)a.e, (const double *)a.p0,
+              (const double *)a.p1, m, t.tol_cg, t.rel, t.max_cg);
 }
 
 hipError_t launch_accept(const Geo &g, const Soil &so, const Arrays &a, bool track, int serial,
