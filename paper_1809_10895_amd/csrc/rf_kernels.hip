@@ -819,15 +819,18 @@ __device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, d
 }
 
 // max(m, |a_c| / d_c) over the lane's active cells c (d_c > 0) with one
-// division: the larger of the cross products |a_0| d_1, |a_1| d_0 over d_0 d_1.
+// division: with d_c = 2^-e_c c_c, c_c in [1, 2) (exact scalings, so that no
+// product over- or underflows where the quotients do not),
+// |a_c| / d_c = 2^e_c |a_c| c_other / (c_0 c_1).
 template <typename T>
 __device__ __forceinline__ double max_ratio_pair(double m, T a0, T d0, bool act0, T a1, T d1,
                                                  bool act1)
 {
-    const double x0 = fabs((double)a0), x1 = fabs((double)a1);
-    const double num = act0 ? (act1 ? fmax(x0 * (double)d1, x1 * (double)d0) : x0) : x1;
-    const double den = act0 ? (act1 ? (double)d0 * (double)d1 : (double)d0) : (double)d1;
-    return (act0 || act1) ? fmax(m, num / den) : m;
+    const int e0 = 1 - frexp_exponent((double)d0), e1 = 1 - frexp_exponent((double)d1);
+    const double c0 = ldexp((double)d0, e0), c1 = ldexp((double)d1, e1);
+    const double n0 = act0 ? ldexp(fabs((double)a0) * c1, e0) : 0.0;
+    const double n1 = act1 ? ldexp(fabs((double)a1) * c0, e1) : 0.0;
+    return (act0 || act1) ? fmax(m, fmax(n0, n1) / (c0 * c1)) : m;
 }
 
 // Two columns of at most 64 cells at once, one per half-wave, two cells per
@@ -919,10 +922,14 @@ __device__ __forceinline__ void resid_pair(const Geo &g, const CgVec<T> &cv, dou
             }
             const double P0 = diag[0] * u0 - q0 * u1;
             const double P1 = diag[1] * P0 - q1 * u0;
-            // 1/d_k = P_{k-1} / P_k for both cells from one division
-            const double inv = 1.0 / (P0 * P1);
-            rdp[0] = act[0] ? u0 * P1 * inv : 0.0;
-            rdp[1] = act[1] ? P0 * P0 * inv : 0.0;
+            // 1/d_k = P_{k-1} / P_k for both cells from one division, with
+            // P_c = 2^-s_c p_c, p_c in [1, 2) (exact scalings: no product of
+            // two minors can over- or underflow)
+            const int s0 = 1 - frexp_exponent(P0), s1 = 1 - frexp_exponent(P1);
+            const double p0 = ldexp(P0, s0), p1 = ldexp(P1, s1);
+            const double inv = 1.0 / (p0 * p1);
+            rdp[0] = act[0] ? ldexp(u0 * p1 * inv, s0) : 0.0;        // u0 / P0
+            rdp[1] = act[1] ? ldexp(p0 * p0 * inv, s1 - s0) : 0.0;   // P0 / P1
             tzv[0] = tup[0];
             tzv[1] = tup[1];
         } else {
@@ -1724,9 +1731,13 @@ __global__ void __launch_bounds__(kThreads) k_update(Geo g, Arrays a, CgVec<T> c
                 // neighbour is the lower lane's second cell
                 const T r0 = act[0] ? gr.rd[0] : T(1), r1 = act[1] ? gr.rd[1] : T(1);
                 const T rb = from_below0<T>(r1), tb = from_below0<T>(gr.t[1]);
-                const T inv = T(1) / (r0 * r1);   // 1/r0 = r1 inv, 1/r1 = r0 inv
-                dg[0] = r1 * inv + tb * tb * rb;
-                dg[1] = r0 * inv + gr.t[0] * gr.t[0] * r0;
+                // 1/r0 and 1/r1 from one division, with r_c = 2^-e_c s_c,
+                // s_c in [1, 2) (exact scalings: no overflow of r0 r1 in FP32)
+                const int e0 = 1 - frexp_exponent(r0), e1 = 1 - frexp_exponent(r1);
+                const T s0 = ldexp(r0, e0), s1 = ldexp(r1, e1);
+                const T inv = T(1) / (s0 * s1);
+                dg[0] = ldexp(s1 * inv, e0) + tb * tb * rb;
+                dg[1] = ldexp(s0 * inv, e1) + gr.t[0] * gr.t[0] * r0;
             }
 #pragma unroll
             for (int c = 0; c < 2; c++) {

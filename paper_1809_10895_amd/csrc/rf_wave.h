@@ -181,6 +181,7 @@ __device__ __forceinline__ T scan_affine_down(T b, T c, T carry, int lane)
 // Exponent e of a finite x with |x| in [2^(e-1), 2^e) (v_frexp_exp_i32_f64;
 // 0 for x = 0).
 __device__ __forceinline__ int frexp_exponent(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ __forceinline__ int frexp_exponent(float x) { return __builtin_amdgcn_frexp_expf(x); }
 
 // Scales (m00, m01, m10, m11) by the power of two that brings the largest
 // magnitude into [1, 2) (exact; zero stays zero).

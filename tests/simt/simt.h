@@ -117,10 +117,17 @@ inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask,
     return simt::from_bits<int>(simt::lane_op(simt::kDpp, packed,
                                               ctrl | (row_mask << 16) | ((int)bound_ctrl << 20), 64));
 }
-// exponent e with |x| in [2^(e-1), 2^e) (v_frexp_exp_i32_f64: 0 for 0, inf, NaN)
+// exponent e with |x| in [2^(e-1), 2^e) (v_frexp_exp_i32_f64 / _f32: 0 for 0, inf, NaN)
 inline int __builtin_amdgcn_frexp_exp(double x)
 {
     if (x == 0.0 || !std::isfinite(x)) return 0;
+    int e = 0;
+    std::frexp(x, &e);
+    return e;
+}
+inline int __builtin_amdgcn_frexp_expf(float x)
+{
+    if (x == 0.0f || !std::isfinite(x)) return 0;
     int e = 0;
     std::frexp(x, &e);
     return e;
