@@ -37,7 +37,7 @@ def kernel_source_hash():
 
 def short_name(name):
     """A kernel's name without return type and argument list."""
-    name = name.strip()
+    name = name.strip().replace("(anonymous namespace)", "{anon}")
     if name.startswith("void "):
         name = name[5:]
     depth = 0
