@@ -61,8 +61,9 @@ def test_tiles_walked_per_block_on_a_large_grid():
     assert rel_err(S_t.get_state()[0].cpu().numpy(), S_c.get_state()[0].cpu().numpy(), m) <= 1e-12
 
 
-def test_tiled_steps_match_oracle(orc):
-    w = masked_grid(nx=21, ny=14, nz=40, seed=11)
+@pytest.mark.parametrize("nz", [40, 33])   # 33: odd column height (cell pairs at odd offsets)
+def test_tiled_steps_match_oracle(orc, nz):
+    w = masked_grid(nx=21, ny=14, nz=nz, seed=11)
     P = make_oracle(orc, w)
     S = make_solver(w, stencil=1)
     m = w.active_mask()

@@ -79,9 +79,9 @@ def test_solver_emulated_short_column_variants(exe, tmp_path):
     """The short-column kernels (two columns per wave, two cells per lane)
     in their other instantiations: FP32 PCG vectors, the Jacobi
     preconditioner, z-line factors kept from a step's first Picard iteration,
-    tiles of 8 x 4 columns.  Same Picard iterations as the oracle, heads to
-    1e-8 (FP32 solves: 10 tol_picard).  The three cases run as concurrent
-    driver processes."""
+    tiles of 8 x 4 columns, and an odd column height.  Same Picard iterations
+    as the oracle, heads to 1e-8 (FP32 solves: 10 tol_picard).  The cases run
+    as concurrent driver processes."""
     w = W.watershed(nx=10, ny=6, nz=20, kmin=10)
     w.h0 = np.where(w.active_mask(), -1.5, 0.0)
     variants = [  # precond, precision, zline_refactor, tile_rows, steps
@@ -94,8 +94,21 @@ def test_solver_emulated_short_column_variants(exe, tmp_path):
         paths.append(os.path.join(str(tmp_path), "short%d.txt" % i))
         cases.solver_case(paths[-1], w, n, 600.0, stencil=1, precond=precond, precision=precision,
                           zline_refactor=refactor, tile_rows=tile_rows)
+    # and the default kernels on an odd column height (pairs of cells start at
+    # odd element offsets; a full column has an odd top)
+    wo = W.watershed(nx=9, ny=4, nz=21, kmin=9)
+    wo.h0 = np.where(wo.active_mask(), -1.5, 0.0)
+    paths.append(os.path.join(str(tmp_path), "short_odd.txt"))
+    cases.solver_case(paths[-1], wo, 2, 600.0, stencil=1)
     with ThreadPoolExecutor(len(paths)) as pool:
         outs = list(pool.map(lambda p: cases.run(exe, "solver", p, timeout=600), paths))
+    Po = make_oracle(orc_mod, wo, dt0=600.0, ebats=0)
+    its_o = [Po.step(600.0)[1]["picard_iters"] for _ in range(2)]
+    ho, _ = Po.get_state()
+    out = outs.pop()
+    assert [s["status"] for s in out["steps"]] == [0, 0]
+    assert [s["picard_iters"] for s in out["steps"]] == its_o
+    assert rel_err(out["h"], ho, wo.active_mask()) <= 1e-8
     P = make_oracle(orc_mod, w, dt0=600.0, ebats=0)
     its = [P.step(600.0)[1]["picard_iters"] for _ in range(2)]
     h2, _ = P.get_state()
