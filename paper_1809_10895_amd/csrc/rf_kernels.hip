@@ -995,42 +995,53 @@ __global__ void __launch_bounds__(kThreads) k_resid(Geo g, Arrays a, CgVec<T> cv
     RF_WAVE_IDS;
     double v[2] = {0.0, 0.0};
     if (g.nz <= kWave) {
-        // short columns: gather K and h^m at the cell and its lateral
-        // neighbours for G2 columns; vertical neighbours from adjacent lanes
-        constexpr int G2 = 2;
-        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * G2) {
-            ColSlot cs[G2];
-            bool nb[G2][4];
-            size_t in[G2][4];
-            double Kp[G2], hp[G2], Dp[G2], bp[G2], Kn[G2][4], hn[G2][4];
-            double tzs[G2], rds[G2];   // stored z-line factors (reused when not refactoring)
+        // short columns, two at a time (resid_pair): column c0 + 8 h in
+        // half-wave h, cells k0 and k0 + 1 in each lane.  K and h^m at the
+        // cells and their lateral neighbours are gathered first; a cell at or
+        // above its column's top reads a cell of its own column (valid
+        // memory, masked afterwards); vertical neighbours come from the
+        // adjacent lanes
+        const int half = lane >> 5, k0 = 2 * (lane & 31);
+        const size_t sx = (size_t)g.nz, sy = (size_t)g.nz * g.nx;
+        for (int c0 = cb + w; c0 < ce; c0 += kWavesPerBlock * 2) {
+            const int cq = c0 + half * kWavesPerBlock;
+            const int col = (cq < ce) ? cq : c0;
+            const int kcol = a.ktop[col];
+            const int kt = (cq < ce) ? kcol : 0;
+            const size_t base = (size_t)col * g.nz;
+            const int ci = col % g.nx, cj = col / g.nx;
+            const bool has[4] = {ci > 0, ci < g.nx - 1, cj > 0, cj < g.ny - 1};
+            const int cn[4] = {has[0] ? col - 1 : col, has[1] ? col + 1 : col,
+                               has[2] ? col - g.nx : col, has[3] ? col + g.nx : col};
+            int ktn[4];
 #pragma unroll
-            for (int u = 0; u < G2; u++) {
-                cs[u] = col_slot(g, a.ktop, c0 + u * kWavesPerBlock, ce, lane);
-                lateral(g, a.ktop, cs[u], lane, nb[u], in[u]);
-            }
+            for (int d = 0; d < 4; d++) ktn[d] = a.ktop[cn[d]];
+            double Kp[2], hp[2], Dp[2], bp[2], Kn[2][4], hn[2][4], tzs[2], rds[2];
+            bool nb[2][4];
 #pragma unroll
-            for (int u = 0; u < G2; u++) {
-                const size_t i = cs[u].i;
-                Kp[u] = a.K[i];
-                hp[u] = hmv[i];
-                Dp[u] = a.Dd[i];
-                bp[u] = a.bst[i];
+            for (int c = 0; c < 2; c++) {
+                const int k = k0 + c;
+                const size_t i = base + min(k, g.nz - 1);
+                Kp[c] = a.K[i];
+                hp[c] = hmv[i];
+                Dp[c] = a.Dd[i];
+                bp[c] = a.bst[i];
+                tzs[c] = rds[c] = 0.0;
                 if (PRECOND == RF_PRECOND_ZLINE && !refactor) {
-                    tzs[u] = (double)cv.tz[i];
-                    rds[u] = (double)cv.rdp[i];
+                    tzs[c] = (double)cv.tz[i];
+                    rds[c] = (double)cv.rdp[i];
                 }
 #pragma unroll
                 for (int d = 0; d < 4; d++) {
-                    Kn[u][d] = a.K[in[u][d]];
-                    hn[u][d] = hmv[in[u][d]];
+                    const size_t off = (d < 2) ? sx : sy;
+                    const size_t in = has[d] ? ((d & 1) ? i + off : i - off) : i;
+                    nb[c][d] = (k < kt) & has[d] & (k < ktn[d]);   // no short-circuit branches
+                    Kn[c][d] = a.K[in];
+                    hn[c][d] = hmv[in];
                 }
             }
-#pragma unroll
-            for (int u = 0; u < G2; u++)
-                resid_column<PRECOND, T>(g, cv, bout, refactor, cs[u].act, cs[u].kt, cs[u].i, lane,
-                                         Kp[u], hp[u], Dp[u], bp[u], Kn[u], hn[u], nb[u], tzs[u],
-                                         rds[u], v);
+            resid_pair<PRECOND, T>(g, cv, bout, refactor, kt, base + k0, k0, lane, Kp, hp, Dp, bp,
+                                   Kn, hn, nb, tzs, rds, v);
         }
     } else
     for (int col = cb + w; col < ce; col += kWavesPerBlock) {
