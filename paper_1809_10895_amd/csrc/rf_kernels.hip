@@ -730,94 +730,6 @@ __device__ __forceinline__ void zline_solve_pair(const T (&r)[2], const T (&rd)[
 // Residual of the Picard system and PCG start
 // ---------------------------------------------------------------------------
 
-// One column of at most 64 cells (lane = k): the interior faces, the
-// residual r = b - A h^m of the increment system, diag (stored only where a
-// later kernel reads it: Jacobi, factors kept from an earlier iteration, or
-// the assembly for the caller; the update kernel otherwise rebuilds it from
-// this iteration's factors), the z-line factors (refactor) and z = M^-1 r,
-// and the block-partial contributions v = (r.z, max|r/diag|).  The PCG
-// iterate e needs no clearing: the first spmv kernel to add to it writes it.  Kp, hp, Dp, bp: K, h^m, Dd, bst of the lane's
-// cell; Kn, hn, nb: the lateral neighbours (-x, +x, -y, +y) and whether they
-// are active; tzs, rds: the stored z-line factors (used when !refactor).
-// Lanes at or above the active length kt only take part in the scans.
-template <int PRECOND, typename T>
-__device__ __forceinline__ void resid_column(const Geo &g, const CgVec<T> &cv, double *bout,
-                                             int refactor, bool act, int kt, size_t i, int lane,
-                                             double Kp, double hp, double Dp, double bp,
-                                             const double (&Kn)[4], const double (&hn)[4],
-                                             const bool (&nb)[4], double tzs, double rds,
-                                             double (&v)[2])
-{
-    constexpr bool kCopyKD = !std::is_same<T, double>::value;
-    const double gz[2] = {gdot(g, 4), gdot(g, 5)};
-    const double Kd = from_below0(Kp), hd = from_below0(hp);
-    const double Ku = from_above0(Kp), hu = from_above0(hp);
-    double diag = act ? Dp : 1.0, Ap = Dp * hp, b = bp, tup = 0.0;
-#pragma unroll
-    for (int d = 0; d < 4; d++) {
-        if (!nb[d]) continue;
-        const double Kf = 0.5 * (Kp + Kn[d]);
-        const double Tf = g.Tk[d >> 1] * Kf;
-        diag += Tf;
-        Ap += Tf * (hp - hn[d]);
-        b += g.A[d >> 1] * Kf * gdot(g, d);
-    }
-    if (act && lane > 0) {
-        const double Kf = 0.5 * (Kp + Kd);
-        const double Tf = g.Tk[2] * Kf;
-        diag += Tf;
-        Ap += Tf * (hp - hd);
-        b += g.A[2] * Kf * gz[0];
-    }
-    if (act && lane + 1 < kt) {
-        const double Kf = 0.5 * (Kp + Ku);
-        tup = g.Tk[2] * Kf;
-        diag += tup;
-        Ap += tup * (hp - hu);
-        b += g.A[2] * Kf * gz[1];
-    }
-    const double r = act ? b - Ap : 0.0;
-    const T rs = (T)r, ds = (T)diag;
-    const bool keep_diag = PRECOND == RF_PRECOND_JACOBI || !refactor || bout != nullptr;
-    if (act) {
-        if (bout) bout[i] = b;
-        cv.r[i] = rs;
-        if (keep_diag) cv.diag[i] = ds;
-        if (kCopyKD) {
-            cv.K[i] = (T)Kp;
-            cv.Dd[i] = (T)Dp;
-        }
-        v[1] = fmax(v[1], fabs(r / diag));
-        if (PRECOND == RF_PRECOND_JACOBI) v[0] += (double)rs * (double)(rs / ds);
-    }
-    if (PRECOND == RF_PRECOND_ZLINE) {
-        // factors of this iteration's column tridiagonal, or the stored ones
-        // of the step's first iteration
-        double tzv, rdp;
-        if (refactor) {
-            const double tprev = from_below0(tup);
-            const double dpiv = scan_pivots(diag, act ? tprev * tprev : 0.0, 0.0, lane);
-            tzv = tup;
-            rdp = act ? 1.0 / dpiv : 0.0;
-        } else {
-            tzv = act ? tzs : 0.0;
-            rdp = act ? rds : 0.0;
-        }
-        const double tprev = from_below0(tzv);
-        const double wk = scan_affine_up<double>(tprev * rdp, r * rdp, 0.0, lane);
-        const double zk = scan_affine_down<double>(tzv * rdp, wk, 0.0, lane);
-        if (act) {
-            const T zs = (T)zk;
-            if (refactor) {
-                cv.tz[i] = (T)tup;
-                cv.rdp[i] = (T)rdp;
-            }
-            cv.z[i] = zs;
-            v[0] += (double)rs * (double)zs;
-        }
-    }
-}
-
 // max(m, |a_c| / d_c) over the lane's active cells c (d_c > 0) with one
 // division: with d_c = 2^-e_c c_c, c_c in [1, 2) (exact scalings, so that no
 // product over- or underflows where the quotients do not),
@@ -835,8 +747,14 @@ __device__ __forceinline__ double max_ratio_pair(double m, T a0, T d0, bool act0
 
 // Two columns of at most 64 cells at once, one per half-wave, two cells per
 // lane: cells k0 = 2 (lane & 31) and k0 + 1 of this half's column (active
-// length kt, first cell i0 = its index of k0).  Per cell, the arithmetic of
-// resid_column; the z-line pivots and sweeps first compose each lane's two
+// length kt, first cell i0 = its index of k0): the interior faces, the
+// residual r = b - A h^m of the increment system, diag (stored only where a
+// later kernel reads it: Jacobi, factors kept from an earlier iteration, or
+// the assembly for the caller; the update kernel otherwise rebuilds it from
+// this iteration's factors), the z-line factors (refactor) and z = M^-1 r,
+// and the block-partial contributions v = (r.z, max|r/diag|); the PCG
+// iterate e needs no clearing (the first spmv kernel to add to it writes
+// it).  The z-line pivots and sweeps first compose each lane's two
 // cells and then scan over the 32 lanes of the half (half the scan steps per
 // cell, and no chaining across four rows).  Kp, hp, Dp, bp, tzs, rds: the two
 // cells' values; Kn, hn, nb: their lateral neighbours.
