@@ -153,4 +153,34 @@ def test_watershed_full_size_step_matches_oracle_at_bench_options(ws, orc):
     err = rel_err(host(S.get_state()[0]), h_o, m)
     print("watershed step at tol_cg 1e-8: relative head difference %.3e" % err)
     assert err <= 1e-8
+    # the water balance (k_accept's seven block partials, folded): the storage
+    # moves with the heads by C dh (dh ~ 1e-8 m), the boundary inflows with K(h);
+    # both storages are sums of 12.5 M positive terms in different orders, whose
+    # rounding alone reaches ~1e-10 relative (n eps is 1.4e-9)
+    mb_g, mb_o = S.mass_balance(), P.mass_balance()
+    assert mb_g["storage"] == pytest.approx(mb_o["storage"], rel=1e-9)
+    assert mb_g["storage0"] == pytest.approx(mb_o["storage0"], rel=1e-9)
+    scale = max(abs(x) for x in mb_o["inflow"])
+    assert np.allclose(mb_g["inflow"], mb_o["inflow"], rtol=1e-6, atol=1e-9 * scale)
+
+
+def test_watershed_full_size_mixed_matches_fp64_at_bench_options(ws):
+    """FP32 PCG under FP64 Picard refinement against the FP64 path, two
+    steps at the benchmark's options (PCG tol 1e-8 m, no relative test): the
+    same Picard counts, and heads within 1e-9 m.  The FP32 solves end
+    at the same absolute tolerance on the FP64 residual of each Picard system,
+    so the two paths differ by rounding inside the tolerance; measured ~2e-13 m
+    over 20 steps."""
+    w, _, _ = ws
+    S64 = make_solver(w, precond=1, tol_cg=1e-8, cg_rel_tol=0.0)
+    S32 = make_solver(w, precond=1, precision=1, tol_cg=1e-8, cg_rel_tol=0.0)
+    for n in range(2):
+        s64, st64 = S64.step(w.dt)
+        s32, st32 = S32.step(w.dt)
+        assert s64 == 0 and s32 == 0, (S64.last_error(), S32.last_error())
+        assert st32["picard_iters"] == st64["picard_iters"], n
+    m = w.active_mask()
+    d = np.abs(host(S32.get_state()[0]) - host(S64.get_state()[0]))[m].max()
+    print("mixed vs FP64 after two watershed steps: max |dh| %.3e m" % d)
+    assert d <= 1e-9
 
