@@ -242,7 +242,7 @@ __device__ __forceinline__ void lateral(const Geo &g, const int32_t *__restrict_
 template <int TY>
 struct Tile {
     static constexpr int SX = kTileX + 2, SY = TY + 2, NS = SX * SY;
-    static constexpr int PER = (NS + kWavesPerBlock - 1) / kWavesPerBlock;   // slots per wave
+    static constexpr int NH = 2 * kTileX + 2 * TY;                           // halo slots
     static_assert(kTileX == kWavesPerBlock, "one tile row along x per wave");
 
     // Column of slot sl of the tile whose slot (0, 0) is the grid column
@@ -259,12 +259,39 @@ struct Tile {
     __device__ static __forceinline__ int own(int w, int t) { return (w + 1) + SX * (t + 1); }
 };
 
+// Which slots of a Tile<TY> wave w loads (its u-th: slot(w, u), or NS for
+// none).  OWN_FIRST = false: slots w, w + 8, ... (neighbouring waves load
+// neighbouring columns).  OWN_FIRST = true: its own TY interior columns
+// first, so that it holds their values itself, then its share of the halo
+// (dealt w, w + 8, ...: the first row, the two ends of each interior row,
+// the last row).
+template <int TY, bool OWN_FIRST>
+struct TileSlots {
+    using Tl = Tile<TY>;
+    static constexpr int PER = OWN_FIRST ? TY + (Tl::NH + kWavesPerBlock - 1) / kWavesPerBlock
+                                         : (Tl::NS + kWavesPerBlock - 1) / kWavesPerBlock;
+
+    __device__ static __forceinline__ int slot(int w, int u)
+    {
+        if (!OWN_FIRST) return w + u * kWavesPerBlock;
+        if (u < TY) return Tl::own(w, u);
+        int h = w + (u - TY) * kWavesPerBlock;
+        if (h >= Tl::NH) return Tl::NS;
+        if (h < kTileX) return 1 + h;
+        h -= kTileX;
+        if (h < 2 * TY) return (h & 1) * (Tl::SX - 1) + Tl::SX * (1 + (h >> 1));
+        h -= 2 * TY;
+        return 1 + h + Tl::SX * (Tl::SY - 1);
+    }
+};
+
 // The columns and active lengths one wave needs for tile `tile` (-1: none):
-// its share of the slots (w, w + 8, ...) and its own TY interior columns.
-// The active lengths are scalar loads, issued together.
-template <int TY>
+// its share of the slots (TileSlots) and its own TY interior columns.  The
+// active lengths are scalar loads, issued together.
+template <int TY, bool OWN_FIRST>
 struct TileCols {
-    int col[Tile<TY>::PER], kt[Tile<TY>::PER], oc[TY], okt[TY];
+    using Sl = TileSlots<TY, OWN_FIRST>;
+    int col[Sl::PER], kt[Sl::PER], oc[TY], okt[TY];
 
     __device__ __forceinline__ void fetch(const Geo &g, const int32_t *__restrict__ ktop, int tile,
                                           int w)
@@ -272,8 +299,8 @@ struct TileCols {
         using Tl = Tile<TY>;
         const int i0 = (tile % g.ntx) * kTileX - 1, j0 = (tile / g.ntx) * TY - 1;
 #pragma unroll
-        for (int u = 0; u < Tl::PER; u++) {
-            col[u] = (tile >= 0) ? Tl::column(g, i0, j0, w + u * kWavesPerBlock) : -1;
+        for (int u = 0; u < Sl::PER; u++) {
+            col[u] = (tile >= 0) ? Tl::column(g, i0, j0, Sl::slot(w, u)) : -1;
             kt[u] = (col[u] >= 0) ? ktop[col[u]] : 0;
         }
 #pragma unroll
@@ -1088,15 +1115,16 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
     const double *hmv = (m == 0) ? a.h0m : (m & 1) ? a.hb1 : a.hb0;
     if (stop) return;
     RF_WAVE_IDS;
-    TileCols<TY> tc;
+    TileCols<TY, false> tc;
+    using Sl = TileSlots<TY, false>;
     tc.fetch(g, a.ktop, blockIdx.x, w);
     static_assert(TY % 2 == 0, "columns are formed in pairs");
     constexpr int NP = TY / 2;
     // the lane's two cells in column h = lane >> 5 of each pair of own columns
     const int half = lane >> 5, k0 = 2 * (lane & 31);
-    double K[Tl::PER], h[Tl::PER], Dp[NP][2], bp[NP][2], tzs[NP][2], rds[NP][2];
+    double K[Sl::PER], h[Sl::PER], Dp[NP][2], bp[NP][2], tzs[NP][2], rds[NP][2];
 #pragma unroll
-    for (int u = 0; u < Tl::PER; u++) {
+    for (int u = 0; u < Sl::PER; u++) {
         K[u] = 0.0;
         h[u] = 0.0;
         if (lane < tc.kt[u]) {
@@ -1130,8 +1158,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_resid_tile(Geo g, Arrays a, CgV
         }
     }
 #pragma unroll
-    for (int u = 0; u < Tl::PER; u++) {
-        const int sl = w + u * kWavesPerBlock;
+    for (int u = 0; u < Sl::PER; u++) {
+        const int sl = Sl::slot(w, u);
         if (sl >= Tl::NS) continue;
         if (lane < tc.kt[u]) {
             sK[sl][lane] = K[u];
@@ -1409,14 +1437,15 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     T *__restrict__ p_out = parity ? cv.p0 : cv.p1;
     if (stop) return;
     RF_WAVE_IDS;
-    TileCols<TY> tc;
+    TileCols<TY, true> tc;
+    using Sl = TileSlots<TY, true>;
     tc.fetch(g, a.ktop, blockIdx.x, w);
     double pv[2];
     gather_partials<2, 2u>(a.pr + 2 * g.foff, g.np, pv);
     const bool first = (j == 0);
-    T z[Tl::PER], po[Tl::PER], K[Tl::PER], Dd[TY], eo[TY], pw[TY];
+    T z[Sl::PER], po[Sl::PER], K[Sl::PER], Dd[TY], eo[TY], pw[TY];
 #pragma unroll
-    for (int u = 0; u < Tl::PER; u++) {
+    for (int u = 0; u < Sl::PER; u++) {
         z[u] = T(0);
         po[u] = T(0);
         K[u] = T(0);
@@ -1429,11 +1458,11 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     }
 #pragma unroll
     for (int t = 0; t < TY; t++) {
-        Dd[t] = eo[t] = pw[t] = T(0);
+        Dd[t] = eo[t] = T(0);
+        pw[t] = po[t];                          // own column t is the wave's slot t
         if (lane < tc.okt[t]) {
             const size_t i = (size_t)tc.oc[t] * g.nz + lane;
             Dd[t] = cv.Dd[i];
-            if (!first) pw[t] = p_in[i];
             if (j >= 2) eo[t] = cv.e[i];        // (e is 0 before the first step)
         }
     }
@@ -1443,8 +1472,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_spmv_tile(Geo g, Arrays a, CgVe
     if (lead_thread()) s->plast = parity ? 0 : 1;
     const T beta = first ? T(0) : (T)(tot[0] / rho_slot[(j + 1) & 1]);
 #pragma unroll
-    for (int u = 0; u < Tl::PER; u++) {
-        const int sl = w + u * kWavesPerBlock;
+    for (int u = 0; u < Sl::PER; u++) {
+        const int sl = Sl::slot(w, u);
         if (sl >= Tl::NS) continue;
         if (lane < tc.kt[u]) {
             sP[sl][lane] = first ? z[u] : z[u] + beta * po[u];
